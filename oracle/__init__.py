@@ -1,0 +1,168 @@
+"""FP64 brute-force oracle of the transient NLOS forward operator.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline use it; the product path never imports it.  It shares no code with
+the HIP library.  The arithmetic lives in ``nlos_oracle.c`` (plain C, fp64,
+no FMA contraction); this module only compiles it and marshals arrays.
+
+Functions follow arXiv 2506.03747: Section 2 Eq. (1) (forward model),
+Section 2 depth-to-volume mapping / Algorithm 1 step 2.1 (patches from a
+depth map), Section 2 temporal jitter / Algorithm 1 step 2.3 (Gaussian taps).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nlos_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+CFLAGS = ["-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c11"]
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("half_x", C.c_double),
+                ("half_y", C.c_double), ("cx", C.c_double), ("cy", C.c_double)]
+
+
+class Params(C.Structure):
+    _fields_ = [("relay", Grid), ("laser", Grid), ("standoff_m", C.c_double),
+                ("bin_ps", C.c_double), ("n_bins", C.c_int32), ("fwhm_ps", C.c_double),
+                ("cosines", C.c_int32)]
+
+
+def compile_library(src: str = _SRC, out: str = _LIB, extra=()) -> str:
+    """Compile the oracle with gcc (plain C, OpenMP, no FMA contraction)."""
+    cmd = ["gcc", *CFLAGS, *extra, src, "-o", out + ".tmp", "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def load(path: str | None = None, rebuild: bool = False):
+    """Load (compiling first if needed) the oracle library."""
+    global _lib
+    with _lock:
+        if path is not None:
+            return _bind(C.CDLL(path))
+        if _lib is None or rebuild:
+            stale = (not os.path.exists(_LIB)) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)
+            if stale or rebuild:
+                compile_library()
+            _lib = _bind(C.CDLL(_LIB))
+        return _lib
+
+
+def _bind(lib):
+    dp = C.POINTER(C.c_double)
+    lib.oracle_grid_coords.argtypes = [C.POINTER(Grid), dp, dp]
+    lib.oracle_inv_bin.argtypes = [C.c_double]
+    lib.oracle_inv_bin.restype = C.c_double
+    lib.oracle_patches.argtypes = [C.POINTER(Grid), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, dp]
+    lib.oracle_patches.restype = C.c_int32
+    lib.oracle_taps.argtypes = [C.c_double, C.c_double, dp, C.c_int32]
+    lib.oracle_taps.restype = C.c_int32
+    lib.oracle_forward.argtypes = [C.POINTER(Params), dp, C.c_int32, C.c_void_p, C.c_int32,
+                                   C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.oracle_forward.restype = C.c_int32
+    return lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_grid(g: dict) -> Grid:
+    return Grid(int(g["nx"]), int(g["ny"]), float(g["half_x"]), float(g["half_y"]),
+                float(g["cx"]), float(g["cy"]))
+
+
+def make_params(scene) -> Params:
+    laser = make_grid(scene.laser) if scene.laser is not None else Grid(0, 0, 0.0, 0.0, 0.0, 0.0)
+    return Params(make_grid(scene.relay), laser, float(scene.standoff_m), float(scene.bin_ps),
+                  int(scene.n_bins), float(scene.fwhm_ps), 1 if scene.cosines else 0)
+
+
+def grid_coords(g: dict, lib=None):
+    lib = lib or load()
+    xs = np.zeros(int(g["nx"]), np.float64)
+    ys = np.zeros(int(g["ny"]), np.float64)
+    lib.oracle_grid_coords(C.byref(make_grid(g)), _dptr(xs), _dptr(ys))
+    return xs, ys
+
+
+def inv_bin(bin_ps: float, lib=None) -> float:
+    lib = lib or load()
+    return lib.oracle_inv_bin(float(bin_ps))
+
+
+def patches(scene, lib=None) -> np.ndarray:
+    """[nx*ny, 8] fp64 records (px, py, pz, a, n_x, n_y, n_z, present), x major."""
+    lib = lib or load()
+    g = scene.patch_grid
+    depth = np.ascontiguousarray(scene.depth, np.float32)
+    albedo = None if scene.albedo is None else np.ascontiguousarray(scene.albedo, np.float32)
+    mask = None if scene.mask is None else np.ascontiguousarray(scene.mask, np.uint8)
+    assert depth.shape == (g["nx"], g["ny"])
+    rec = np.zeros((g["nx"] * g["ny"], 8), np.float64)
+    lib.oracle_patches(C.byref(make_grid(g)), depth.ctypes.data,
+                       None if albedo is None else albedo.ctypes.data,
+                       None if mask is None else mask.ctypes.data,
+                       1 if scene.cosines else 0, _dptr(rec))
+    return rec
+
+
+def taps(fwhm_ps: float, bin_ps: float, lib=None) -> np.ndarray:
+    lib = lib or load()
+    buf = np.zeros(1024, np.float64)
+    R = lib.oracle_taps(float(fwhm_ps), float(bin_ps), _dptr(buf), 1024)
+    if R < 0:
+        raise ValueError("jitter kernel too long")
+    return buf[: 2 * R + 1].copy()
+
+
+def forward(scene, rec: np.ndarray | None = None, subset=None, want_hist=False,
+            want_tau=True, want_bins=False, lib=None):
+    """Run the brute-force operator.  Returns a dict with any of
+    ``hist`` / ``tau`` ([n_out, T] fp64) and ``bins`` ([n_out, P] int32),
+    where n_out = L*S (or len(subset)) in [laser][x'][y'] order."""
+    lib = lib or load()
+    if rec is None:
+        rec = patches(scene, lib)
+    rec = np.ascontiguousarray(rec, np.float64)
+    P = rec.shape[0]
+    prm = make_params(scene)
+    n_total = scene.n_laser * scene.n_scan
+    sub = None
+    if subset is not None:
+        sub = np.ascontiguousarray(subset, np.int32)
+        n_out = sub.shape[0]
+    else:
+        n_out = n_total
+    T = int(scene.n_bins)
+    hist = np.zeros((n_out, T), np.float64) if want_hist else None
+    tau = np.zeros((n_out, T), np.float64) if want_tau else None
+    bins = np.zeros((n_out, P), np.int32) if want_bins else None
+    rc = lib.oracle_forward(C.byref(prm), _dptr(rec), P,
+                            None if sub is None else sub.ctypes.data,
+                            0 if sub is None else n_out,
+                            None if hist is None else hist.ctypes.data,
+                            None if tau is None else tau.ctypes.data,
+                            None if bins is None else bins.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_forward rejected its arguments")
+    out = {}
+    if want_hist:
+        out["hist"] = hist
+    if want_tau:
+        out["tau"] = tau
+    if want_bins:
+        out["bins"] = bins
+    return out

@@ -1,0 +1,71 @@
+"""The pins have teeth: plant one plausible mistake at a time in a copy of
+the oracle's source (CPU only), rebuild it, and check that at least one pin
+fails on the broken copy."""
+import os
+
+import pytest
+
+import oracle
+import pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "nlos_oracle.c")
+
+# (name, text in the oracle source, planted replacement)
+MUTANTS = [
+    ("drop_patch_cosine", "cw_l * cp_l * cp_d * cw_d", "cw_l * cp_l * cw_d"),
+    ("drop_wall_cosine", "cw_l * cp_l * cp_d * cw_d", "cp_l * cp_d * cw_d"),
+    ("inverse_square_to_inverse", "(r_l * r_l * r_d * r_d)", "(r_l * r_d)"),
+    ("normal_faces_away", "o[6] = -1.0 / len;", "o[6] = 1.0 / len;"),
+    ("normal_x_sign", "o[4] = gx / len;", "o[4] = -gx / len;"),
+    ("no_cosine_clamp", "if (cp_l < 0.0) cp_l = 0.0;", ""),
+    ("round_not_floor", "floor(u)", "floor(u + 0.5)"),
+    ("single_leg_path", "((r_l + r_d) + o) * inv", "((r_d + r_d) + o) * inv"),
+    ("drop_standoff_path", "const double o = o_l + o_d;", "const double o = 0.0;"),
+    ("drop_standoff_weight", "H[k] += w * g_l * g_d;", "H[k] += w;"),
+    ("standoff_weight_square", "*weight = (s / L) * (s / L) * (s / L);", "*weight = (s / L) * (s / L);"),
+    ("taps_unnormalised", "taps[j] /= sum;", "taps[j] /= 1.0;"),
+    ("fwhm_without_factor_2", "fwhm_ps / (2.0 * sqrt(2.0 * log(2.0)))", "fwhm_ps / sqrt(2.0 * log(2.0))"),
+    ("radius_ceil_sigma", "(int32_t)ceil(2.0 * sigma)", "(int32_t)ceil(sigma)"),
+    ("projected_area_with_cosines", "(cosines ? len : 1.0)", "1.0"),
+    ("grid_not_cell_centred", "((double)i + 0.5) * step", "((double)i) * step"),
+    ("scan_xy_swapped", "const double wdx = rx[d / rg->ny], wdy = rx[rg->nx + d % rg->ny];",
+     "const double wdx = rx[d % rg->ny], wdy = rx[rg->nx + d / rg->ny];"),
+    ("jitter_wraps_around", "if (src >= 0 && src < T) acc += taps[j + R] * H[src];",
+     "acc += taps[j + R] * H[(src + T) % T];"),
+    ("gate_at_zero", "*offset = L - s;", "*offset = L;"),
+    ("half_central_difference", "/ (2.0 * h);", "/ h;"),
+]
+
+
+def _run_pins(lib):
+    failures = []
+    for pin in pins.FAST_PINS:
+        try:
+            pin(lib)
+        except Exception as e:  # noqa: BLE001 - any failure counts
+            failures.append((pin.__name__, type(e).__name__))
+    try:
+        pins.pin_mpmath_bruteforce(lib, seeds=(101, 102), nonconfocal=True)
+    except Exception as e:  # noqa: BLE001
+        failures.append(("pin_mpmath_bruteforce", type(e).__name__))
+    return failures
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation site for {name} not found"
+    bad = src.replace(old, new)
+    path = str(tmp_path / "mut.c")
+    with open(path, "w") as f:
+        f.write(bad)
+    so = str(tmp_path / "libmut.so")
+    oracle.compile_library(path, so)
+    lib = oracle.load(so)
+    failures = _run_pins(lib)
+    assert failures, f"mutant {name} passed every pin"
+    print(name, "caught by", failures)
+
+
+def test_unmutated_passes_all(olib):
+    assert _run_pins(olib) == []
