@@ -1,0 +1,152 @@
+"""Throughput of the transient NLOS forward operator on one MI355X.
+
+One step = the whole hot path on one seeded scene already resident in HBM:
+depth/albedo/mask -> patch records (nlos_patches_from_depth) -> pair
+evaluation, LDS binning, guard re-binning, jitter and write-out
+(nlos_forward).  Default workload: confocal 64x64 scan points on a 2x2 m
+wall, 256x256-pixel depth map with a blob mask (~32k active patches),
+T = 1024 bins of 8 ps, jitter FWHM 50 ps.
+
+Prints one JSON line: value = scan-point x patch pairs per second (Gpairs/s)
+over the timed steps, plus the dominant kernel's roofline figures (measured
+with HIP events on the launch stream) and the FP64 oracle timed on the host
+cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gpairs/s (scan pt×patch) + % FP32 peak; p50/p99 latency, batched vs plain"
+FLOPS_CONFOCAL = 29      # nominal flops per confocal pair (formula written without FMA)
+FLOPS_NONCONFOCAL = 48   # per non-confocal (laser, detector, patch) triple
+FP32_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
+
+WORKLOADS = {
+    "cfg2": "confocal 64x64 scan on 2x2 m wall, 256x256 patch depth map in [0.4,1.2] m with blob mask, "
+            "albedo U[0,1], T=1024 x 8 ps, FWHM 50 ps, no stand-off",
+    "cfg1": "confocal 32x32 scan on 1x1 m wall, stand-off 1 m, 64x64 patches at 0.5 m +/- 5 cm with blob "
+            "mask, T=512 x 16 ps, FWHM 70 ps",
+    "cfg3": "non-confocal 8x8 lasers x 128x128 detectors on 2x2 m wall, stand-off 2 m, 128x128 patches from "
+            "two overlapping surfaces, T=2048 x 4 ps, FWHM 30 ps",
+    "cfg5": "confocal 128x128 scan on 2x2 m wall, 128x128 patches (no mask), T=1024 x 8 ps, FWHM 50 ps",
+}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build runs the operator on a single MI355X "
+              f"(--gpus {args.gpus} is not supported; the multi-GPU sharding is a design note only)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2506_03747_amd as nl
+    import scenes
+
+    sc = scenes.by_name(args.workload)
+    dev = "cuda"
+    depth = torch.from_numpy(sc.depth).to(dev)
+    albedo = torch.from_numpy(sc.albedo).to(dev) if sc.albedo is not None else None
+    mask = torch.from_numpy(sc.mask).to(dev) if sc.mask is not None else None
+    prm = nl.params_of(sc)
+    npx = sc.n_patch_total
+    patches = torch.empty((npx, 8), dtype=torch.float32, device=dev)
+    n_act = torch.empty(1, dtype=torch.int32, device=dev)
+    out = torch.empty(nl.out_shape(prm), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        nl.patches_from_depth(depth, sc.patch_grid, albedo, mask, cosines=sc.cosines, out=patches,
+                              n_active=n_act)
+        if ev is not None:
+            ev[0].record(stream)
+        nl.forward(prm, patches, n_act, out=out)
+        if ev is not None:
+            ev[1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    P_act = int(n_act.item())
+    H = nl.n_histograms(prm)
+    pairs = H * P_act
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    step_ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step_ev[0].record(stream)
+    for i in range(args.steps):
+        step(evs[i])
+        step_ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    kern_ms = np.array([a.elapsed_time(b) for a, b in evs])
+    step_ms = np.array([step_ev[i].elapsed_time(step_ev[i + 1]) for i in range(args.steps)])
+    ms_per_step = wall * 1e3 / args.steps
+    value = pairs / (ms_per_step * 1e-3) / 1e9
+    F = FLOPS_CONFOCAL if sc.laser is None else FLOPS_NONCONFOCAL
+    kern_avg = float(kern_ms.mean())
+    achieved = F * pairs / (kern_avg * 1e-3) / 1e12
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        olib = oracle.load()
+        sample = sc
+        sub = None
+        if sc.laser is not None:
+            sub = np.sort(np.random.default_rng(0).choice(H, 512, replace=False)).astype(np.int32)
+        times = []
+        for _ in range(3):
+            t = time.perf_counter()
+            rec = oracle.patches(sample, lib=olib)
+            oracle.forward(sample, rec, subset=sub, lib=olib)
+            times.append(time.perf_counter() - t)
+        n_h = H if sub is None else len(sub)
+        cpu_pairs = n_h * P_act
+        cpu = {"value": cpu_pairs / float(np.median(times)) / 1e9, "unit": "Gpairs/s",
+               "cores": oracle.num_threads(olib), "kind": "oracle",
+               "sample": (f"full {args.workload} step ({n_h} histograms x {P_act} patches, jitter "
+                          f"included), fp64 brute force, median of 3 runs" if sub is None else
+                          f"{n_h} of {H} histograms x {P_act} patches, median of 3 runs")}
+
+    line = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gpairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "histograms": H,
+                   "patches_active": P_act, "patches_total": npx, "n_bins": sc.n_bins,
+                   "pairs_per_step": pairs},
+        "pct_fp32_peak": round(100 * achieved / FP32_PEAK_TFLOPS, 2),
+        "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 5),
+                       "p99": round(float(np.percentile(step_ms, 99)), 5)},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                     "traffic": None, "kernel": "k_confocal" if sc.laser is None else "k_nonconfocal",
+                     "kernel_ms": round(kern_avg, 5), "flops_per_pair": F},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

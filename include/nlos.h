@@ -1,0 +1,192 @@
+/*
+ * nlos.h -- C ABI of the MI355X (gfx950) transient NLOS forward operator.
+ *
+ * The operator simulates the time-resolved measurement of a non-line-of-sight
+ * setup (arXiv 2506.03747): a hidden surface given as a depth map and an
+ * albedo map, a planar relay wall at z = 0 scanned on a grid, a pulsed laser
+ * and a time-resolved detector.  For every wall scan point and every hidden
+ * patch it computes the three-bounce path (device -> wall -> patch -> wall ->
+ * device), the Lambertian radiometric weight with inverse-square falloff, bins
+ * the weight into the scan point's histogram and blurs each histogram with the
+ * detector's Gaussian time jitter.
+ *
+ *   Section 2, Eq. (1): tau(x',y',t) = iiint rho / r^4 delta(2 r - t c) dx dy dz
+ *   Section 2, depth-to-volume mapping (Algorithm 1, step 2.1): the hidden
+ *     object is a depth map plus an albedo map (0.5 when absent).
+ *   Section 2, temporal jitter (Algorithm 1, step 2.3): per-trace Gaussian,
+ *     sigma = FWHM / (2 sqrt(2 ln 2)), kernel length 2 ceil(2 sigma) + 1.
+ *
+ * Conventions (they fix points the paper leaves open):
+ *   - c = 299 792 458 m/s.  Grids are cell-centred: cell i of n over
+ *     [c - half, c + half] sits at fp32((c - half) + (i + 0.5) * (2 half / n)),
+ *     computed in fp64 and rounded once.
+ *   - Maps and outputs are indexed [x][y] (x major); histograms are [x'][y'][t]
+ *     with t contiguous; non-confocal output is [laser][x'][y'][t], laser
+ *     points also x major.
+ *   - The device (laser and detector) sits on the wall normal through the
+ *     relay-grid centre at distance s = standoff_m.  Time 0 is the gate 2 s / c.
+ *     Each device leg adds (L - s) to the path and weighs (s / L)^3, with
+ *     L the device-to-wall-point distance; s = 0 means calibrated data with no
+ *     device legs (Eq. (1) as printed).
+ *   - Path u (in bins) = ((r_l + r_d) + o) * (1 / (c dt)), o the sum of the
+ *     two device-leg offsets; bin k = floor(u), kept when 0 <= k < T.  The bin
+ *     index is that of the fp64 evaluation of this expression (in this order,
+ *     IEEE round-to-nearest, no fused multiply-add) from the fp32 coordinates,
+ *     exactly: the kernels evaluate pairs in fp32 and re-evaluate in fp64
+ *     every pair whose fp32 arrival lies too close to a bin edge to decide.
+ *   - Weight with NLOS_F_COSINES: a * cos_wall,l * cos_patch,l * cos_patch,d *
+ *     cos_wall,d / (r_l^2 r_d^2) * g_l * g_d, patch cosines clamped at 0,
+ *     a = albedo * true patch area; without the flag a / (r_l^2 r_d^2) * g_l *
+ *     g_d with a = albedo * projected area.  No global constant (pi, c, dt).
+ *   - Jitter taps are normalised to sum 1; zero padding outside [0, T).
+ *
+ * Ownership and execution: the caller owns every buffer (device memory
+ * unless stated otherwise).  The library never allocates, frees or
+ * synchronises inside these calls: work is enqueued on the caller's stream
+ * (`stream` is a hipStream_t; NULL = the null stream) and the call returns
+ * immediately.  Host-side argument checks happen before anything is
+ * enqueued; a rejected call enqueues nothing.  Calls on distinct streams are
+ * independent; the library's only global state is its error slot (per
+ * thread).
+ *
+ * Errors: every int-returning call gives NLOS_OK (0) or a negative code:
+ *   NLOS_EINVAL  bad sizes or parameters, a null required pointer, a
+ *                misaligned buffer, a limit below exceeded;
+ *   NLOS_ENOSPC  the workspace passed is smaller than required;
+ *   NLOS_EHIP    a HIP runtime call failed (nlos_last_hip_error() has its code);
+ *   NLOS_ENODEV  no usable GPU.
+ * No C++ exception crosses this boundary.
+ */
+#ifndef NLOS_H
+#define NLOS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NLOS_ABI_VERSION 1
+
+#define NLOS_OK 0
+#define NLOS_EINVAL (-1)
+#define NLOS_ENOSPC (-2)
+#define NLOS_EHIP (-3)
+#define NLOS_ENODEV (-4)
+
+/* flags */
+#define NLOS_F_COSINES 1u /* Lambertian cosines and true patch area (default) */
+
+/* limits */
+#define NLOS_MAX_BINS (1 << 22)        /* T */
+#define NLOS_MAX_RADIUS 127            /* jitter half-width R = ceil(2 sigma) */
+#define NLOS_MAX_PATCHES (1 << 24)     /* records per call */
+#define NLOS_MAX_GRID 65536            /* nx, ny of any grid */
+#define NLOS_RECORD_FLOATS 8           /* floats per patch record (32 bytes) */
+
+/* A cell-centred grid of nx x ny points on the wall plane z = 0 (or the lateral
+ * grid of a depth map) covering [cx-half_x, cx+half_x] x [cy-half_y, cy+half_y],
+ * metres. */
+typedef struct nlos_grid {
+    int32_t nx, ny;
+    double half_x, half_y;
+    double cx, cy;
+} nlos_grid;
+
+/* System parameters (Algorithm 1 inputs; Section 1 lists relay surface,
+ * stand-off distance, time resolution and acquisition window). */
+typedef struct nlos_params {
+    nlos_grid relay;   /* confocal scan grid, or the detector grid when laser.nx > 0 */
+    nlos_grid laser;   /* laser grid; nx = ny = 0 -> confocal */
+    double standoff_m; /* s >= 0 (0: calibrated, no device legs) */
+    double bin_ps;     /* dt > 0, picoseconds */
+    int32_t n_bins;    /* T, 1..NLOS_MAX_BINS; window [2s/c, 2s/c + T dt) */
+    uint32_t flags;    /* NLOS_F_COSINES */
+    double fwhm_ps;    /* jitter FWHM >= 0, picoseconds; 0 -> no jitter */
+} nlos_params;
+
+/* Version of this ABI (NLOS_ABI_VERSION). */
+int nlos_abi_version(void);
+
+/* Static description of an error code; never NULL. */
+const char* nlos_strerror(int code);
+
+/* hipError_t of the last HIP failure on this thread (0 if none). */
+int nlos_last_hip_error(void);
+
+/* Bytes of workspace nlos_patches_from_depth needs for grid g (written to
+ * *bytes, a host pointer). */
+int nlos_patches_workspace_bytes(const nlos_grid* g, size_t* bytes);
+
+/*
+ * Depth map (+ albedo, + mask) -> patch records (Section 2 depth-to-volume
+ * mapping; Algorithm 1 step 2.1).
+ *   g       host pointer: lateral grid of the maps (g->nx * g->ny pixels).
+ *   depth   device float [nx][ny], metres along +z from the wall.
+ *   albedo  device float [nx][ny] in [0, 1], or NULL for 0.5 everywhere
+ *           (8-bit maps are divided by 255 by the caller).
+ *   mask    device uint8 [nx][ny], nonzero = present, or NULL for all.
+ *   flags   NLOS_F_COSINES selects the true patch area
+ *           dx dy sqrt(1 + D_x^2 + D_y^2), else the projected area dx dy;
+ *           pass the same flags to nlos_forward.
+ *   patches device float [nx*ny][8], 16-byte aligned: the first *n_active
+ *           records are the present patches
+ *              { x, y, z, a = albedo * area, n_x, n_y, n_z, bits(int32 ix*ny+iy) }
+ *           with n = (D_x, D_y, -1) / sqrt(1 + D_x^2 + D_y^2) from central
+ *           differences of the depth map (one-sided at the border); the rest
+ *           of the buffer is left unspecified.  A pixel is present when its
+ *           mask is nonzero, its albedo > 0 and its depth finite and > 0.
+ *           Records come in a fixed spatially interleaved order (pixels whose
+ *           (ix mod 8, iy mod 8) phase is equal are consecutive), which spreads
+ *           consecutive records over the surface; the order is deterministic.
+ *   n_active device int32[1]: number of present patches.
+ *   ws, ws_bytes device workspace of at least nlos_patches_workspace_bytes.
+ * Limits: nx*ny <= NLOS_MAX_PATCHES.
+ */
+int nlos_patches_from_depth(const nlos_grid* g, const float* depth, const float* albedo,
+                            const uint8_t* mask, uint32_t flags, float* patches,
+                            int32_t* n_active, void* ws, size_t ws_bytes, void* stream);
+
+/* Bytes of workspace nlos_forward needs (written to *bytes, host pointer). */
+int nlos_forward_workspace_bytes(const nlos_params* p, int32_t n_patches, size_t* bytes);
+
+/*
+ * Forward operator (Section 2 Eq. (1) with the conventions above, then the
+ * Gaussian jitter of Section 2 / Algorithm 1 step 2.3).
+ *   p          host pointer to the parameters.
+ *   patches    device float [n_patches][8] records as written by
+ *              nlos_patches_from_depth (16-byte aligned).
+ *   n_patches  capacity of `patches` (0..NLOS_MAX_PATCHES).
+ *   n_active   device int32[1] with the number of leading records to use
+ *              (clamped to [0, n_patches]), or NULL to use n_patches.
+ *   out        device float, fully overwritten, 16-byte aligned:
+ *              confocal [relay.nx][relay.ny][T];
+ *              non-confocal [laser.nx*laser.ny][relay.nx][relay.ny][T].
+ *   ws, ws_bytes device workspace (see nlos_forward_workspace_bytes; may be
+ *              NULL when that size is 0).
+ */
+int nlos_forward(const nlos_params* p, const float* patches, int32_t n_patches,
+                 const int32_t* n_active, float* out, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Test hook: the bin index of every (histogram, record) pair, decided by the
+ * same device functions and the same fp32-then-fp64 rule as nlos_forward.
+ *   bins    device int32 [H][n_patches], H = histograms of the output
+ *           (S confocal, L*S non-confocal); records at or beyond *n_active get
+ *           INT32_MIN.  Bins outside [0, T) are still reported (the exact
+ *           floor of the fp64 arrival), so every pair can be checked.
+ *   u_fast  device double [H][n_patches] or NULL: the fp32 arrival (in bins)
+ *           the kernels use to decide (exactly representable in fp64).
+ *   u_exact device double [H][n_patches] or NULL: the fp64 arrival.
+ * Limits: H * n_patches <= 2^31.
+ */
+int nlos_debug_bins(const nlos_params* p, const float* patches, int32_t n_patches,
+                    const int32_t* n_active, int32_t* bins, double* u_fast, double* u_exact,
+                    void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NLOS_H */

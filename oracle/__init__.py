@@ -72,7 +72,12 @@ def _bind(lib):
     lib.oracle_forward.argtypes = [C.POINTER(Params), dp, C.c_int32, C.c_void_p, C.c_int32,
                                    C.c_void_p, C.c_void_p, C.c_void_p]
     lib.oracle_forward.restype = C.c_int32
+    lib.oracle_num_threads.restype = C.c_int
     return lib
+
+
+def num_threads(lib=None) -> int:
+    return int((lib or load()).oracle_num_threads())
 
 
 def _dptr(a: np.ndarray):

@@ -62,6 +62,19 @@ typedef struct {
 
 int oracle_abi_version(void) { return 1; }
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+/* Threads the brute-force loop runs on. */
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* Cell-centred coordinate of cell i of n over [c-half, c+half], computed in
  * fp64 in this order and rounded once to fp32 (canonical input). */
 static double grid_coord(double half, double c, int32_t n, int32_t i)

@@ -1,0 +1,146 @@
+"""MI355X-native transient NLOS forward operator (arXiv 2506.03747).
+
+Python face of the C ABI in include/nlos.h: PyTorch supplies device memory
+and the current HIP stream, the HIP kernels in libnlos.so do every step of
+the computation.  Functions take and return torch tensors on the GPU; CPU
+tensors are rejected (there is no CPU fallback).
+
+    patches, n_active = patches_from_depth(depth, grid, albedo, mask)
+    tau = forward(params, patches, n_active)         # [nx, ny, T] fp32
+
+Grids are dicts ``dict(nx, ny, half_x, half_y, cx, cy)`` (metres, cell-centred
+on the wall plane z = 0); maps are [nx, ny] (x major).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import torch
+
+from ._native import (NLOS_F_COSINES, NLOS_MAX_BINS, NLOS_MAX_PATCHES, NLOS_MAX_RADIUS,  # noqa: F401
+                      NLOS_RECORD_FLOATS, Grid, NlosError, Params, check, lib, strerror)
+
+__all__ = ["Grid", "Params", "NlosError", "make_grid", "make_params", "params_of",
+           "patches_from_depth", "forward", "debug_bins", "out_shape", "n_histograms"]
+
+
+def make_grid(g) -> Grid:
+    if isinstance(g, Grid):
+        return g
+    return Grid(int(g["nx"]), int(g["ny"]), float(g["half_x"]), float(g["half_y"]),
+                float(g.get("cx", 0.0)), float(g.get("cy", 0.0)))
+
+
+def make_params(relay, n_bins: int, bin_ps: float, fwhm_ps: float = 0.0, standoff_m: float = 0.0,
+                laser=None, cosines: bool = True) -> Params:
+    lg = Grid(0, 0, 0.0, 0.0, 0.0, 0.0) if laser is None else make_grid(laser)
+    return Params(make_grid(relay), lg, float(standoff_m), float(bin_ps), int(n_bins),
+                  NLOS_F_COSINES if cosines else 0, float(fwhm_ps))
+
+
+def params_of(scene) -> Params:
+    """Parameters of any object with relay / laser / n_bins / bin_ps / fwhm_ps /
+    standoff_m / cosines attributes."""
+    return make_params(scene.relay, scene.n_bins, scene.bin_ps, scene.fwhm_ps, scene.standoff_m,
+                       scene.laser, getattr(scene, "cosines", True))
+
+
+def n_histograms(p: Params) -> int:
+    s = p.relay.nx * p.relay.ny
+    return s if p.laser.nx == 0 else s * p.laser.nx * p.laser.ny
+
+
+def out_shape(p: Params):
+    if p.laser.nx == 0:
+        return (p.relay.nx, p.relay.ny, p.n_bins)
+    return (p.laser.nx * p.laser.ny, p.relay.nx, p.relay.ny, p.n_bins)
+
+
+def _dev(t: Optional[torch.Tensor], dtype, name: str):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU torch tensor (no CPU fallback)")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> C.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def patches_from_depth(depth: torch.Tensor, grid, albedo: Optional[torch.Tensor] = None,
+                       mask: Optional[torch.Tensor] = None, cosines: bool = True,
+                       out: Optional[torch.Tensor] = None, n_active: Optional[torch.Tensor] = None,
+                       workspace: Optional[torch.Tensor] = None, stream=None):
+    """Depth (+ albedo, + mask) maps -> (records [nx*ny, 8] fp32, n_active int32[1])."""
+    g = make_grid(grid)
+    _dev(depth, torch.float32, "depth")
+    _dev(albedo, torch.float32, "albedo")
+    _dev(mask, torch.uint8, "mask")
+    npx = g.nx * g.ny
+    for t, name in ((depth, "depth"), (albedo, "albedo"), (mask, "mask")):
+        if t is not None and t.numel() != npx:
+            raise ValueError(f"{name} must have {g.nx}x{g.ny} elements")
+    dev = depth.device
+    if out is None:
+        out = torch.empty((npx, NLOS_RECORD_FLOATS), dtype=torch.float32, device=dev)
+    if n_active is None:
+        n_active = torch.empty(1, dtype=torch.int32, device=dev)
+    need = C.c_size_t(0)
+    check(lib().nlos_patches_workspace_bytes(C.byref(g), C.byref(need)), "nlos_patches_workspace_bytes")
+    if workspace is None or workspace.numel() < need.value:
+        workspace = torch.empty(need.value, dtype=torch.uint8, device=dev)
+    check(lib().nlos_patches_from_depth(C.byref(g), _ptr(depth), _ptr(albedo), _ptr(mask),
+                                        NLOS_F_COSINES if cosines else 0, _ptr(out), _ptr(n_active),
+                                        _ptr(workspace), workspace.numel(), _stream(stream)),
+          "nlos_patches_from_depth")
+    return out, n_active
+
+
+def forward(params: Params, patches: torch.Tensor, n_active: Optional[torch.Tensor] = None,
+            out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Transient histograms, jittered: [nx, ny, T] (confocal) or [L, nx, ny, T]."""
+    _dev(patches, torch.float32, "patches")
+    _dev(n_active, torch.int32, "n_active")
+    if patches.dim() != 2 or patches.shape[1] != NLOS_RECORD_FLOATS:
+        raise ValueError("patches must be [n, 8]")
+    if out is None:
+        out = torch.empty(out_shape(params), dtype=torch.float32, device=patches.device)
+    _dev(out, torch.float32, "out")
+    if out.numel() != n_histograms(params) * params.n_bins:
+        raise ValueError("out has the wrong size")
+    need = C.c_size_t(0)
+    check(lib().nlos_forward_workspace_bytes(C.byref(params), patches.shape[0], C.byref(need)),
+          "nlos_forward_workspace_bytes")
+    ws = torch.empty(need.value, dtype=torch.uint8, device=patches.device) if need.value else None
+    check(lib().nlos_forward(C.byref(params), _ptr(patches), patches.shape[0], _ptr(n_active), _ptr(out),
+                             _ptr(ws), 0 if ws is None else ws.numel(), _stream(stream)),
+          "nlos_forward")
+    return out
+
+
+def debug_bins(params: Params, patches: torch.Tensor, n_active: Optional[torch.Tensor] = None,
+               want_u: bool = False, stream=None):
+    """Test hook: bin index of every (histogram, record) pair, decided like
+    forward(); optionally the fp32 and fp64 arrivals."""
+    _dev(patches, torch.float32, "patches")
+    _dev(n_active, torch.int32, "n_active")
+    H, P = n_histograms(params), patches.shape[0]
+    bins = torch.empty((H, P), dtype=torch.int32, device=patches.device)
+    uf = ue = None
+    if want_u:
+        uf = torch.empty((H, P), dtype=torch.float64, device=patches.device)
+        ue = torch.empty((H, P), dtype=torch.float64, device=patches.device)
+    check(lib().nlos_debug_bins(C.byref(params), _ptr(patches), P, _ptr(n_active), _ptr(bins), _ptr(uf),
+                                _ptr(ue), _stream(stream)), "nlos_debug_bins")
+    return (bins, uf, ue) if want_u else bins

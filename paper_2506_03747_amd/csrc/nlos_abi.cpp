@@ -1,0 +1,365 @@
+// C ABI layer of the transient NLOS forward operator: argument checks,
+// jitter taps, the launch plan (tile shape, time windows, patch split) and
+// error reporting.  Every arithmetic step of the operator runs in the HIP
+// kernels; this file only prepares their arguments.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+
+#include "../../include/nlos.h"
+#include "nlos_internal.h"
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+constexpr double kC = 299792458.0;   // m/s
+constexpr size_t kLdsMax = 163840;   // LDS per workgroup on gfx950
+constexpr int kQueueDefault = 2048;
+constexpr int kTargetBlocks = 256;   // one workgroup per CU
+
+int hip_fail(hipError_t e)
+{
+    g_last_hip = (int)e;
+    return NLOS_EHIP;
+}
+
+int device_check()
+{
+    static std::once_flag once;
+    static int status = NLOS_OK;
+    std::call_once(once, [] {
+        int n = 0;
+        const hipError_t e = hipGetDeviceCount(&n);
+        if (e != hipSuccess || n <= 0) {
+            status = NLOS_ENODEV;
+            g_last_hip = (int)e;
+        }
+    });
+    return status;
+}
+
+bool finite(double v) { return std::isfinite(v); }
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+bool grid_ok(const nlos_grid* g)
+{
+    return g && g->nx >= 1 && g->ny >= 1 && g->nx <= NLOS_MAX_GRID && g->ny <= NLOS_MAX_GRID &&
+           finite(g->half_x) && finite(g->half_y) && g->half_x > 0 && g->half_y > 0 &&
+           finite(g->cx) && finite(g->cy);
+}
+
+nlos::Axis axis(double half, double c, int32_t n)
+{
+    nlos::Axis a;
+    a.a0 = c - half;
+    a.step = (2.0 * half) / (double)n;
+    a.n = n;
+    return a;
+}
+
+// Jitter taps (Section 2): sigma in bins = FWHM / (2 sqrt(2 ln 2)) / dt,
+// R = ceil(2 sigma), normalised Gaussian; FWHM = 0 -> identity.
+int jitter_taps(double fwhm_ps, double bin_ps, float* taps, int32_t* R_out)
+{
+    if (fwhm_ps == 0.0) {
+        taps[0] = 1.0f;
+        *R_out = 0;
+        return NLOS_OK;
+    }
+    const double sigma = fwhm_ps / (2.0 * std::sqrt(2.0 * std::log(2.0))) / bin_ps;
+    const double rr = std::ceil(2.0 * sigma);
+    if (!(rr <= (double)NLOS_MAX_RADIUS)) return NLOS_EINVAL;
+    const int R = (int)rr;
+    double g[nlos::kMaxTaps];
+    double sum = 0.0;
+    for (int j = -R; j <= R; ++j) {
+        g[j + R] = std::exp(-(double)j * (double)j / (2.0 * sigma * sigma));
+        sum += g[j + R];
+    }
+    for (int i = 0; i < 2 * R + 1; ++i) taps[i] = (float)(g[i] / sum);
+    *R_out = R;
+    return NLOS_OK;
+}
+
+bool is_confocal(const nlos_params* p) { return p->laser.nx == 0 && p->laser.ny == 0; }
+
+int params_ok(const nlos_params* p)
+{
+    if (!p || !grid_ok(&p->relay)) return NLOS_EINVAL;
+    if (!is_confocal(p) && !grid_ok(&p->laser)) return NLOS_EINVAL;
+    if (!finite(p->standoff_m) || p->standoff_m < 0) return NLOS_EINVAL;
+    if (!finite(p->bin_ps) || !(p->bin_ps > 0)) return NLOS_EINVAL;
+    if (p->n_bins < 1 || p->n_bins > NLOS_MAX_BINS) return NLOS_EINVAL;
+    if (!finite(p->fwhm_ps) || p->fwhm_ps < 0) return NLOS_EINVAL;
+    if ((p->flags & ~NLOS_F_COSINES) != 0) return NLOS_EINVAL;
+    return NLOS_OK;
+}
+
+int64_t n_hist(const nlos_params* p)
+{
+    const int64_t S = (int64_t)p->relay.nx * p->relay.ny;
+    const int64_t L = is_confocal(p) ? 1 : (int64_t)p->laser.nx * p->laser.ny;
+    return S * L;
+}
+
+// Fill the kernel arguments common to the pair kernels and the bin export.
+int fill_args(const nlos_params* p, const float* patches, int32_t n_patches, const int32_t* n_active,
+              float* out, nlos::FwdArgs* a)
+{
+    std::memset(a, 0, sizeof(*a));
+    a->patches = reinterpret_cast<const float4*>(patches);
+    a->n_active = n_active;
+    a->n_cap = n_patches;
+    a->out = out;
+    a->rx = axis(p->relay.half_x, p->relay.cx, p->relay.nx);
+    a->ry = axis(p->relay.half_y, p->relay.cy, p->relay.ny);
+    if (is_confocal(p)) {
+        a->lx = a->rx;
+        a->ly = a->ry;
+    } else {
+        a->lx = axis(p->laser.half_x, p->laser.cx, p->laser.nx);
+        a->ly = axis(p->laser.half_y, p->laser.cy, p->laser.ny);
+    }
+    a->cx = p->relay.cx;
+    a->cy = p->relay.cy;
+    a->s = p->standoff_m;
+    a->inv = 1.0 / (kC * (p->bin_ps * 1e-12));
+    a->inv_f = (float)a->inv;
+    a->inv2_f = (float)(2.0 * a->inv);
+    a->T = p->n_bins;
+    // Guard half-width: the fp32 arrival is within a few ulp (relative) of
+    // the fp64 one for pairs near the window; 16 ulp of T + 2 bins keeps a
+    // factor >= 2 over the bound derived for the fast path.
+    a->delta = (float)(16.0 * ((double)p->n_bins + 2.0) * std::ldexp(1.0, -24));
+    a->two_delta = 2.0f * a->delta;
+    // stand-in patch for idle lanes: beyond every wall point by (T + 64) / (2 inv)
+    // metres, so both legs add up to at least T + 64 bins
+    double reach = p->relay.cx + p->relay.half_x;
+    if (!is_confocal(p)) reach = std::max(reach, p->laser.cx + p->laser.half_x);
+    a->dummy_x = (float)(reach + ((double)p->n_bins + 64.0) / (2.0 * a->inv) + 1.0);
+    a->cosines = (p->flags & NLOS_F_COSINES) ? 1 : 0;
+    return jitter_taps(p->fwhm_ps, p->bin_ps, a->taps, &a->R);
+}
+
+struct Cand {
+    int tl, tx, ty;
+};
+
+// Launch plan: the largest tile whose histograms fit in LDS and that still
+// gives about one workgroup per CU; patches are split over workgroups when
+// there are fewer tiles than CUs; time windows when even one histogram is
+// too long for LDS.
+int make_plan(const nlos_params* p, int32_t n_patches, int R, nlos::Plan* plan)
+{
+    const bool conf = is_confocal(p);
+    static const Cand conf_c[] = {{1, 8, 4}, {1, 4, 4}, {1, 2, 4}, {1, 2, 2}, {1, 1, 2}, {1, 1, 1}};
+    static const Cand nc_c[] = {{4, 2, 2}, {2, 2, 2}, {2, 1, 2}, {1, 1, 2}, {1, 1, 1}};
+    const Cand* cands = conf ? conf_c : nc_c;
+    const int nc = conf ? 6 : 5;
+    const int T = p->n_bins;
+    const int64_t L = conf ? 1 : (int64_t)p->laser.nx * p->laser.ny;
+    int q_cap = kQueueDefault;
+
+    auto stride_of = [](int tl) { return (tl + 1) & ~1; };
+    auto tiles_of = [&](const Cand& c) {
+        return ((L + c.tl - 1) / c.tl) * (int64_t)((p->relay.nx + c.tx - 1) / c.tx) *
+               (int64_t)((p->relay.ny + c.ty - 1) / c.ty);
+    };
+    // the largest tile that fits and reaches the target; else the largest that fits
+    int chosen = -1, largest = -1;
+    for (int i = 0; i < nc; ++i) {
+        const int slots = cands[i].tl * cands[i].tx * cands[i].ty;
+        if (nlos::lds_bytes_for(slots, stride_of(T), q_cap) > kLdsMax) continue;
+        if (largest < 0) largest = i;
+        if (tiles_of(cands[i]) >= kTargetBlocks) {
+            chosen = i;
+            break;
+        }
+    }
+    if (chosen < 0) chosen = largest;
+    int tw = T, n_tw = 1;
+    if (chosen < 0) {
+        // even one histogram does not fit: split the time axis
+        chosen = nc - 1;
+        q_cap = 1024;
+        const size_t fixed = nlos::lds_bytes_for(1, 0, q_cap);
+        const int tl_max = (int)((kLdsMax - fixed - 256) / 4) & ~1;
+        tw = tl_max - 2 * R;
+        if (tw < 64) return NLOS_EINVAL;
+        tw &= ~3;
+        n_tw = (T + tw - 1) / tw;
+    }
+    const Cand c = cands[chosen];
+    const int tl_len = (n_tw == 1) ? T : std::min(T, tw + 2 * R);
+    plan->tl = c.tl;
+    plan->tx = c.tx;
+    plan->ty = c.ty;
+    plan->tw = tw;
+    plan->n_tw = n_tw;
+    plan->stride = stride_of(tl_len);
+    plan->q_cap = q_cap;
+    plan->lds_bytes = nlos::lds_bytes_for(c.tl * c.tx * c.ty, plan->stride, q_cap);
+    if (plan->lds_bytes > kLdsMax || plan->stride < tl_len) return NLOS_EINVAL;
+    const int64_t tiles = tiles_of(c) * n_tw;
+    int64_t split = 1;
+    if (tiles < kTargetBlocks) {
+        split = (kTargetBlocks + tiles - 1) / tiles;
+        const int64_t by_patches = std::max<int64_t>(1, n_patches / nlos::kBlock);
+        split = std::min(split, by_patches);
+    }
+    plan->n_split = (int)split;
+    plan->n_blocks = tiles * split;
+    if (plan->n_blocks > 0x7fffffff) return NLOS_EINVAL;
+    return NLOS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nlos_abi_version(void) { return NLOS_ABI_VERSION; }
+
+const char* nlos_strerror(int code)
+{
+    switch (code) {
+    case NLOS_OK: return "ok";
+    case NLOS_EINVAL: return "invalid argument";
+    case NLOS_ENOSPC: return "workspace too small";
+    case NLOS_EHIP: return "HIP runtime error";
+    case NLOS_ENODEV: return "no usable GPU";
+    default: return "unknown error";
+    }
+}
+
+int nlos_last_hip_error(void) { return g_last_hip; }
+
+int nlos_patches_workspace_bytes(const nlos_grid* g, size_t* bytes)
+{
+    if (!grid_ok(g) || !bytes) return NLOS_EINVAL;
+    const int64_t bx = (g->nx + nlos::kInterleave - 1) / nlos::kInterleave;
+    const int64_t by = (g->ny + nlos::kInterleave - 1) / nlos::kInterleave;
+    const int64_t n_enum = 64 * bx * by;
+    const int64_t blocks = (n_enum + nlos::kGeomBlock - 1) / nlos::kGeomBlock;
+    *bytes = (size_t)(2 * blocks * sizeof(int32_t) + 256);
+    return NLOS_OK;
+}
+
+int nlos_patches_from_depth(const nlos_grid* g, const float* depth, const float* albedo,
+                            const uint8_t* mask, uint32_t flags, float* patches, int32_t* n_active,
+                            void* ws, size_t ws_bytes, void* stream)
+{
+    if (!grid_ok(g) || !depth || !patches || !n_active || !ws) return NLOS_EINVAL;
+    if ((int64_t)g->nx * g->ny > NLOS_MAX_PATCHES) return NLOS_EINVAL;
+    if ((flags & ~NLOS_F_COSINES) != 0) return NLOS_EINVAL;
+    if (!aligned(patches, 16) || !aligned(depth, 4) || (albedo && !aligned(albedo, 4)) ||
+        !aligned(n_active, 4) || !aligned(ws, 4))
+        return NLOS_EINVAL;
+    size_t need = 0;
+    nlos_patches_workspace_bytes(g, &need);
+    if (ws_bytes < need) return NLOS_ENOSPC;
+    const int dev = device_check();
+    if (dev != NLOS_OK) return dev;
+
+    nlos::GeomArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.depth = depth;
+    a.albedo = albedo;
+    a.mask = mask;
+    a.patches = reinterpret_cast<float4*>(patches);
+    a.n_active = n_active;
+    a.ax = axis(g->half_x, g->cx, g->nx);
+    a.ay = axis(g->half_y, g->cy, g->ny);
+    a.hx = (float)a.ax.step;
+    a.hy = (float)a.ay.step;
+    a.bx = (g->nx + nlos::kInterleave - 1) / nlos::kInterleave;
+    a.by = (g->ny + nlos::kInterleave - 1) / nlos::kInterleave;
+    a.n_enum = 64 * (int64_t)a.bx * a.by;
+    a.n_blocks = (int32_t)((a.n_enum + nlos::kGeomBlock - 1) / nlos::kGeomBlock);
+    a.counts = reinterpret_cast<int32_t*>(ws);
+    a.offsets = a.counts + a.n_blocks;
+    a.cosines = (flags & NLOS_F_COSINES) ? 1 : 0;
+    const hipError_t e = nlos::launch_geometry(a, (hipStream_t)stream);
+    return e == hipSuccess ? NLOS_OK : hip_fail(e);
+}
+
+int nlos_forward_workspace_bytes(const nlos_params* p, int32_t n_patches, size_t* bytes)
+{
+    if (params_ok(p) != NLOS_OK || !bytes || n_patches < 0 || n_patches > NLOS_MAX_PATCHES)
+        return NLOS_EINVAL;
+    *bytes = 0;
+    return NLOS_OK;
+}
+
+int nlos_forward(const nlos_params* p, const float* patches, int32_t n_patches, const int32_t* n_active,
+                 float* out, void* ws, size_t ws_bytes, void* stream)
+{
+    (void)ws;
+    (void)ws_bytes;
+    int rc = params_ok(p);
+    if (rc != NLOS_OK) return rc;
+    if (n_patches < 0 || n_patches > NLOS_MAX_PATCHES || !out) return NLOS_EINVAL;
+    if (n_patches > 0 && !patches) return NLOS_EINVAL;
+    if ((patches && !aligned(patches, 16)) || !aligned(out, 16) || (n_active && !aligned(n_active, 4)))
+        return NLOS_EINVAL;
+    nlos::FwdArgs a;
+    rc = fill_args(p, patches, n_patches, n_active, out, &a);
+    if (rc != NLOS_OK) return rc;
+    nlos::Plan plan;
+    rc = make_plan(p, n_patches, a.R, &plan);
+    if (rc != NLOS_OK) return rc;
+    const int dev = device_check();
+    if (dev != NLOS_OK) return dev;
+    const bool conf = is_confocal(p);
+    a.tiles_l = conf ? 1 : (p->laser.nx * p->laser.ny + plan.tl - 1) / plan.tl;
+    a.tiles_x = (p->relay.nx + plan.tx - 1) / plan.tx;
+    a.tiles_y = (p->relay.ny + plan.ty - 1) / plan.ty;
+    a.n_split = plan.n_split;
+    a.tw = plan.tw;
+    a.n_tw = plan.n_tw;
+    a.stride = plan.stride;
+    a.q_cap = plan.q_cap;
+    a.atomic_out = plan.n_split > 1 ? 1 : 0;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (a.atomic_out) {
+        e = nlos::launch_fill(out, (size_t)n_hist(p) * (size_t)p->n_bins, st);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    e = nlos::launch_forward(a, plan, conf, st);
+    return e == hipSuccess ? NLOS_OK : hip_fail(e);
+}
+
+int nlos_debug_bins(const nlos_params* p, const float* patches, int32_t n_patches, const int32_t* n_active,
+                    int32_t* bins, double* u_fast, double* u_exact, void* stream)
+{
+    int rc = params_ok(p);
+    if (rc != NLOS_OK) return rc;
+    if (n_patches < 0 || n_patches > NLOS_MAX_PATCHES || !bins) return NLOS_EINVAL;
+    if (n_patches > 0 && !patches) return NLOS_EINVAL;
+    if ((patches && !aligned(patches, 16)) || !aligned(bins, 4) || (u_fast && !aligned(u_fast, 8)) ||
+        (u_exact && !aligned(u_exact, 8)))
+        return NLOS_EINVAL;
+    const int64_t pairs = n_hist(p) * (int64_t)n_patches;
+    if (pairs > ((int64_t)1 << 31)) return NLOS_EINVAL;
+    nlos::DebugArgs d;
+    std::memset(&d, 0, sizeof(d));
+    rc = fill_args(p, patches, n_patches, n_active, nullptr, &d.f);
+    if (rc != NLOS_OK) return rc;
+    const int dev = device_check();
+    if (dev != NLOS_OK) return dev;
+    d.bins = bins;
+    d.u_fast = u_fast;
+    d.u_exact = u_exact;
+    d.n_pairs = pairs;
+    d.confocal = is_confocal(p) ? 1 : 0;
+    const hipError_t e = nlos::launch_debug(d, (hipStream_t)stream);
+    return e == hipSuccess ? NLOS_OK : hip_fail(e);
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Internal interface between the C ABI layer (nlos_abi.cpp) and the HIP
+// kernels (nlos_geometry.hip, nlos_forward.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace nlos {
+
+constexpr int kMaxRadius = 127;
+constexpr int kMaxTaps = 2 * kMaxRadius + 1;
+constexpr int kBlock = 1024;           // threads per workgroup of the pair kernels
+constexpr int kInterleave = 8;         // record order: (ix mod 8, iy mod 8) phases
+
+// Canonical cell-centred coordinate: fp32(a0 + (i + 0.5) * step), computed in
+// fp64 (a0 = c - half, step = 2 half / n, both computed on the host in fp64).
+struct Axis {
+    double a0, step;
+    int32_t n;
+};
+
+struct GeomArgs {
+    const float* depth;
+    const float* albedo;   // nullable -> 0.5
+    const uint8_t* mask;   // nullable -> all present
+    float4* patches;       // [n][2] float4 records
+    int32_t* n_active;
+    int32_t* counts;       // workspace: per enumeration block
+    int32_t* offsets;      // workspace: exclusive prefix of counts
+    Axis ax, ay;
+    float hx, hy;          // spacings
+    int32_t bx, by;        // ceil(n / 8) per axis
+    int64_t n_enum;        // 64 * bx * by
+    int32_t n_blocks;      // ceil(n_enum / kGeomBlock)
+    int32_t cosines;
+};
+constexpr int kGeomBlock = 1024;
+
+// Arguments of the pair kernels (confocal and non-confocal).
+struct FwdArgs {
+    const float4* patches;
+    const int32_t* n_active;   // nullable
+    int32_t n_cap;
+    float* out;
+    Axis rx, ry;               // relay (detector) grid
+    Axis lx, ly;               // laser grid (non-confocal)
+    double cx, cy, s;          // device position (cx, cy, s)
+    double inv;                // 1 / (c dt), bins per metre
+    float inv_f;               // fp32(inv)
+    float inv2_f;              // fp32(2 inv)
+    float delta;               // guard half-width, bins
+    float two_delta;
+    float dummy_x;             // x of a stand-in patch arriving >= T + 64 bins
+    int32_t T;
+    int32_t tiles_x, tiles_y;  // tiles over the detector grid
+    int32_t tiles_l;           // tiles over the laser points (non-confocal)
+    int32_t n_split;           // patch ranges per tile
+    int32_t tw, n_tw;          // output time window per workgroup, and count
+    int32_t stride;            // floats per LDS histogram row
+    int32_t q_cap;             // guard-queue entries
+    int32_t atomic_out;        // 1: accumulate into a zeroed output
+    int32_t cosines;
+    int32_t R;
+    float taps[kMaxTaps];
+};
+
+// Debug/test hook arguments.
+struct DebugArgs {
+    FwdArgs f;
+    int32_t* bins;
+    double* u_fast;
+    double* u_exact;
+    int64_t n_pairs;
+    int32_t confocal;
+};
+
+// Launch plan of the pair kernel.
+struct Plan {
+    int tx, ty, tl;        // tile: detector points along x, y; laser points
+    int n_split;
+    int tw, n_tw;
+    int stride;
+    int q_cap;
+    size_t lds_bytes;
+    int64_t n_blocks;
+};
+
+size_t lds_bytes_for(int slots, int stride, int q_cap);
+bool tile_supported(bool confocal, int tx, int ty, int tl);
+
+hipError_t launch_geometry(const GeomArgs& a, hipStream_t st);
+hipError_t launch_forward(const FwdArgs& a, const Plan& plan, bool confocal, hipStream_t st);
+hipError_t launch_fill(float* out, size_t n, hipStream_t st);
+hipError_t launch_debug(const DebugArgs& a, hipStream_t st);
+
+}  // namespace nlos

@@ -1,0 +1,147 @@
+"""The C-ABI library without a GPU: it loads, exports every entry point the
+header declares, its structs have the header's layout, and host-side argument
+checks give the documented codes before anything touches a device."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nlos.h")
+
+
+@pytest.fixture(scope="module")
+def nat():
+    from paper_2506_03747_amd import _native
+    _native.lib()
+    return _native
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(nlos_\w+)\s*\(", src, re.M)))
+
+
+def test_exports_every_declared_symbol(nat):
+    names = declared_functions()
+    assert len(names) == 8, names
+    for n in names:
+        assert hasattr(nat.lib(), n), n
+    bound = {s[0] for s in nat.SIGNATURES}
+    assert bound == set(names)
+    out = subprocess.run(["nm", "-D", "--defined-only", nat.LIB_PATH], capture_output=True, text=True).stdout
+    for n in names:
+        assert re.search(rf"\bT {n}$", out, re.M), n
+
+
+def test_version_and_strerror(nat):
+    L = nat.lib()
+    assert L.nlos_abi_version() == 1
+    for code, text in ((0, "ok"), (-1, "invalid argument"), (-2, "workspace too small"),
+                       (-3, "HIP runtime error"), (-4, "no usable GPU"), (7, "unknown error")):
+        assert nat.strerror(code) == text
+
+
+def test_struct_layout_matches_header(nat, tmp_path):
+    """sizeof / offsetof from a C compiler reading the header itself."""
+    prog = tmp_path / "lay.c"
+    prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "nlos.h"\n'
+                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
+                    'sizeof(nlos_grid), offsetof(nlos_grid, half_x), offsetof(nlos_grid, cy),'
+                    'sizeof(nlos_params), offsetof(nlos_params, laser), offsetof(nlos_params, standoff_m),'
+                    'offsetof(nlos_params, n_bins), offsetof(nlos_params, flags), offsetof(nlos_params, fwhm_ps));'
+                    'return 0;}\n')
+    exe = tmp_path / "lay"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    G, P = nat.Grid, nat.Params
+    want = [C.sizeof(G), G.half_x.offset, G.cy.offset, C.sizeof(P), P.laser.offset, P.standoff_m.offset,
+            P.n_bins.offset, P.flags.offset, P.fwhm_ps.offset]
+    assert got == want
+
+
+def _params(nat, **kw):
+    g = nat.Grid(4, 4, 0.5, 0.5, 0.0, 0.0)
+    p = nat.Params(g, nat.Grid(0, 0, 0, 0, 0, 0), 0.0, 16.0, 64, nat.NLOS_F_COSINES, 70.0)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+FAKE = C.c_void_p(0x10000)   # aligned, never dereferenced: checks fail first
+
+
+@pytest.mark.parametrize("field,value", [
+    ("bin_ps", 0.0), ("bin_ps", -1.0), ("bin_ps", float("nan")), ("n_bins", 0), ("n_bins", (1 << 22) + 1),
+    ("standoff_m", -0.1), ("fwhm_ps", -1.0), ("flags", 2), ("fwhm_ps", 1e9)])
+def test_forward_rejects_bad_params(nat, field, value):
+    p = _params(nat, **{field: value})
+    rc = nat.lib().nlos_forward(C.byref(p), FAKE, 16, None, FAKE, None, 0, None)
+    assert rc == nat.NLOS_EINVAL
+
+
+def test_forward_rejects_bad_buffers(nat):
+    L = nat.lib()
+    p = _params(nat)
+    assert L.nlos_forward(None, FAKE, 16, None, FAKE, None, 0, None) == nat.NLOS_EINVAL
+    assert L.nlos_forward(C.byref(p), None, 16, None, FAKE, None, 0, None) == nat.NLOS_EINVAL
+    assert L.nlos_forward(C.byref(p), FAKE, 16, None, None, None, 0, None) == nat.NLOS_EINVAL
+    assert L.nlos_forward(C.byref(p), C.c_void_p(0x10004), 16, None, FAKE, None, 0, None) == nat.NLOS_EINVAL
+    assert L.nlos_forward(C.byref(p), FAKE, -1, None, FAKE, None, 0, None) == nat.NLOS_EINVAL
+    assert L.nlos_forward(C.byref(p), FAKE, (1 << 24) + 1, None, FAKE, None, 0, None) == nat.NLOS_EINVAL
+    bad_grid = _params(nat)
+    bad_grid.relay.nx = 0
+    assert L.nlos_forward(C.byref(bad_grid), FAKE, 16, None, FAKE, None, 0, None) == nat.NLOS_EINVAL
+    half_laser = _params(nat)
+    half_laser.laser.nx = 2   # ny = 0: neither confocal nor a valid laser grid
+    assert L.nlos_forward(C.byref(half_laser), FAKE, 16, None, FAKE, None, 0, None) == nat.NLOS_EINVAL
+
+
+def test_patches_checks(nat):
+    L = nat.lib()
+    g = nat.Grid(64, 64, 0.5, 0.5, 0.0, 0.0)
+    need = C.c_size_t(0)
+    assert L.nlos_patches_workspace_bytes(C.byref(g), C.byref(need)) == 0
+    assert need.value >= 8
+    assert L.nlos_patches_from_depth(C.byref(g), FAKE, None, None, 1, FAKE, FAKE, FAKE, need.value - 1,
+                                     None) == nat.NLOS_ENOSPC
+    assert L.nlos_patches_from_depth(C.byref(g), None, None, None, 1, FAKE, FAKE, FAKE, need.value,
+                                     None) == nat.NLOS_EINVAL
+    assert L.nlos_patches_from_depth(C.byref(g), FAKE, None, None, 4, FAKE, FAKE, FAKE, need.value,
+                                     None) == nat.NLOS_EINVAL
+    big = nat.Grid(8192, 4096, 0.5, 0.5, 0.0, 0.0)   # 2^25 pixels > limit
+    assert L.nlos_patches_from_depth(C.byref(big), FAKE, None, None, 1, FAKE, FAKE, FAKE, 1 << 30,
+                                     None) == nat.NLOS_EINVAL
+
+
+def test_debug_bins_limit(nat):
+    p = _params(nat)
+    p.relay.nx = p.relay.ny = 4096
+    rc = nat.lib().nlos_debug_bins(C.byref(p), FAKE, 1 << 20, None, FAKE, None, None, None)
+    assert rc == nat.NLOS_EINVAL
+
+
+def _gpu_present():
+    try:
+        import torch
+        return torch.cuda.device_count() > 0
+    except Exception:   # noqa: BLE001
+        return False
+
+
+@pytest.mark.skipif(_gpu_present(), reason="checks the no-device path; a GPU is present")
+def test_no_device_is_reported(nat):
+    p = _params(nat)
+    assert nat.lib().nlos_forward(C.byref(p), FAKE, 16, None, FAKE, None, 0, None) == nat.NLOS_ENODEV
+
+
+def test_python_layer_rejects_cpu_tensors(nat):
+    import torch
+    import paper_2506_03747_amd as nl
+    p = nl.make_params(dict(nx=4, ny=4, half_x=0.5, half_y=0.5), 64, 16.0)
+    with pytest.raises(TypeError):
+        nl.forward(p, torch.zeros(16, 8))
+    with pytest.raises(TypeError):
+        nl.patches_from_depth(torch.zeros(4, 4), dict(nx=4, ny=4, half_x=0.5, half_y=0.5))

@@ -1,0 +1,277 @@
+"""HIP path against the FP64 oracle on the same seeded inputs (GPU).
+
+Bar: bins bit-exact; every histogram within relative L2 1e-5 of the oracle
+(exact zeros where the oracle's histogram is zero)."""
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from gpu_helpers import (assert_parity, gpu_forward, gpu_patches, guard_delta, log,
+                         oracle_bins_for_records)
+
+pytestmark = pytest.mark.gpu
+
+
+def _records_vs_oracle(sc):
+    import torch
+    patches, n_act = gpu_patches(sc)
+    torch.cuda.synchronize()
+    P = patches.cpu().numpy()
+    n = int(n_act.item())
+    rec = oracle.patches(sc)
+    present = np.nonzero(rec[:, 7])[0]
+    assert n == len(present)
+    idx = P[:n, 7].view(np.int32)
+    assert sorted(idx.tolist()) == present.tolist()       # every present pixel exactly once
+    R = rec[idx]
+    # canonical positions and depth: identical fp32 values
+    np.testing.assert_array_equal(P[:n, 0], R[:, 0].astype(np.float32))
+    np.testing.assert_array_equal(P[:n, 1], R[:, 1].astype(np.float32))
+    np.testing.assert_array_equal(P[:n, 2], R[:, 2].astype(np.float32))
+    np.testing.assert_allclose(P[:n, 3], R[:, 3], rtol=2e-6)
+    np.testing.assert_allclose(P[:n, 4:7], R[:, 4:7], rtol=2e-6, atol=2e-7)
+    return n
+
+
+@pytest.mark.parametrize("make", [lambda: scenes.tiny(seed=300, patches=(13, 7)),
+                                  lambda: scenes.tiny(seed=301, patches=(1, 1), masked=False),
+                                  scenes.cfg1, scenes.cfg2, scenes.cfg3])
+def test_records_match_oracle(make):
+    sc = make()
+    log(f"records {sc.name}")
+    _records_vs_oracle(sc)
+
+
+TINY = [
+    dict(seed=400),
+    dict(seed=401, standoff_m=0.8),
+    dict(seed=402, cosines=False),
+    dict(seed=403, fwhm_ps=0.0),
+    dict(seed=404, scan=(3, 5), patches=(11, 9)),
+    dict(seed=405, scan=(7, 2), patches=(5, 13), standoff_m=0.4),
+    dict(seed=406, scan=(9, 9), patches=(17, 17), n_bins=61),            # T not a multiple of 4
+    dict(seed=407, scan=(1, 1), patches=(6, 6)),
+    dict(seed=408, laser=(2, 2), standoff_m=0.6),
+    dict(seed=409, laser=(3, 1), scan=(3, 4), standoff_m=0.0, cosines=False),
+    dict(seed=410, laser=(1, 1), scan=(5, 3), fwhm_ps=0.0),
+    dict(seed=411, laser=(5, 3), scan=(3, 3), patches=(9, 10), standoff_m=1.1),
+]
+
+
+@pytest.mark.parametrize("kw", TINY, ids=[str(k["seed"]) for k in TINY])
+def test_tiny_parity(kw):
+    sc = scenes.tiny(**kw)
+    log(f"tiny {kw}")
+    tau, _, _ = gpu_forward(sc)
+    ref = oracle.forward(sc)["tau"]
+    assert_parity(tau.cpu().numpy(), ref, what=sc.name)
+
+
+@pytest.mark.parametrize("kw", TINY[:6] + TINY[8:], ids=[str(k["seed"]) for k in TINY[:6] + TINY[8:]])
+def test_tiny_bins_exact(kw):
+    import torch
+    import paper_2506_03747_amd as nl
+    sc = scenes.tiny(**kw)
+    log(f"bins {kw}")
+    patches, n_act = gpu_patches(sc)
+    bins = nl.debug_bins(nl.params_of(sc), patches, n_act)
+    torch.cuda.synchronize()
+    n = int(n_act.item())
+    P = patches.cpu().numpy()
+    ref = oracle_bins_for_records(sc, P, n)
+    got = bins.cpu().numpy()
+    np.testing.assert_array_equal(got[:, :n], ref)
+    assert np.all(got[:, n:] == np.iinfo(np.int32).min)
+
+
+def test_cfg1_full():
+    sc = scenes.cfg1()
+    log("cfg1")
+    tau, _, _ = gpu_forward(sc)
+    ref = oracle.forward(sc)["tau"]
+    e = assert_parity(tau.cpu().numpy(), ref, what="cfg1")
+    log(f"cfg1 worst rel-L2 {e:.3e}")
+
+
+def test_cfg2_full():
+    sc = scenes.cfg2()
+    log("cfg2")
+    tau, _, _ = gpu_forward(sc)
+    ref = oracle.forward(sc)["tau"]
+    e = assert_parity(tau.cpu().numpy(), ref, what="cfg2")
+    log(f"cfg2 worst rel-L2 {e:.3e}")
+
+
+def test_cfg5_full():
+    sc = scenes.cfg5()
+    log("cfg5")
+    tau, _, _ = gpu_forward(sc)
+    ref = oracle.forward(sc)["tau"]
+    e = assert_parity(tau.cpu().numpy(), ref, what="cfg5")
+    log(f"cfg5 worst rel-L2 {e:.3e}")
+
+
+def test_cfg3_sampled():
+    """Non-confocal 64 lasers x 128^2 detectors x T=2048 (8.6 GB output):
+    4096 seeded histograms checked against the oracle."""
+    import torch
+    sc = scenes.cfg3()
+    log("cfg3")
+    tau, _, _ = gpu_forward(sc)
+    H = sc.n_laser * sc.n_scan
+    rng = np.random.default_rng(33)
+    sub = np.sort(rng.choice(H, 4096, replace=False)).astype(np.int32)
+    got = tau.reshape(H, -1)[torch.from_numpy(sub).long().cuda()].cpu().numpy()
+    del tau
+    torch.cuda.empty_cache()
+    ref = oracle.forward(sc, subset=sub)["tau"]
+    e = assert_parity(got, ref, what="cfg3")
+    log(f"cfg3 worst rel-L2 {e:.3e}")
+
+
+@pytest.mark.parametrize("name,n_hist", [("cfg1", None), ("cfg2", 256), ("cfg3", 128)])
+def test_bins_exact_configs(name, n_hist):
+    import torch
+    import paper_2506_03747_amd as nl
+    sc = scenes.by_name(name)
+    log(f"bins {name}")
+    patches, n_act = gpu_patches(sc)
+    prm = nl.params_of(sc)
+    H = nl.n_histograms(prm)
+    if n_hist is None:
+        sub = np.arange(H, dtype=np.int32)
+    else:
+        sub = np.sort(np.random.default_rng(7).choice(H, n_hist, replace=False)).astype(np.int32)
+    n = int(n_act.item())
+    # the GPU export covers every histogram; keep memory modest on the big ones
+    rows = []
+    Pn = patches.cpu().numpy()
+    if H * patches.shape[0] <= (1 << 28):
+        bins = nl.debug_bins(prm, patches, n_act)
+        torch.cuda.synchronize()
+        got = bins[torch.from_numpy(sub).long().cuda()].cpu().numpy()
+        del bins
+    else:
+        # cfg3: pass a record subset of the same patches through fewer histograms is not
+        # possible (H is fixed), so split the records instead
+        step = max(1, (1 << 28) // H)
+        for s0 in range(0, n, step):
+            part = patches[s0:min(n, s0 + step)].contiguous()
+            b = nl.debug_bins(prm, part, None)
+            torch.cuda.synchronize()
+            rows.append(b[torch.from_numpy(sub).long().cuda()].cpu().numpy())
+            del b
+        got = np.concatenate(rows, axis=1)
+    ref = oracle_bins_for_records(sc, Pn, n, subset=sub)
+    np.testing.assert_array_equal(got[:, :n], ref)
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg2", "cfg3"])
+def test_guard_band_holds(name):
+    """The fp32 arrival stays within half the guard width of the fp64 one for
+    every pair at or before the window end: the fast path's bins are safe."""
+    import torch
+    import paper_2506_03747_amd as nl
+    sc = scenes.by_name(name)
+    log(f"guard {name}")
+    patches, n_act = gpu_patches(sc)
+    n = int(n_act.item())
+    prm = nl.params_of(sc)
+    H = nl.n_histograms(prm)
+    cap = max(1, (1 << 26) // H)
+    part = patches[: min(n, cap)].contiguous()
+    _, uf, ue = nl.debug_bins(prm, part, None, want_u=True)
+    torch.cuda.synchronize()
+    near = ue <= sc.n_bins + 1
+    err = (uf - ue).abs()[near].max().item()
+    d = guard_delta(sc.n_bins)
+    log(f"{name}: max |u32 - u64| = {err:.3e} bins, guard {d:.3e}")
+    assert err <= 0.5 * d
+
+
+def test_empty_scene():
+    sc = scenes.tiny(seed=500, scan=(4, 4), patches=(8, 8))
+    sc.mask = np.zeros_like(sc.mask)
+    tau, _, n_act = gpu_forward(sc)
+    assert int(n_act.item()) == 0
+    assert not tau.cpu().numpy().any()
+
+
+def test_without_n_active_pointer():
+    sc = scenes.tiny(seed=501, scan=(5, 5), patches=(12, 12), standoff_m=0.3)
+    tau, _, _ = gpu_forward(sc, use_n_active=False)
+    assert_parity(tau.cpu().numpy(), oracle.forward(sc)["tau"], what="no n_active")
+
+
+def test_single_bin_window():
+    sc = scenes.tiny(seed=502, scan=(3, 3), patches=(10, 10), n_bins=1, bin_ps=2000.0, fwhm_ps=0.0)
+    tau, _, _ = gpu_forward(sc)
+    ref = oracle.forward(sc)["tau"]
+    assert ref.any()
+    assert_parity(tau.cpu().numpy(), ref, what="T=1")
+
+
+def test_time_windows():
+    """A histogram longer than LDS: the time axis is split over workgroups."""
+    sc = scenes.tiny(seed=503, scan=(2, 3), patches=(24, 24), n_bins=50000, bin_ps=2.0,
+                     fwhm_ps=40.0, zlo=0.5, zhi=4.0, half=2.0)
+    tau, _, _ = gpu_forward(sc)
+    ref = oracle.forward(sc)["tau"]
+    assert_parity(tau.cpu().numpy(), ref, what="time windows")
+
+
+def test_patch_split_many_patches_few_scan_points():
+    """Few histograms, many patches: patches are split over workgroups and
+    the partial histograms combined with float atomics."""
+    sc = scenes.tiny(seed=504, scan=(2, 2), patches=(160, 160), n_bins=256, bin_ps=20.0,
+                     fwhm_ps=60.0, masked=False)
+    tau, _, _ = gpu_forward(sc)
+    assert_parity(tau.cpu().numpy(), oracle.forward(sc)["tau"], what="split")
+
+
+def test_side_stream():
+    import torch
+    sc = scenes.tiny(seed=505, scan=(6, 6), patches=(20, 20), standoff_m=0.5)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        tau, _, _ = gpu_forward(sc, stream=s)
+    s.synchronize()
+    assert_parity(tau.cpu().numpy(), oracle.forward(sc)["tau"], what="side stream")
+
+
+def test_near_edge_arrivals():
+    """Depths chosen so that many fp64 arrivals lie within 1e-6 bins of a
+    bin edge: exactly the pairs the fp32 path must hand to the fp64 path."""
+    import torch
+    import paper_2506_03747_amd as nl
+    rng = np.random.default_rng(506)
+    inv = 1.0 / (299792458.0 * (10.0 * 1e-12))
+    n = 32
+    # patch right below scan point (0,0): u = 2 z inv; pick fp32 z with frac(u) tiny
+    cands = rng.uniform(0.3, 0.9, 2_000_000).astype(np.float32)
+    u = 2.0 * cands.astype(np.float64) * inv
+    fr = u - np.floor(u)
+    close = cands[(fr < 1e-6) | (fr > 1 - 1e-6)]
+    assert len(close) >= n * n // 4
+    depth = rng.uniform(0.3, 0.9, (n, n)).astype(np.float32)
+    depth.flat[: n * n // 4] = close[: n * n // 4]
+    sc = scenes.tiny(seed=506, scan=(1, 1), patches=(n, n), n_bins=512, bin_ps=10.0, half=0.5,
+                     masked=False)
+    sc.depth = depth
+    sc.relay = scenes.grid(1, 1, 0.5)
+    patches, n_act = gpu_patches(sc)
+    bins = nl.debug_bins(nl.params_of(sc), patches, n_act)
+    torch.cuda.synchronize()
+    k = int(n_act.item())
+    ref = oracle_bins_for_records(sc, patches.cpu().numpy(), k)
+    np.testing.assert_array_equal(bins.cpu().numpy()[:, :k], ref)
+    tau, _, _ = gpu_forward(sc)
+    assert_parity(tau.cpu().numpy(), oracle.forward(sc)["tau"], what="near edge")
+
+
+def test_repeatable_within_tolerance():
+    sc = scenes.cfg1()
+    a, _, _ = gpu_forward(sc)
+    b, _, _ = gpu_forward(sc)
+    assert_parity(a.cpu().numpy(), b.cpu().numpy().astype(np.float64), tol=1e-6, what="repeat")
