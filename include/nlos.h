@@ -137,9 +137,9 @@ int nlos_patches_workspace_bytes(const nlos_grid* g, size_t* bytes);
  *           differences of the depth map (one-sided at the border); the rest
  *           of the buffer is left unspecified.  A pixel is present when its
  *           mask is nonzero, its albedo > 0 and its depth finite and > 0.
- *           Records come in a fixed spatially interleaved order (pixels whose
- *           (ix mod 8, iy mod 8) phase is equal are consecutive), which spreads
- *           consecutive records over the surface; the order is deterministic.
+ *           Records come in a fixed, deterministic order: 16x16-pixel
+ *           blocks (x major), each as 4 stride-2 phases of 8x8 pixels, so any
+ *           64 consecutive records cover a small square of the surface.
  *   n_active device int32[1]: number of present patches.
  *   ws, ws_bytes device workspace of at least nlos_patches_workspace_bytes.
  * Limits: nx*ny <= NLOS_MAX_PATCHES.

@@ -10,7 +10,7 @@
 #include <cstring>
 #include <mutex>
 
-#include "../../include/nlos.h"
+#include "nlos.h"
 #include "nlos_internal.h"
 
 namespace {
@@ -189,7 +189,7 @@ int make_plan(const nlos_params* p, int32_t n_patches, int R, nlos::Plan* plan)
         chosen = nc - 1;
         q_cap = 1024;
         const size_t fixed = nlos::lds_bytes_for(1, 0, q_cap);
-        const int tl_max = (int)((kLdsMax - fixed - 256) / 4) & ~1;
+        const int tl_max = (int)((kLdsMax - fixed - 256) / 8) & ~1;
         tw = tl_max - 2 * R;
         if (tw < 64) return NLOS_EINVAL;
         tw &= ~3;
@@ -242,9 +242,9 @@ int nlos_last_hip_error(void) { return g_last_hip; }
 int nlos_patches_workspace_bytes(const nlos_grid* g, size_t* bytes)
 {
     if (!grid_ok(g) || !bytes) return NLOS_EINVAL;
-    const int64_t bx = (g->nx + nlos::kInterleave - 1) / nlos::kInterleave;
-    const int64_t by = (g->ny + nlos::kInterleave - 1) / nlos::kInterleave;
-    const int64_t n_enum = 64 * bx * by;
+    const int64_t bx = (g->nx + nlos::kBlockPx - 1) / nlos::kBlockPx;
+    const int64_t by = (g->ny + nlos::kBlockPx - 1) / nlos::kBlockPx;
+    const int64_t n_enum = (int64_t)nlos::kBlockPx * nlos::kBlockPx * bx * by;
     const int64_t blocks = (n_enum + nlos::kGeomBlock - 1) / nlos::kGeomBlock;
     *bytes = (size_t)(2 * blocks * sizeof(int32_t) + 256);
     return NLOS_OK;
@@ -277,9 +277,9 @@ int nlos_patches_from_depth(const nlos_grid* g, const float* depth, const float*
     a.ay = axis(g->half_y, g->cy, g->ny);
     a.hx = (float)a.ax.step;
     a.hy = (float)a.ay.step;
-    a.bx = (g->nx + nlos::kInterleave - 1) / nlos::kInterleave;
-    a.by = (g->ny + nlos::kInterleave - 1) / nlos::kInterleave;
-    a.n_enum = 64 * (int64_t)a.bx * a.by;
+    a.bx = (g->nx + nlos::kBlockPx - 1) / nlos::kBlockPx;
+    a.by = (g->ny + nlos::kBlockPx - 1) / nlos::kBlockPx;
+    a.n_enum = (int64_t)nlos::kBlockPx * nlos::kBlockPx * a.bx * a.by;
     a.n_blocks = (int32_t)((a.n_enum + nlos::kGeomBlock - 1) / nlos::kGeomBlock);
     a.counts = reinterpret_cast<int32_t*>(ws);
     a.offsets = a.counts + a.n_blocks;

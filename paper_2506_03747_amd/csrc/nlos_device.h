@@ -108,6 +108,7 @@ __device__ __forceinline__ void row_terms(const PatchC& c, float wy, float* cy2,
 //   q = clamp(pz^3 n.(w-p) / r^4, 0, 1) = cos_wall cos_patch (pz / r)^2.
 struct Leg {
     float rr;   // r
+    float ri2;  // 1 / r^2
     float ri4;  // 1 / r^4
     float q;    // cosine factor in [0, 1]
 };
@@ -118,8 +119,8 @@ __device__ __forceinline__ Leg leg_eval(float cx2, float cy2, float ax, float by
     const float r2 = cx2 + cy2;
     const float ri = __builtin_amdgcn_rsqf(r2);
     l.rr = r2 * ri;
-    const float ri2 = ri * ri;
-    l.ri4 = ri2 * ri2;
+    l.ri2 = ri * ri;
+    l.ri4 = l.ri2 * l.ri2;
     l.q = cosines ? __builtin_amdgcn_fmed3f((ax + by) * l.ri4, 0.0f, 1.0f) : 1.0f;
     return l;
 }

@@ -8,10 +8,11 @@
 //   3. scatter: each present pixel computes its record (canonical position,
 //               normal from central differences, albedo * area) and writes it
 //               at offset + rank within the block (wave ballots).
-// Enumeration order: e -> phase = e / (bx*by) picks (ix mod 8, iy mod 8), the
-// remainder walks the coarse 8x8 cells x major.  Consecutive records are thus
-// 8 pixels apart, which spreads the patches a wavefront holds over the
-// surface (their arrivals fall in different bins, so LDS atomics collide less).
+// Enumeration order: 16x16-pixel blocks (x major over blocks), each split
+// into 4 phases (ix mod 2, iy mod 2) of 8x8 pixels at stride 2.  A wavefront
+// of 64 consecutive records then covers one small square of the surface (so a
+// whole wavefront can be culled against a scan tile) while neighbouring lanes
+// sit 2 pixels apart (so their arrivals fall in fewer common bins).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -24,11 +25,13 @@ namespace nlos {
 __device__ __forceinline__ bool enum_pixel(const GeomArgs& a, int64_t e, int* ix, int* iy)
 {
     if (e >= a.n_enum) return false;
-    const int64_t nb = (int64_t)a.bx * a.by;
-    const int phase = (int)(e / nb);
-    const int64_t c = e - (int64_t)phase * nb;
-    *ix = (int)(c / a.by) * kInterleave + phase / kInterleave;
-    *iy = (int)(c % a.by) * kInterleave + phase % kInterleave;
+    const int64_t chunk = e >> 6;
+    const int w = (int)(e & 63);
+    const int phase = (int)(chunk & 3);
+    const int64_t blk = chunk >> 2;
+    const int bxi = (int)(blk / a.by), byi = (int)(blk % a.by);
+    *ix = bxi * kBlockPx + (w >> 3) * 2 + (phase >> 1);
+    *iy = byi * kBlockPx + (w & 7) * 2 + (phase & 1);
     return *ix < a.ax.n && *iy < a.ay.n;
 }
 

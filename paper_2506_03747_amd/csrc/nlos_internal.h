@@ -12,7 +12,7 @@ namespace nlos {
 constexpr int kMaxRadius = 127;
 constexpr int kMaxTaps = 2 * kMaxRadius + 1;
 constexpr int kBlock = 1024;           // threads per workgroup of the pair kernels
-constexpr int kInterleave = 8;         // record order: (ix mod 8, iy mod 8) phases
+constexpr int kBlockPx = 16;           // record order: 16x16-pixel blocks, 4 stride-2 phases
 
 // Canonical cell-centred coordinate: fp32(a0 + (i + 0.5) * step), computed in
 // fp64 (a0 = c - half, step = 2 half / n, both computed on the host in fp64).
@@ -31,8 +31,8 @@ struct GeomArgs {
     int32_t* offsets;      // workspace: exclusive prefix of counts
     Axis ax, ay;
     float hx, hy;          // spacings
-    int32_t bx, by;        // ceil(n / 8) per axis
-    int64_t n_enum;        // 64 * bx * by
+    int32_t bx, by;        // ceil(n / 16) per axis
+    int64_t n_enum;        // 256 * bx * by
     int32_t n_blocks;      // ceil(n_enum / kGeomBlock)
     int32_t cosines;
 };
