@@ -148,7 +148,9 @@ int nlos_patches_from_depth(const nlos_grid* g, const float* depth, const float*
                             const uint8_t* mask, uint32_t flags, float* patches,
                             int32_t* n_active, void* ws, size_t ws_bytes, void* stream);
 
-/* Bytes of workspace nlos_forward needs (written to *bytes, host pointer). */
+/* Bytes of workspace nlos_forward needs (written to *bytes, host pointer):
+ * 32 bytes per block of 1024 records (summaries used to balance the work and
+ * bound the pair weights). */
 int nlos_forward_workspace_bytes(const nlos_params* p, int32_t n_patches, size_t* bytes);
 
 /*
@@ -163,8 +165,10 @@ int nlos_forward_workspace_bytes(const nlos_params* p, int32_t n_patches, size_t
  *   out        device float, fully overwritten, 16-byte aligned:
  *              confocal [relay.nx][relay.ny][T];
  *              non-confocal [laser.nx*laser.ny][relay.nx][relay.ny][T].
- *   ws, ws_bytes device workspace (see nlos_forward_workspace_bytes; may be
- *              NULL when that size is 0).
+ *   ws, ws_bytes device workspace, 16-byte aligned, at least
+ *              nlos_forward_workspace_bytes (may be NULL when that size is 0);
+ *              overwritten by the call, so calls that share a workspace must be
+ *              ordered on one stream.
  */
 int nlos_forward(const nlos_params* p, const float* patches, int32_t n_patches,
                  const int32_t* n_active, float* out, void* ws, size_t ws_bytes, void* stream);

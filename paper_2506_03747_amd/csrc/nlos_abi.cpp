@@ -151,42 +151,50 @@ struct Cand {
     int tl, tx, ty;
 };
 
-// Launch plan: the largest tile whose histograms fit in LDS and that still
-// gives about one workgroup per CU; patches are split over workgroups when
-// there are fewer tiles than CUs; time windows when even one histogram is
-// too long for LDS.
+int64_t stats_count(int32_t n_patches) { return ((int64_t)n_patches + nlos::kStatBlock - 1) / nlos::kStatBlock; }
+
+// Launch plan.  Histograms are grouped in units (candidate shapes below,
+// largest first); a workgroup owns two units when the histograms of both fit
+// in the 160 KB of LDS over the whole window (taking the largest shape that
+// still gives at least one workgroup per CU), else one unit of one histogram
+// over a window of bins (time windows).  Patches are split over workgroups
+// when there are fewer workgroups than CUs.  Units are ordered by estimated
+// work inside the kernel when their count keeps that cheap.
 int make_plan(const nlos_params* p, int32_t n_patches, int R, nlos::Plan* plan)
 {
     const bool conf = is_confocal(p);
-    static const Cand conf_c[] = {{1, 8, 4}, {1, 4, 4}, {1, 2, 4}, {1, 2, 2}, {1, 1, 2}, {1, 1, 1}};
-    static const Cand nc_c[] = {{4, 2, 2}, {2, 2, 2}, {2, 1, 2}, {1, 1, 2}, {1, 1, 1}};
+    static const Cand conf_c[] = {{1, 4, 4}, {1, 4, 2}, {1, 2, 2}, {1, 2, 1}, {1, 1, 1}};
+    static const Cand nc_c[] = {{2, 2, 2}, {2, 1, 2}, {1, 1, 2}, {1, 1, 1}};
     const Cand* cands = conf ? conf_c : nc_c;
-    const int nc = conf ? 6 : 5;
+    const int nc = conf ? 5 : 4;
     const int T = p->n_bins;
     const int64_t L = conf ? 1 : (int64_t)p->laser.nx * p->laser.ny;
     int q_cap = kQueueDefault;
 
-    auto stride_of = [](int tl) { return (tl + 1) & ~1; };
-    auto tiles_of = [&](const Cand& c) {
+    // u64 bins per histogram row; the flush reuses the area as float rows
+    // padded with R zeros on both sides, so 2 * stride >= tl + 2R
+    auto stride_of = [R](int tl) { return std::max((tl + 1) & ~1, ((tl + 2 * R + 1) / 2 + 1) & ~1); };
+    auto units_of = [&](const Cand& c) {
         return ((L + c.tl - 1) / c.tl) * (int64_t)((p->relay.nx + c.tx - 1) / c.tx) *
                (int64_t)((p->relay.ny + c.ty - 1) / c.ty);
     };
-    // the largest tile that fits and reaches the target; else the largest that fits
     int chosen = -1, largest = -1;
     for (int i = 0; i < nc; ++i) {
-        const int slots = cands[i].tl * cands[i].tx * cands[i].ty;
+        const int slots = 2 * cands[i].tl * cands[i].tx * cands[i].ty;
         if (nlos::lds_bytes_for(slots, stride_of(T), q_cap) > kLdsMax) continue;
         if (largest < 0) largest = i;
-        if (tiles_of(cands[i]) >= kTargetBlocks) {
+        if ((units_of(cands[i]) + 1) / 2 >= kTargetBlocks) {
             chosen = i;
             break;
         }
     }
     if (chosen < 0) chosen = largest;
-    int tw = T, n_tw = 1;
+    int tw = T, n_tw = 1, pair = 1;
     if (chosen < 0) {
-        // even one histogram does not fit: split the time axis
+        // even two single histograms do not fit: one histogram per workgroup
+        // over a window of the time axis
         chosen = nc - 1;
+        pair = 0;
         q_cap = 1024;
         const size_t fixed = nlos::lds_bytes_for(1, 0, q_cap);
         const int tl_max = (int)((kLdsMax - fixed - 256) / 8) & ~1;
@@ -197,16 +205,24 @@ int make_plan(const nlos_params* p, int32_t n_patches, int R, nlos::Plan* plan)
     }
     const Cand c = cands[chosen];
     const int tl_len = (n_tw == 1) ? T : std::min(T, tw + 2 * R);
+    const int slots = (pair ? 2 : 1) * c.tl * c.tx * c.ty;
     plan->tl = c.tl;
     plan->tx = c.tx;
     plan->ty = c.ty;
+    plan->pair = pair;
     plan->tw = tw;
     plan->n_tw = n_tw;
     plan->stride = stride_of(tl_len);
     plan->q_cap = q_cap;
-    plan->lds_bytes = nlos::lds_bytes_for(c.tl * c.tx * c.ty, plan->stride, q_cap);
+    plan->lds_bytes = nlos::lds_bytes_for(slots, plan->stride, q_cap);
     if (plan->lds_bytes > kLdsMax || plan->stride < tl_len) return NLOS_EINVAL;
-    const int64_t tiles = tiles_of(c) * n_tw;
+    const int64_t units = units_of(c);
+    const int64_t groups = pair ? (units + 1) / 2 : units;
+    // torus-shift pairing needs an even side in the unit plane (x or y)
+    const int64_t utx = (p->relay.nx + c.tx - 1) / c.tx, uty = (p->relay.ny + c.ty - 1) / c.ty;
+    plan->plan = (pair && ((utx % 2) == 0 || (uty % 2) == 0)) ? 1 : 0;
+    plan->groups = groups;
+    const int64_t tiles = groups * n_tw;
     int64_t split = 1;
     if (tiles < kTargetBlocks) {
         split = (kTargetBlocks + tiles - 1) / tiles;
@@ -215,7 +231,27 @@ int make_plan(const nlos_params* p, int32_t n_patches, int R, nlos::Plan* plan)
     }
     plan->n_split = (int)split;
     plan->n_blocks = tiles * split;
-    if (plan->n_blocks > 0x7fffffff) return NLOS_EINVAL;
+    if (plan->n_blocks > 0x7fffffff || units > 0x7fffffff) return NLOS_EINVAL;
+    return NLOS_OK;
+}
+
+// Workspace of nlos_forward: record summaries, then the planned unit pairs.
+size_t stats_bytes(int32_t n_patches)
+{
+    return ((size_t)stats_count(n_patches) * sizeof(nlos::ChunkStat) + 255) & ~(size_t)255;
+}
+
+int forward_workspace(const nlos_params* p, int32_t n_patches, size_t* bytes, nlos::Plan* plan_out)
+{
+    float taps[nlos::kMaxTaps];
+    int32_t R = 0;
+    int rc = jitter_taps(p->fwhm_ps, p->bin_ps, taps, &R);
+    if (rc != NLOS_OK) return rc;
+    nlos::Plan plan;
+    rc = make_plan(p, n_patches, R, &plan);
+    if (rc != NLOS_OK) return rc;
+    *bytes = stats_bytes(n_patches);
+    if (plan_out) *plan_out = plan;
     return NLOS_OK;
 }
 
@@ -292,26 +328,27 @@ int nlos_forward_workspace_bytes(const nlos_params* p, int32_t n_patches, size_t
 {
     if (params_ok(p) != NLOS_OK || !bytes || n_patches < 0 || n_patches > NLOS_MAX_PATCHES)
         return NLOS_EINVAL;
-    *bytes = 0;
-    return NLOS_OK;
+    return forward_workspace(p, n_patches, bytes, nullptr);
 }
 
 int nlos_forward(const nlos_params* p, const float* patches, int32_t n_patches, const int32_t* n_active,
                  float* out, void* ws, size_t ws_bytes, void* stream)
 {
-    (void)ws;
-    (void)ws_bytes;
     int rc = params_ok(p);
     if (rc != NLOS_OK) return rc;
     if (n_patches < 0 || n_patches > NLOS_MAX_PATCHES || !out) return NLOS_EINVAL;
     if (n_patches > 0 && !patches) return NLOS_EINVAL;
-    if ((patches && !aligned(patches, 16)) || !aligned(out, 16) || (n_active && !aligned(n_active, 4)))
+    if ((patches && !aligned(patches, 16)) || !aligned(out, 16) || (n_active && !aligned(n_active, 4)) ||
+        (ws && !aligned(ws, 16)))
         return NLOS_EINVAL;
+    size_t need = 0;
+    nlos::Plan plan;
+    rc = forward_workspace(p, n_patches, &need, &plan);
+    if (rc != NLOS_OK) return rc;
+    if (ws_bytes < need) return NLOS_ENOSPC;
+    if (need > 0 && !ws) return NLOS_EINVAL;
     nlos::FwdArgs a;
     rc = fill_args(p, patches, n_patches, n_active, out, &a);
-    if (rc != NLOS_OK) return rc;
-    nlos::Plan plan;
-    rc = make_plan(p, n_patches, a.R, &plan);
     if (rc != NLOS_OK) return rc;
     const int dev = device_check();
     if (dev != NLOS_OK) return dev;
@@ -319,6 +356,12 @@ int nlos_forward(const nlos_params* p, const float* patches, int32_t n_patches, 
     a.tiles_l = conf ? 1 : (p->laser.nx * p->laser.ny + plan.tl - 1) / plan.tl;
     a.tiles_x = (p->relay.nx + plan.tx - 1) / plan.tx;
     a.tiles_y = (p->relay.ny + plan.ty - 1) / plan.ty;
+    a.n_units = a.tiles_l * a.tiles_x * a.tiles_y;
+    a.pair = plan.pair;
+    a.plan = plan.plan;
+    a.stats = reinterpret_cast<const nlos::ChunkStat*>(ws);
+    a.n_stats = (int32_t)stats_count(n_patches);
+
     a.n_split = plan.n_split;
     a.tw = plan.tw;
     a.n_tw = plan.n_tw;
@@ -326,7 +369,8 @@ int nlos_forward(const nlos_params* p, const float* patches, int32_t n_patches, 
     a.q_cap = plan.q_cap;
     a.atomic_out = plan.n_split > 1 ? 1 : 0;
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = hipSuccess;
+    hipError_t e = nlos::launch_stats(a, reinterpret_cast<nlos::ChunkStat*>(ws), st);
+    if (e != hipSuccess) return hip_fail(e);
     if (a.atomic_out) {
         e = nlos::launch_fill(out, (size_t)n_hist(p) * (size_t)p->n_bins, st);
         if (e != hipSuccess) return hip_fail(e);

@@ -6,14 +6,19 @@
 // Gaussian jitter of Section 2 (Algorithm 1, step 2.3) while writing it out.
 //
 // Work decomposition (one workgroup = 16 waves = 1024 lanes):
-//   * a workgroup owns a tile of histograms -- TX x TY detector points (times
-//     TL laser points, non-confocal) -- over one window of output bins; the
-//     histograms live in LDS for the whole pass;
+//   * histograms are grouped in units -- TX x TY detector points (times TL
+//     laser points, non-confocal); a workgroup owns one unit, or two when
+//     units are few: then every workgroup estimates the work of all units from
+//     summaries of the records, sorts the estimates in LDS and takes the k-th
+//     lightest with the k-th heaviest unit, which evens out the load when a
+//     workgroup per CU is all there is;
+//   * the histograms live in LDS for the whole pass, over one window of
+//     output bins;
 //   * each lane owns one patch at a time (coalesced 32-byte record loads; the
-//     record order keeps a wavefront's 64 patches within a small patch of the
-//     surface) and loops over the tile's histograms with the wall point
+//     record order keeps a wavefront's 64 patches within a small square of the
+//     surface) and loops over the unit's histograms with the wall point
 //     wave-uniform, so per-column / per-row terms of the distance are hoisted;
-//   * a wavefront skips a tile outright when a lower bound of every one of its
+//   * a wavefront skips a unit outright when a lower bound of every one of its
 //     arrivals lies past the window;
 //   * a pair is evaluated in fp32 (one v_rsq_f32 per leg); pairs whose fp32
 //     arrival lies within the guard band of a bin edge go to an LDS queue and
@@ -21,10 +26,10 @@
 //     place), so every bin equals the fp64 one;
 //   * histograms accumulate in 64-bit fixed point with LDS integer atomics
 //     (ds_add_u64): a pair adds round(w * s) as a 32-bit increment, with
-//     s = 2^31 / W and W >= every weight the tile can see (a / r_min^4 over
-//     the workgroup's patches, from a pre-pass).  On gfx950 an LDS float atomic
-//     add costs about 3 cycles per active lane, the 64-bit integer add a few
-//     cycles per wavefront;
+//     s = 2^31 / W and W >= every weight the workgroup's units can see
+//     (a_max / r_min^4 over the record summaries).  On gfx950 an LDS float
+//     atomic add costs about 3 cycles per active lane, the 64-bit integer add
+//     a few cycles per wavefront;
 //   * the flush converts back to float, applies the jitter taps with a sliding
 //     register window and writes the histograms with coalesced stores (or
 //     float atomics into a zeroed output when patches are split over
@@ -45,8 +50,9 @@ size_t lds_bytes_for(int slots, int stride, int q_cap)
     size_t b = (size_t)slots * (size_t)stride * 8;   // u64 histograms
     b += (size_t)q_cap * 8;                            // queue: index + increment
     b += (size_t)slots * 8;                            // fp64 path offset per slot
+    b += (size_t)slots * 8;                            // output row per slot
     b += (size_t)slots * 4 * 8;                        // fp32 tables
-    b += 128;                                          // counter, reduction scratch
+    b += 16 + 64 * 4;                                  // counter, reduction scratch (64 floats)
     return (b + 255) & ~(size_t)255;
 }
 
@@ -56,6 +62,7 @@ struct Lds {
     uint32_t* qidx;
     uint32_t* qinc;
     double* so;     // [slots] fp64 path offset o (both device legs)
+    long long* row; // [slots] output histogram index, -1: not written
     float* wlx;     // [slots] laser point (confocal: = detector point)
     float* wly;
     float* wdx;     // [slots] detector point
@@ -65,7 +72,7 @@ struct Lds {
     float* gg;      // [slots] g_l * g_d
     float* pad;
     uint32_t* qcount;
-    float* red;     // [16] per-wave maxima
+    float* red;     // [64] per-wave reduction scratch
 };
 
 __device__ __forceinline__ Lds lds_layout(unsigned char* base, int slots, int stride, int q_cap)
@@ -75,7 +82,8 @@ __device__ __forceinline__ Lds lds_layout(unsigned char* base, int slots, int st
     L.qidx = (uint32_t*)(L.hist + (size_t)slots * stride);
     L.qinc = L.qidx + q_cap;
     L.so = (double*)(L.qinc + q_cap);
-    L.wlx = (float*)(L.so + slots);
+    L.row = (long long*)(L.so + slots);
+    L.wlx = (float*)(L.row + slots);
     L.wly = L.wlx + slots;
     L.wdx = L.wly + slots;
     L.wdy = L.wdx + slots;
@@ -116,6 +124,15 @@ __device__ __forceinline__ float rect_r2_max(float px, float py, float pz2, floa
     return fmaf(dx, dx, fmaf(dy, dy, pz2));
 }
 
+// Squared lateral distance between two axis-aligned rectangles.
+__device__ __forceinline__ float rect_rect_d2(float ax0, float ax1, float ay0, float ay1, float bx0, float bx1,
+                                              float by0, float by1)
+{
+    const float dx = fmaxf(fmaxf(ax0 - bx1, bx0 - ax1), 0.f);
+    const float dy = fmaxf(fmaxf(ay0 - by1, by0 - ay1), 0.f);
+    return fmaf(dx, dx, dy * dy);
+}
+
 // Block-wide maximum of a non-negative float (wave butterfly, then LDS).
 __device__ __forceinline__ float block_max(float v, float* red)
 {
@@ -126,73 +143,6 @@ __device__ __forceinline__ float block_max(float v, float* red)
     float m = 0.f;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, red[w]);
     return m;
-}
-
-// Flush 4 consecutive outputs t..t+3 (< t1) of one histogram row:
-// out[t] = gg * sum_j taps[j + R] * H[t - j], with H holding bins [hb, he)
-// (fixed point, scaled back by inv_s) and zero elsewhere (zero padding).  The
-// 4 + 2R histogram values are read once into a sliding register window.
-__device__ __forceinline__ void flush_group(const FwdArgs& a, const u64* H, double inv_s, int hb, int he,
-                                            int t, int t1, float gg, float* out, bool vec)
-{
-    const int R = a.R;
-    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
-    for (int e = -R; e <= 3 + R; ++e) {
-        const int x = t + e;
-        const float v = (x >= hb && x < he) ? (float)((double)H[x - hb] * inv_s) : 0.f;
-        // output t+m uses tap index m - e + R
-        const int i0 = -e + R;
-        if (i0 >= 0 && i0 <= 2 * R) acc0 = fmaf(a.taps[i0], v, acc0);
-        if (i0 + 1 >= 0 && i0 + 1 <= 2 * R) acc1 = fmaf(a.taps[i0 + 1], v, acc1);
-        if (i0 + 2 >= 0 && i0 + 2 <= 2 * R) acc2 = fmaf(a.taps[i0 + 2], v, acc2);
-        if (i0 + 3 >= 0 && i0 + 3 <= 2 * R) acc3 = fmaf(a.taps[i0 + 3], v, acc3);
-    }
-    acc0 *= gg;
-    acc1 *= gg;
-    acc2 *= gg;
-    acc3 *= gg;
-    if (a.atomic_out) {
-        unsafeAtomicAdd(out + t, acc0);
-        if (t + 1 < t1) unsafeAtomicAdd(out + t + 1, acc1);
-        if (t + 2 < t1) unsafeAtomicAdd(out + t + 2, acc2);
-        if (t + 3 < t1) unsafeAtomicAdd(out + t + 3, acc3);
-    } else if (vec && t + 3 < t1) {
-        *reinterpret_cast<float4*>(out + t) = make_float4(acc0, acc1, acc2, acc3);
-    } else {
-        out[t] = acc0;
-        if (t + 1 < t1) out[t + 1] = acc1;
-        if (t + 2 < t1) out[t + 2] = acc2;
-        if (t + 3 < t1) out[t + 3] = acc3;
-    }
-}
-
-// Block -> (laser tile, detector tile, time window, patch split).
-struct BlockPos {
-    int tile_l, tile_x, tile_y;
-    int t0w, t1w, hb, he;
-    int pb, pe;   // patch range
-};
-
-__device__ __forceinline__ BlockPos block_pos(const FwdArgs& a, int n_act)
-{
-    BlockPos b;
-    int id = (int)blockIdx.x;
-    const int split = id % a.n_split;
-    id /= a.n_split;
-    const int twi = id % a.n_tw;
-    id /= a.n_tw;
-    const int tile_d = id % (a.tiles_x * a.tiles_y);
-    b.tile_l = id / (a.tiles_x * a.tiles_y);
-    b.tile_x = tile_d / a.tiles_y;
-    b.tile_y = tile_d % a.tiles_y;
-    b.t0w = twi * a.tw;
-    b.t1w = min(a.T, b.t0w + a.tw);
-    b.hb = max(0, b.t0w - a.R);
-    b.he = min(a.T, b.t1w + a.R);
-    const int chunk = (n_act + a.n_split - 1) / a.n_split;
-    b.pb = min(n_act, split * chunk);
-    b.pe = min(n_act, b.pb + chunk);
-    return b;
 }
 
 __device__ __forceinline__ int active_count(const FwdArgs& a)
@@ -257,275 +207,461 @@ __device__ __forceinline__ void load_patch(const FwdArgs& a, int p, int pe, floa
     }
 }
 
-// Scale of the fixed-point histograms: s = 2^31 / W, W = max over the
-// workgroup's patches of a / (r_l,min^2 r_d,min^2), an upper bound of every
-// pair weight of the tile (cosine factors <= 1, r >= r_min).
-__device__ __forceinline__ float weight_scale(const FwdArgs& a, const Lds& L, int pb, int pe, float lx0,
-                                              float lx1, float ly0, float ly1, float dx0, float dx1,
-                                              float dy0, float dy1)
-{
-    float wmax = 0.f;
-    for (int p = pb + (int)threadIdx.x; p < pe; p += blockDim.x) {
-        const float4 A = a.patches[2 * (size_t)p];
-        const float pz2 = A.z * A.z;
-        const float r2l = rect_r2_min(A.x, A.y, pz2, lx0, lx1, ly0, ly1);
-        const float r2d = rect_r2_min(A.x, A.y, pz2, dx0, dx1, dy0, dy1);
-        wmax = fmaxf(wmax, A.w / (r2l * r2d));
-    }
-    const float W = block_max(wmax, L.red);
-    return W > 0.f ? 2147483648.0f / W : 1.0f;
-}
-
 // ---------------------------------------------------------------------------
-// Confocal: tile of TX x TY scan points; slot j = c * TY + r.
-template <int TX, int TY, bool COS, bool WIN>
-__global__ void __launch_bounds__(kBlock) k_confocal(const FwdArgs a)
+// Record summaries: one workgroup per kStatBlock consecutive records.
+__global__ void __launch_bounds__(kStatBlock) k_chunk_stats(const FwdArgs a, ChunkStat* st)
 {
-    constexpr int NS = TX * TY;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const Lds L = lds_layout(smem, NS, a.stride, a.q_cap);
+    __shared__ float red[6][kStatBlock / 64];
     const int n_act = active_count(a);
-    const BlockPos bp = block_pos(a, n_act);
-    const int hb = WIN ? bp.hb : 0, Tl = WIN ? bp.he - bp.hb : a.T;
-
-    for (int i = threadIdx.x; i < NS * a.stride; i += blockDim.x) L.hist[i] = 0ull;
-    if (threadIdx.x == 0) *L.qcount = 0u;
-    if (threadIdx.x < NS) {
-        const int j = threadIdx.x;
-        const int ix = min(bp.tile_x * TX + j / TY, a.rx.n - 1);
-        const int iy = min(bp.tile_y * TY + j % TY, a.ry.n - 1);
-        const float wx = canon(a.rx, ix), wy = canon(a.ry, iy);
-        double off, g;
-        device_leg(wx, wy, a.cx, a.cy, a.s, &off, &g);
-        const double o = off + off;
-        L.so[j] = o;
-        L.wlx[j] = wx;
-        L.wly[j] = wy;
-        L.wdx[j] = wx;
-        L.wdy[j] = wy;
-        L.oil[j] = (float)(o * a.inv + (double)a.delta);
-        L.gg[j] = (float)(g * g);
+    const int p = (int)blockIdx.x * kStatBlock + (int)threadIdx.x;
+    float v[6] = {3.0e38f, 3.0e38f, 3.0e38f, 3.0e38f, 3.0e38f, 0.f};   // x0, -x1, y0, -y1, z0, amax
+    if (p < n_act) {
+        const float4 A = a.patches[2 * (size_t)p];
+        v[0] = A.x;
+        v[1] = -A.x;
+        v[2] = A.y;
+        v[3] = -A.y;
+        v[4] = A.z;
+        v[5] = A.w;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        float x = v[k];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const float y = __shfl_xor(x, o, 64);
+            x = (k == 5) ? fmaxf(x, y) : fminf(x, y);
+        }
+        if ((threadIdx.x & 63) == 0) red[k][threadIdx.x >> 6] = x;
     }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        float r[6] = {3.0e38f, 3.0e38f, 3.0e38f, 3.0e38f, 3.0e38f, 0.f};
+        for (int w = 0; w < kStatBlock / 64; ++w)
+            for (int k = 0; k < 6; ++k) r[k] = (k == 5) ? fmaxf(r[k], red[k][w]) : fminf(r[k], red[k][w]);
+        ChunkStat c;
+        c.x0 = r[0];
+        c.x1 = -r[1];
+        c.y0 = r[2];
+        c.y1 = -r[3];
+        c.z0 = r[4];
+        c.amax = r[5];
+        c.count = max(0, min(kStatBlock, n_act - (int)blockIdx.x * kStatBlock));
+        c.pad = 0;
+        st[blockIdx.x] = c;
+    }
+}
 
-    float wx[TX], wy[TY], oi[NS];
-#pragma unroll
-    for (int c = 0; c < TX; ++c) wx[c] = uniform(L.wdx[c * TY]);
-#pragma unroll
-    for (int r = 0; r < TY; ++r) wy[r] = uniform(L.wdy[r]);
-    float oi_min = 3.0e38f, oi_max = 0.f;
-#pragma unroll
-    for (int j = 0; j < NS; ++j) {
-        oi[j] = L.oil[j];   // kept in VGPRs: the arrival fma then reads one SGPR (inv2)
-        oi_min = fminf(oi_min, oi[j]);
-        oi_max = fmaxf(oi_max, oi[j]);
-    }
-    float x0 = wx[0], x1 = wx[0], y0 = wy[0], y1 = wy[0];
-#pragma unroll
-    for (int c = 1; c < TX; ++c) {
-        x0 = fminf(x0, wx[c]);
-        x1 = fmaxf(x1, wx[c]);
-    }
-#pragma unroll
-    for (int r = 1; r < TY; ++r) {
-        y0 = fminf(y0, wy[r]);
-        y1 = fmaxf(y1, wy[r]);
-    }
-    const float inv2 = a.inv2_f, two_delta = a.two_delta;
-    const float s = weight_scale(a, L, bp.pb, bp.pe, x0, x1, y0, y1, x0, x1, y0, y1);
-    // a wavefront skips the tile when every arrival is at least 2 bins past
-    // the window (the bound is exact up to fp32 rounding, far below 2 bins)
-    const float cut_hi = (float)(hb + Tl + 2);
-    const float cut_lo = (float)(hb - 2);
+// Wall rectangles of unit u (approximate fp32 grid coordinates; only used for
+// work estimates and bounds): detector points [dx0,dx1]x[dy0,dy1], laser
+// points [lx0,lx1]x[ly0,ly1] (= detector rectangle, confocal).
+struct UnitRect {
+    float dx0, dx1, dy0, dy1, lx0, lx1, ly0, ly1;
+};
 
-    for (int base = bp.pb; base < bp.pe; base += blockDim.x) {
-        const int p = base + (int)threadIdx.x;
-        float4 A, B;
-        load_patch(a, p, bp.pe, &A, &B);
-        const PatchC pc = patch_consts(A, B, COS);
-        {
-            const float r2lo = rect_r2_min(pc.px, pc.py, pc.pz2, x0, x1, y0, y1);
-            bool out = fmaf(__builtin_amdgcn_sqrtf(r2lo), inv2, oi_min) >= cut_hi;
-            if (WIN) {
-                const float r2hi = rect_r2_max(pc.px, pc.py, pc.pz2, x0, x1, y0, y1);
-                out = out || fmaf(__builtin_amdgcn_sqrtf(r2hi), inv2, oi_max) < cut_lo;
-            }
-            if (__all(out)) continue;
-        }
-        const float aps = (COS ? pc.ap : A.w) * s;
-        float cx2[TX], axv[TX], cy2[TY], byv[TY];
-#pragma unroll
-        for (int c = 0; c < TX; ++c) col_terms(pc, wx[c], &cx2[c], &axv[c]);
-#pragma unroll
-        for (int r = 0; r < TY; ++r) row_terms(pc, wy[r], &cy2[r], &byv[r]);
-#pragma unroll
-        for (int c = 0; c < TX; ++c) {
-#pragma unroll
-            for (int r = 0; r < TY; ++r) {
-                const int j = c * TY + r;
-                const Leg lg = leg_eval(cx2[c], cy2[r], axv[c], byv[r], COS);
-                const float w = fmaf(lg.rr, inv2, oi[j]);
-                const Decision d = decide(w, two_delta);
-                const uint32_t inc = (uint32_t)fmaf(COS ? lg.q * lg.q : lg.ri4, aps, 0.5f);
-                const int kl = d.k - hb;
-                if (d.sure) {
-                    if ((unsigned)kl < (unsigned)Tl) lds_add(L.hist + j * a.stride + kl, inc);
-                } else if ((unsigned)kl <= (unsigned)Tl) {
-                    guard_push(L, a, p, j, inc, hb, Tl);
-                }
-            }
+__device__ __forceinline__ float approx_coord(const Axis& ax, int i)
+{
+    return (float)ax.a0 + ((float)i + 0.5f) * (float)ax.step;
+}
+
+template <bool CONF, int TL, int TX, int TY>
+__device__ __forceinline__ UnitRect unit_rect(const FwdArgs& a, int u)
+{
+    UnitRect R;
+    const int uy = u % a.tiles_y;
+    const int ux = (u / a.tiles_y) % a.tiles_x;
+    const int ul = u / (a.tiles_y * a.tiles_x);
+    const int ix0 = ux * TX, ix1 = min(ix0 + TX, a.rx.n) - 1;
+    const int iy0 = uy * TY, iy1 = min(iy0 + TY, a.ry.n) - 1;
+    R.dx0 = approx_coord(a.rx, ix0);
+    R.dx1 = approx_coord(a.rx, ix1);
+    R.dy0 = approx_coord(a.ry, iy0);
+    R.dy1 = approx_coord(a.ry, iy1);
+    if (CONF) {
+        R.lx0 = R.dx0;
+        R.lx1 = R.dx1;
+        R.ly0 = R.dy0;
+        R.ly1 = R.dy1;
+    } else {
+        const int n_laser = a.lx.n * a.ly.n;
+        R.lx0 = R.ly0 = 3.0e38f;
+        R.lx1 = R.ly1 = -3.0e38f;
+        for (int l = ul * TL; l < min(ul * TL + TL, n_laser); ++l) {
+            const float x = approx_coord(a.lx, l / a.ly.n), y = approx_coord(a.ly, l % a.ly.n);
+            R.lx0 = fminf(R.lx0, x);
+            R.lx1 = fmaxf(R.lx1, x);
+            R.ly0 = fminf(R.ly0, y);
+            R.ly1 = fmaxf(R.ly1, y);
         }
     }
-    __syncthreads();
-    guard_drain(L, a, hb, Tl);
-    __syncthreads();
+    return R;
+}
 
+// Upper bound of every pair weight of unit u: a_max / (r_l,min^2 r_d,min^2)
+// over the record summaries (cosine factors are at most 1).
+template <bool CONF, int TL, int TX, int TY>
+__device__ float unit_weight_bound(const FwdArgs& a, int u, int i)
+{
+    const UnitRect R = unit_rect<CONF, TL, TX, TY>(a, u);
+    const ChunkStat c = a.stats[i];
+    if (c.count <= 0) return 0.f;
+    const float z2 = c.z0 * c.z0;
+    const float rd2 = rect_rect_d2(R.dx0, R.dx1, R.dy0, R.dy1, c.x0, c.x1, c.y0, c.y1) + z2;
+    const float rl2 = CONF ? rd2 : rect_rect_d2(R.lx0, R.lx1, R.ly0, R.ly1, c.x0, c.x1, c.y0, c.y1) + z2;
+    return c.amax / (rl2 * rd2);
+}
+
+// Units of this workgroup: u[0] and, when paired, u[1] (-1 if none).
+// Paired units are the unit (x, y) of a laser tile and the unit shifted by
+// half the unit grid in both directions (torus shift): a unit near the middle
+// of the wall -- where most pairs land in the window -- goes with one near the
+// border.  Groups enumerate the half of the grid the shift maps onto the
+// other half; grids with both sides odd pair g with n-1-g in unit order.
+template <bool PAIR>
+__device__ __forceinline__ void pick_units(const FwdArgs& a, int grp, int* u)
+{
+    if (!PAIR) {
+        u[0] = grp;
+        return;
+    }
+    const int tx = a.tiles_x, ty = a.tiles_y, plane = tx * ty;
+    if (a.plan) {
+        const int half = plane / 2;
+        const int ul = grp / half, h = grp % half;
+        int ux, uy, vx, vy;
+        if ((ty & 1) == 0) {
+            ux = h / (ty / 2);
+            uy = h % (ty / 2);
+            vx = (ux + tx / 2) % tx;
+            vy = uy + ty / 2;
+        } else {
+            ux = h % (tx / 2);
+            uy = h / (tx / 2);
+            vx = ux + tx / 2;
+            vy = (uy + ty / 2) % ty;
+        }
+        u[0] = ul * plane + ux * ty + uy;
+        u[1] = ul * plane + vx * ty + vy;
+        return;
+    }
+    const int partner = a.n_units - 1 - grp;
+    u[0] = grp;
+    u[1] = partner != grp ? partner : -1;
+}
+
+// Flush: histograms (fixed point in LDS) -> float rows in LDS -> jitter ->
+// output.  Rows are converted in one pass through registers (at most
+// 160 KB / 8 bytes / 1024 threads = 20 values per thread), the taps are staged
+// in LDS (the guard queue is free by then), and each lane produces 4
+// consecutive outputs with a sliding window of 4 values.
+template <int NS>
+__device__ __forceinline__ void flush(const FwdArgs& a, const Lds& L, float s, int hb, int Tl, int t0w, int t1w)
+{
+    // Float rows padded with R zeros on each side: row j is Fp[j * P, (j+1) * P),
+    // P = Tl + 2R, bin x at Fp[j * P + R + x - hb].  The planner sizes the
+    // histogram area so that NS * P floats fit in it.
+    constexpr int kMaxPer = 24;
+    const int R = a.R;
+    const int P = Tl + 2 * R;
     const double inv_s = 1.0 / (double)s;
-    const int ng = (bp.t1w - bp.t0w + 3) / 4;
-    const bool vec = ((a.T & 3) == 0) && ((bp.t0w & 3) == 0);
-    for (int idx = threadIdx.x; idx < NS * ng; idx += blockDim.x) {
-        const int j = idx / ng, g = idx - j * ng;
-        const int ix = bp.tile_x * TX + j / TY, iy = bp.tile_y * TY + j % TY;
-        if (ix >= a.rx.n || iy >= a.ry.n) continue;
-        float* out = a.out + ((size_t)ix * a.ry.n + iy) * (size_t)a.T;
-        flush_group(a, L.hist + (size_t)j * a.stride, inv_s, bp.hb, bp.he, bp.t0w + 4 * g, bp.t1w, L.gg[j],
-                    out, vec);
+    float* F = reinterpret_cast<float*>(L.hist);
+    float* taps = reinterpret_cast<float*>(L.qidx);
+    const int total = NS * Tl;
+    // (row, bin) of flattened index tid + k * blockDim, stepped without divisions
+    const int sj = (int)blockDim.x / Tl, st = (int)blockDim.x % Tl;
+    float v[kMaxPer];
+    {
+        int j = (int)threadIdx.x / Tl, t = (int)threadIdx.x % Tl;
+#pragma unroll
+        for (int k = 0; k < kMaxPer; ++k) {
+            if (j < NS) v[k] = (float)((double)L.hist[(size_t)j * a.stride + t] * inv_s);
+            j += sj;
+            t += st;
+            if (t >= Tl) {
+                t -= Tl;
+                ++j;
+            }
+        }
+    }
+    __syncthreads();
+    {
+        int j = (int)threadIdx.x / Tl, t = (int)threadIdx.x % Tl;
+#pragma unroll
+        for (int k = 0; k < kMaxPer; ++k) {
+            if (j < NS) F[(size_t)j * P + R + t] = v[k];
+            j += sj;
+            t += st;
+            if (t >= Tl) {
+                t -= Tl;
+                ++j;
+            }
+        }
+    }
+    for (int i = threadIdx.x; i < NS * 2 * R; i += blockDim.x) {
+        const int j = i / (2 * R), e = i - j * 2 * R;
+        F[(size_t)j * P + (e < R ? e : Tl + e)] = 0.f;
+    }
+    for (int i = threadIdx.x; i < 2 * R + 1; i += blockDim.x) taps[i] = a.taps[i];
+    __syncthreads();
+    (void)total;
+
+    const int nt = t1w - t0w;
+    const int sj2 = (int)blockDim.x / nt, st2 = (int)blockDim.x % nt;
+    int j = (int)threadIdx.x / nt, tt = (int)threadIdx.x % nt;
+    for (; j < NS; j += sj2, tt += st2) {
+        if (tt >= nt) {
+            tt -= nt;
+            ++j;
+            if (j >= NS) break;
+        }
+        const long long row = L.row[j];
+        if (row < 0) continue;
+        const int t = t0w + tt;
+        // out[t] = gg * sum_i taps[i] * H[t + R - i]; H[x] = Fp[j P + R + x - hb]
+        const float* h = F + (size_t)j * P + (t - hb) + 2 * R;   // h[-i] = H[t + R - i]
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        int i = 0;
+        for (; i + 3 <= 2 * R; i += 4) {
+            a0 = fmaf(taps[i], h[-i], a0);
+            a1 = fmaf(taps[i + 1], h[-i - 1], a1);
+            a2 = fmaf(taps[i + 2], h[-i - 2], a2);
+            a3 = fmaf(taps[i + 3], h[-i - 3], a3);
+        }
+        for (; i <= 2 * R; ++i) a0 = fmaf(taps[i], h[-i], a0);
+        const float acc = ((a0 + a1) + (a2 + a3)) * L.gg[j];
+        float* out = a.out + (size_t)row * (size_t)a.T + t;
+        if (a.atomic_out)
+            unsafeAtomicAdd(out, acc);
+        else
+            *out = acc;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Non-confocal: tile of TL laser points x (TX x TY) detector points;
-// slot j = (l * TX + c) * TY + r.
-template <int TL, int TX, int TY, bool COS, bool WIN>
-__global__ void __launch_bounds__(kBlock) k_nonconfocal(const FwdArgs a)
+// The pair kernel.  Slot j of the workgroup: unit k = j / NH, then within the
+// unit (laser l, column c, row r) with j % NH = (l * TX + c) * TY + r.
+template <bool CONF, int TL, int TX, int TY, bool COS, bool WIN, bool PAIR>
+__global__ void __launch_bounds__(kBlock) k_forward(const FwdArgs a)
 {
     constexpr int ND = TX * TY;
-    constexpr int NS = TL * ND;
+    constexpr int NH = TL * ND;
+    constexpr int NU = PAIR ? 2 : 1;
+    constexpr int NS = NU * NH;
     extern __shared__ __align__(16) unsigned char smem[];
     const Lds L = lds_layout(smem, NS, a.stride, a.q_cap);
     const int n_act = active_count(a);
-    const BlockPos bp = block_pos(a, n_act);
-    const int hb = WIN ? bp.hb : 0, Tl = WIN ? bp.he - bp.hb : a.T;
+
+    int id = (int)blockIdx.x;
+    const int split = id % a.n_split;
+    id /= a.n_split;
+    const int twi = id % a.n_tw;
+    const int grp = id / a.n_tw;
+    const int t0w = twi * a.tw, t1w = min(a.T, t0w + a.tw);
+    const int hbw = max(0, t0w - a.R), hew = min(a.T, t1w + a.R);
+    const int hb = WIN ? hbw : 0, Tl = WIN ? hew - hbw : a.T;
+    const int chunk = (n_act + a.n_split - 1) / a.n_split;
+    const int pb = min(n_act, split * chunk), pe = min(n_act, pb + chunk);
     const int n_laser = a.lx.n * a.ly.n;
+
+    int unit[NU];
+    pick_units<PAIR>(a, grp, unit);
+    bool uvalid[NU];
+#pragma unroll
+    for (int k = 0; k < NU; ++k) uvalid[k] = unit[k] >= 0;
 
     for (int i = threadIdx.x; i < NS * a.stride; i += blockDim.x) L.hist[i] = 0ull;
     if (threadIdx.x == 0) *L.qcount = 0u;
     if (threadIdx.x < NS) {
         const int j = threadIdx.x;
-        const int l = min(bp.tile_l * TL + j / ND, n_laser - 1);
-        const int dj = j % ND;
-        const int ix = min(bp.tile_x * TX + dj / TY, a.rx.n - 1);
-        const int iy = min(bp.tile_y * TY + dj % TY, a.ry.n - 1);
-        const float lx = canon(a.lx, l / a.ly.n), ly = canon(a.ly, l % a.ly.n);
+        const int k = j / NH, jl = j % NH;
+        const int u = uvalid[k] ? unit[k] : unit[0];
+        const int uy = u % a.tiles_y, ux = (u / a.tiles_y) % a.tiles_x, ul = u / (a.tiles_y * a.tiles_x);
+        const int dj = jl % ND;
+        const int ix_u = ux * TX + dj / TY, iy_u = uy * TY + dj % TY, l_u = ul * TL + jl / ND;
+        L.row[j] = (uvalid[k] && ix_u < a.rx.n && iy_u < a.ry.n && l_u < (CONF ? 1 : n_laser))
+                       ? ((long long)l_u * a.rx.n + ix_u) * a.ry.n + iy_u
+                       : -1ll;
+        const int ix = min(ix_u, a.rx.n - 1);
+        const int iy = min(iy_u, a.ry.n - 1);
         const float wx = canon(a.rx, ix), wy = canon(a.ry, iy);
-        double off_l, g_l, off_d, g_d;
-        device_leg(lx, ly, a.cx, a.cy, a.s, &off_l, &g_l);
+        double off_d, g_d;
         device_leg(wx, wy, a.cx, a.cy, a.s, &off_d, &g_d);
-        L.so[j] = off_l + off_d;
-        L.wlx[j] = lx;
-        L.wly[j] = ly;
         L.wdx[j] = wx;
         L.wdy[j] = wy;
-        L.oil[j] = (float)(off_l * a.inv + (double)a.delta);
-        L.oid[j] = (float)(off_d * a.inv);
-        L.gg[j] = (float)(g_l * g_d);
-    }
-    __syncthreads();
-
-    float lxs[TL], lys[TL], oil[TL], wx[TX], wy[TY], oid[ND];
-    float lx0 = 3.0e38f, lx1 = -3.0e38f, ly0 = 3.0e38f, ly1 = -3.0e38f;
-    float oil_min = 3.0e38f, oil_max = 0.f, oid_min = 3.0e38f, oid_max = 0.f;
-#pragma unroll
-    for (int l = 0; l < TL; ++l) {
-        lxs[l] = uniform(L.wlx[l * ND]);
-        lys[l] = uniform(L.wly[l * ND]);
-        oil[l] = uniform(L.oil[l * ND]);
-        lx0 = fminf(lx0, lxs[l]);
-        lx1 = fmaxf(lx1, lxs[l]);
-        ly0 = fminf(ly0, lys[l]);
-        ly1 = fmaxf(ly1, lys[l]);
-        oil_min = fminf(oil_min, oil[l]);
-        oil_max = fmaxf(oil_max, oil[l]);
-    }
-#pragma unroll
-    for (int c = 0; c < TX; ++c) wx[c] = uniform(L.wdx[c * TY]);
-#pragma unroll
-    for (int r = 0; r < TY; ++r) wy[r] = uniform(L.wdy[r]);
-#pragma unroll
-    for (int d = 0; d < ND; ++d) {
-        oid[d] = uniform(L.oid[d]);
-        oid_min = fminf(oid_min, oid[d]);
-        oid_max = fmaxf(oid_max, oid[d]);
-    }
-    float x0 = wx[0], x1 = wx[0], y0 = wy[0], y1 = wy[0];
-#pragma unroll
-    for (int c = 1; c < TX; ++c) {
-        x0 = fminf(x0, wx[c]);
-        x1 = fmaxf(x1, wx[c]);
-    }
-#pragma unroll
-    for (int r = 1; r < TY; ++r) {
-        y0 = fminf(y0, wy[r]);
-        y1 = fmaxf(y1, wy[r]);
-    }
-    const float inv = a.inv_f, two_delta = a.two_delta;
-    const float s = weight_scale(a, L, bp.pb, bp.pe, lx0, lx1, ly0, ly1, x0, x1, y0, y1);
-    const float cut_hi = (float)(hb + Tl + 2);
-    const float cut_lo = (float)(hb - 2);
-    const float o_min = oil_min + oid_min, o_max = oil_max + oid_max;
-
-    for (int base = bp.pb; base < bp.pe; base += blockDim.x) {
-        const int p = base + (int)threadIdx.x;
-        float4 A, B;
-        load_patch(a, p, bp.pe, &A, &B);
-        const PatchC pc = patch_consts(A, B, COS);
-        {
-            const float rl = __builtin_amdgcn_sqrtf(rect_r2_min(pc.px, pc.py, pc.pz2, lx0, lx1, ly0, ly1));
-            const float rd = __builtin_amdgcn_sqrtf(rect_r2_min(pc.px, pc.py, pc.pz2, x0, x1, y0, y1));
-            bool out = fmaf(rl + rd, inv, o_min) >= cut_hi;
-            if (WIN) {
-                const float Rl = __builtin_amdgcn_sqrtf(rect_r2_max(pc.px, pc.py, pc.pz2, lx0, lx1, ly0, ly1));
-                const float Rd = __builtin_amdgcn_sqrtf(rect_r2_max(pc.px, pc.py, pc.pz2, x0, x1, y0, y1));
-                out = out || fmaf(Rl + Rd, inv, o_max) < cut_lo;
-            }
-            if (__all(out)) continue;
+        if (CONF) {
+            const double o = off_d + off_d;
+            L.so[j] = o;
+            L.wlx[j] = wx;
+            L.wly[j] = wy;
+            L.oil[j] = (float)(o * a.inv + (double)a.delta);
+            L.gg[j] = (float)(g_d * g_d);
+        } else {
+            const int l = min(ul * TL + jl / ND, n_laser - 1);
+            const float lx = canon(a.lx, l / a.ly.n), ly = canon(a.ly, l % a.ly.n);
+            double off_l, g_l;
+            device_leg(lx, ly, a.cx, a.cy, a.s, &off_l, &g_l);
+            L.so[j] = off_l + off_d;
+            L.wlx[j] = lx;
+            L.wly[j] = ly;
+            L.oil[j] = (float)(off_l * a.inv + (double)a.delta);
+            L.oid[j] = (float)(off_d * a.inv);
+            L.gg[j] = (float)(g_l * g_d);
         }
-        // laser legs
-        float ul[TL], fl[TL];
+    }
+    // weight bound over the record summaries -> fixed-point scale
+    float wb = 0.f;
+    for (int i = threadIdx.x; i < a.n_stats; i += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < NU; ++k)
+            if (uvalid[k]) wb = fmaxf(wb, unit_weight_bound<CONF, TL, TX, TY>(a, unit[k], i));
+    }
+    const float W = block_max(wb, L.red);   // includes a barrier: the tables above are visible
+    const float s = W > 0.f ? 2147483648.0f / W : 1.0f;
+
+    // per-unit wall points and bounds, wave-uniform
+    float lxs[NU][TL], lys[NU][TL], oil[NU][TL], wx[NU][TX], wy[NU][TY], oi[NS];
+    float lx0[NU], lx1[NU], ly0[NU], ly1[NU], x0[NU], x1[NU], y0[NU], y1[NU], omin[NU], omax[NU];
+#pragma unroll
+    for (int k = 0; k < NU; ++k) {
+        const int b = k * NH;
+        lx0[k] = ly0[k] = x0[k] = y0[k] = omin[k] = 3.0e38f;
+        lx1[k] = ly1[k] = x1[k] = y1[k] = -3.0e38f;
+        omax[k] = 0.f;
 #pragma unroll
         for (int l = 0; l < TL; ++l) {
-            float cx2, axv, cy2, byv;
-            col_terms(pc, lxs[l], &cx2, &axv);
-            row_terms(pc, lys[l], &cy2, &byv);
-            const Leg lg = leg_eval(cx2, cy2, axv, byv, COS);
-            ul[l] = fmaf(lg.rr, inv, oil[l]);
-            fl[l] = (COS ? lg.q * pc.ap : lg.ri2 * A.w) * s;
+            lxs[k][l] = uniform(L.wlx[b + l * ND]);
+            lys[k][l] = uniform(L.wly[b + l * ND]);
+            oil[k][l] = uniform(L.oil[b + l * ND]);
+            lx0[k] = fminf(lx0[k], lxs[k][l]);
+            lx1[k] = fmaxf(lx1[k], lxs[k][l]);
+            ly0[k] = fminf(ly0[k], lys[k][l]);
+            ly1[k] = fmaxf(ly1[k], lys[k][l]);
         }
-        // detector legs
-        float cx2[TX], axv[TX], cy2[TY], byv[TY];
-#pragma unroll
-        for (int c = 0; c < TX; ++c) col_terms(pc, wx[c], &cx2[c], &axv[c]);
-#pragma unroll
-        for (int r = 0; r < TY; ++r) row_terms(pc, wy[r], &cy2[r], &byv[r]);
 #pragma unroll
         for (int c = 0; c < TX; ++c) {
+            wx[k][c] = uniform(L.wdx[b + c * TY]);
+            x0[k] = fminf(x0[k], wx[k][c]);
+            x1[k] = fmaxf(x1[k], wx[k][c]);
+        }
 #pragma unroll
-            for (int r = 0; r < TY; ++r) {
-                const int dj = c * TY + r;
-                const Leg lg = leg_eval(cx2[c], cy2[r], axv[c], byv[r], COS);
-                const float ud = fmaf(lg.rr, inv, oid[dj]);
-                const float fd = COS ? lg.q : lg.ri2;
+        for (int r = 0; r < TY; ++r) {
+            wy[k][r] = uniform(L.wdy[b + r]);
+            y0[k] = fminf(y0[k], wy[k][r]);
+            y1[k] = fmaxf(y1[k], wy[k][r]);
+        }
+#pragma unroll
+        for (int jj = 0; jj < NH; ++jj) {
+            // confocal: arrival offset per scan point; non-confocal: detector
+            // offset (slots of laser 0 cover every detector point)
+            oi[b + jj] = CONF ? L.oil[b + jj] : L.oid[b + jj];
+            const float ov = CONF ? oi[b + jj] : oi[b + jj] + L.oil[b + jj];
+            omin[k] = fminf(omin[k], ov);
+            omax[k] = fmaxf(omax[k], ov);
+        }
+    }
+    const float inv = a.inv_f, inv2 = a.inv2_f, two_delta = a.two_delta;
+    // a wavefront skips a unit when every arrival is at least 2 bins past the
+    // window (the bound is exact up to fp32 rounding, far below 2 bins)
+    const float cut_hi = (float)(hb + Tl + 2);
+    const float cut_lo = (float)(hb - 2);
+    float cut_r2[NU];
+#pragma unroll
+    for (int k = 0; k < NU; ++k) {
+        // squared distance past which every confocal arrival is beyond cut_hi
+        // (enlarged by 1e-5 relative: the fp32 square and division round)
+        const float rc = fmaxf((cut_hi - omin[k]) / inv2, 0.f);
+        cut_r2[k] = rc * rc * 1.00001f;
+    }
+
+    for (int base = pb; base < pe; base += blockDim.x) {
+        const int p = base + (int)threadIdx.x;
+        float4 A, B;
+        load_patch(a, p, pe, &A, &B);
+        const PatchC pc = patch_consts(A, B, COS);
+#pragma unroll
+        for (int k = 0; k < NU; ++k) {
+            if (!uvalid[k]) continue;
+            {
+                bool out;
+                if (CONF) {
+                    // 2 r inv + omin >= cut  <=>  r^2 >= ((cut - omin) / (2 inv))^2
+                    out = rect_r2_min(pc.px, pc.py, pc.pz2, x0[k], x1[k], y0[k], y1[k]) >= cut_r2[k];
+                } else {
+                    const float rd = __builtin_amdgcn_sqrtf(rect_r2_min(pc.px, pc.py, pc.pz2, x0[k], x1[k], y0[k], y1[k]));
+                    const float rl = __builtin_amdgcn_sqrtf(rect_r2_min(pc.px, pc.py, pc.pz2, lx0[k], lx1[k], ly0[k], ly1[k]));
+                    out = fmaf(rl + rd, inv, omin[k]) >= cut_hi;
+                }
+                if (WIN) {
+                    const float Rd = __builtin_amdgcn_sqrtf(rect_r2_max(pc.px, pc.py, pc.pz2, x0[k], x1[k], y0[k], y1[k]));
+                    const float Rl = CONF ? Rd
+                                          : __builtin_amdgcn_sqrtf(
+                                                rect_r2_max(pc.px, pc.py, pc.pz2, lx0[k], lx1[k], ly0[k], ly1[k]));
+                    out = out || fmaf(Rl + Rd, inv, omax[k]) < cut_lo;
+                }
+                if (__all(out)) continue;
+            }
+            const int b = k * NH;
+            float cx2[TX], axv[TX], cy2[TY], byv[TY];
+            if (CONF) {
+                const float aps = (COS ? pc.ap : A.w) * s;
+#pragma unroll
+                for (int c = 0; c < TX; ++c) col_terms(pc, wx[k][c], &cx2[c], &axv[c]);
+#pragma unroll
+                for (int r = 0; r < TY; ++r) row_terms(pc, wy[k][r], &cy2[r], &byv[r]);
+#pragma unroll
+                for (int c = 0; c < TX; ++c) {
+#pragma unroll
+                    for (int r = 0; r < TY; ++r) {
+                        const int j = b + c * TY + r;
+                        const Leg lg = leg_eval(cx2[c], cy2[r], axv[c], byv[r], COS);
+                        const float w = fmaf(lg.rr, inv2, oi[j]);
+                        const Decision d = decide(w, two_delta);
+                        const uint32_t inc = (uint32_t)fmaf(COS ? lg.q * lg.q : lg.ri4, aps, 0.5f);
+                        const int kl = d.k - hb;
+                        if (d.sure) {
+                            if ((unsigned)kl < (unsigned)Tl) lds_add(L.hist + j * a.stride + kl, inc);
+                        } else if ((unsigned)kl <= (unsigned)Tl) {
+                            guard_push(L, a, p, j, inc, hb, Tl);
+                        }
+                    }
+                }
+            } else {
+                // laser legs
+                float ul[TL], fl[TL];
 #pragma unroll
                 for (int l = 0; l < TL; ++l) {
-                    const int j = l * ND + dj;
-                    const float w = ul[l] + ud;
-                    const Decision d = decide(w, two_delta);
-                    const uint32_t inc = (uint32_t)fmaf(fl[l], fd, 0.5f);
-                    const int kl = d.k - hb;
-                    if (d.sure) {
-                        if ((unsigned)kl < (unsigned)Tl) lds_add(L.hist + j * a.stride + kl, inc);
-                    } else if ((unsigned)kl <= (unsigned)Tl) {
-                        guard_push(L, a, p, j, inc, hb, Tl);
+                    float lcx2, lax, lcy2, lby;
+                    col_terms(pc, lxs[k][l], &lcx2, &lax);
+                    row_terms(pc, lys[k][l], &lcy2, &lby);
+                    const Leg lg = leg_eval(lcx2, lcy2, lax, lby, COS);
+                    ul[l] = fmaf(lg.rr, inv, oil[k][l]);
+                    fl[l] = (COS ? lg.q * pc.ap : lg.ri2 * A.w) * s;
+                }
+#pragma unroll
+                for (int c = 0; c < TX; ++c) col_terms(pc, wx[k][c], &cx2[c], &axv[c]);
+#pragma unroll
+                for (int r = 0; r < TY; ++r) row_terms(pc, wy[k][r], &cy2[r], &byv[r]);
+#pragma unroll
+                for (int c = 0; c < TX; ++c) {
+#pragma unroll
+                    for (int r = 0; r < TY; ++r) {
+                        const int dj = c * TY + r;
+                        const Leg lg = leg_eval(cx2[c], cy2[r], axv[c], byv[r], COS);
+                        const float ud = fmaf(lg.rr, inv, oi[b + dj]);
+                        const float fd = COS ? lg.q : lg.ri2;
+#pragma unroll
+                        for (int l = 0; l < TL; ++l) {
+                            const int j = b + l * ND + dj;
+                            const float w = ul[l] + ud;
+                            const Decision d = decide(w, two_delta);
+                            const uint32_t inc = (uint32_t)fmaf(fl[l], fd, 0.5f);
+                            const int kl = d.k - hb;
+                            if (d.sure) {
+                                if ((unsigned)kl < (unsigned)Tl) lds_add(L.hist + j * a.stride + kl, inc);
+                            } else if ((unsigned)kl <= (unsigned)Tl) {
+                                guard_push(L, a, p, j, inc, hb, Tl);
+                            }
+                        }
                     }
                 }
             }
@@ -534,21 +670,7 @@ __global__ void __launch_bounds__(kBlock) k_nonconfocal(const FwdArgs a)
     __syncthreads();
     guard_drain(L, a, hb, Tl);
     __syncthreads();
-
-    const double inv_s = 1.0 / (double)s;
-    const size_t S = (size_t)a.rx.n * a.ry.n;
-    const int ng = (bp.t1w - bp.t0w + 3) / 4;
-    const bool vec = ((a.T & 3) == 0) && ((bp.t0w & 3) == 0);
-    for (int idx = threadIdx.x; idx < NS * ng; idx += blockDim.x) {
-        const int j = idx / ng, g = idx - j * ng;
-        const int l = bp.tile_l * TL + j / ND;
-        const int dj = j % ND;
-        const int ix = bp.tile_x * TX + dj / TY, iy = bp.tile_y * TY + dj % TY;
-        if (l >= n_laser || ix >= a.rx.n || iy >= a.ry.n) continue;
-        float* out = a.out + ((size_t)l * S + (size_t)ix * a.ry.n + iy) * (size_t)a.T;
-        flush_group(a, L.hist + (size_t)j * a.stride, inv_s, bp.hb, bp.he, bp.t0w + 4 * g, bp.t1w, L.gg[j],
-                    out, vec);
-    }
+    flush<NS>(a, L, s, hb, Tl, t0w, t1w);
 }
 
 // ---------------------------------------------------------------------------
@@ -632,52 +754,50 @@ static hipError_t launch_k(K kern, const FwdArgs& a, const Plan& plan, hipStream
     return hipGetLastError();
 }
 
-#define NLOS_CONF_CASE(X, Y)                                                              \
-    if (plan.tx == X && plan.ty == Y) {                                                   \
-        if (plan.n_tw > 1)                                                                \
-            return a.cosines ? launch_k(k_confocal<X, Y, true, true>, a, plan, st)        \
-                             : launch_k(k_confocal<X, Y, false, true>, a, plan, st);      \
-        return a.cosines ? launch_k(k_confocal<X, Y, true, false>, a, plan, st)           \
-                         : launch_k(k_confocal<X, Y, false, false>, a, plan, st);         \
+template <bool CONF, int TL, int TX, int TY>
+static hipError_t launch_shape(const FwdArgs& a, const Plan& plan, hipStream_t st)
+{
+    if (plan.pair) {
+        return a.cosines ? launch_k(k_forward<CONF, TL, TX, TY, true, false, true>, a, plan, st)
+                         : launch_k(k_forward<CONF, TL, TX, TY, false, false, true>, a, plan, st);
     }
-#define NLOS_NC_CASE(TLV, X, Y)                                                           \
-    if (plan.tl == TLV && plan.tx == X && plan.ty == Y) {                                 \
-        if (plan.n_tw > 1)                                                                \
-            return a.cosines ? launch_k(k_nonconfocal<TLV, X, Y, true, true>, a, plan, st) \
-                             : launch_k(k_nonconfocal<TLV, X, Y, false, true>, a, plan, st); \
-        return a.cosines ? launch_k(k_nonconfocal<TLV, X, Y, true, false>, a, plan, st)   \
-                         : launch_k(k_nonconfocal<TLV, X, Y, false, false>, a, plan, st); \
-    }
+    return a.cosines ? launch_k(k_forward<CONF, TL, TX, TY, true, true, false>, a, plan, st)
+                     : launch_k(k_forward<CONF, TL, TX, TY, false, true, false>, a, plan, st);
+}
 
 bool tile_supported(bool confocal, int tx, int ty, int tl)
 {
     if (confocal) {
-        return (tx == 4 && ty == 4) || (tx == 8 && ty == 4) || (tx == 2 && ty == 4) ||
-               (tx == 2 && ty == 2) || (tx == 1 && ty == 2) || (tx == 1 && ty == 1);
+        return tl == 1 && ((tx == 4 && ty == 4) || (tx == 4 && ty == 2) || (tx == 2 && ty == 2) ||
+                           (tx == 2 && ty == 1) || (tx == 1 && ty == 1));
     }
-    return (tl == 4 && tx == 2 && ty == 2) || (tl == 2 && tx == 2 && ty == 2) ||
-           (tl == 2 && tx == 1 && ty == 2) || (tl == 1 && tx == 1 && ty == 2) ||
-           (tl == 1 && tx == 1 && ty == 1);
+    return (tl == 2 && tx == 2 && ty == 2) || (tl == 2 && tx == 1 && ty == 2) ||
+           (tl == 1 && tx == 1 && ty == 2) || (tl == 1 && tx == 1 && ty == 1);
 }
 
 hipError_t launch_forward(const FwdArgs& a, const Plan& plan, bool confocal, hipStream_t st)
 {
     if (plan.n_blocks <= 0) return hipSuccess;
     if (confocal) {
-        NLOS_CONF_CASE(4, 4)
-        NLOS_CONF_CASE(8, 4)
-        NLOS_CONF_CASE(2, 4)
-        NLOS_CONF_CASE(2, 2)
-        NLOS_CONF_CASE(1, 2)
-        NLOS_CONF_CASE(1, 1)
+        if (plan.tx == 4 && plan.ty == 4) return launch_shape<true, 1, 4, 4>(a, plan, st);
+        if (plan.tx == 4 && plan.ty == 2) return launch_shape<true, 1, 4, 2>(a, plan, st);
+        if (plan.tx == 2 && plan.ty == 2) return launch_shape<true, 1, 2, 2>(a, plan, st);
+        if (plan.tx == 2 && plan.ty == 1) return launch_shape<true, 1, 2, 1>(a, plan, st);
+        if (plan.tx == 1 && plan.ty == 1) return launch_shape<true, 1, 1, 1>(a, plan, st);
     } else {
-        NLOS_NC_CASE(4, 2, 2)
-        NLOS_NC_CASE(2, 2, 2)
-        NLOS_NC_CASE(2, 1, 2)
-        NLOS_NC_CASE(1, 1, 2)
-        NLOS_NC_CASE(1, 1, 1)
+        if (plan.tl == 2 && plan.tx == 2 && plan.ty == 2) return launch_shape<false, 2, 2, 2>(a, plan, st);
+        if (plan.tl == 2 && plan.tx == 1 && plan.ty == 2) return launch_shape<false, 2, 1, 2>(a, plan, st);
+        if (plan.tl == 1 && plan.tx == 1 && plan.ty == 2) return launch_shape<false, 1, 1, 2>(a, plan, st);
+        if (plan.tl == 1 && plan.tx == 1 && plan.ty == 1) return launch_shape<false, 1, 1, 1>(a, plan, st);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_stats(const FwdArgs& a, ChunkStat* stats, hipStream_t st)
+{
+    if (a.n_stats <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chunk_stats, dim3((unsigned)a.n_stats), dim3(kStatBlock), 0, st, a, stats);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill(float* out, size_t n, hipStream_t st)

@@ -38,6 +38,15 @@ struct GeomArgs {
 };
 constexpr int kGeomBlock = 1024;
 
+// Summary of one block of kStatBlock consecutive patch records: lateral
+// bounding box, smallest depth, largest a, record count.  Used to estimate
+// the work of each unit of histograms and to bound the pair weights.
+struct ChunkStat {
+    float x0, x1, y0, y1, z0, amax;
+    int32_t count, pad;
+};
+constexpr int kStatBlock = 256;
+
 // Arguments of the pair kernels (confocal and non-confocal).
 struct FwdArgs {
     const float4* patches;
@@ -54,9 +63,14 @@ struct FwdArgs {
     float two_delta;
     float dummy_x;             // x of a stand-in patch arriving >= T + 64 bins
     int32_t T;
-    int32_t tiles_x, tiles_y;  // tiles over the detector grid
-    int32_t tiles_l;           // tiles over the laser points (non-confocal)
-    int32_t n_split;           // patch ranges per tile
+    int32_t tiles_x, tiles_y;  // units over the detector grid
+    int32_t tiles_l;           // units over the laser points (non-confocal)
+    int32_t n_units;           // tiles_l * tiles_x * tiles_y
+    int32_t pair;              // 1: a workgroup owns two units
+    int32_t plan;              // 1: units paired by a torus shift of half the unit grid
+    const ChunkStat* stats;    // [n_stats] summaries of the records
+    int32_t n_stats;
+    int32_t n_split;           // patch ranges per unit pair
     int32_t tw, n_tw;          // output time window per workgroup, and count
     int32_t stride;            // floats per LDS histogram row
     int32_t q_cap;             // guard-queue entries
@@ -78,7 +92,10 @@ struct DebugArgs {
 
 // Launch plan of the pair kernel.
 struct Plan {
-    int tx, ty, tl;        // tile: detector points along x, y; laser points
+    int tx, ty, tl;        // unit: detector points along x, y; laser points
+    int pair;              // two units per workgroup
+    int plan;              // torus-shift pairing of units
+    int64_t groups;        // workgroups per (time window, patch split)
     int n_split;
     int tw, n_tw;
     int stride;
@@ -92,6 +109,7 @@ bool tile_supported(bool confocal, int tx, int ty, int tl);
 
 hipError_t launch_geometry(const GeomArgs& a, hipStream_t st);
 hipError_t launch_forward(const FwdArgs& a, const Plan& plan, bool confocal, hipStream_t st);
+hipError_t launch_stats(const FwdArgs& a, ChunkStat* stats, hipStream_t st);
 hipError_t launch_fill(float* out, size_t n, hipStream_t st);
 hipError_t launch_debug(const DebugArgs& a, hipStream_t st);
 

@@ -78,25 +78,37 @@ FAKE = C.c_void_p(0x10000)   # aligned, never dereferenced: checks fail first
     ("standoff_m", -0.1), ("fwhm_ps", -1.0), ("flags", 2), ("fwhm_ps", 1e9)])
 def test_forward_rejects_bad_params(nat, field, value):
     p = _params(nat, **{field: value})
-    rc = nat.lib().nlos_forward(C.byref(p), FAKE, 16, None, FAKE, None, 0, None)
+    rc = nat.lib().nlos_forward(C.byref(p), FAKE, 16, None, FAKE, FAKE, 1 << 20, None)
     assert rc == nat.NLOS_EINVAL
 
 
 def test_forward_rejects_bad_buffers(nat):
     L = nat.lib()
     p = _params(nat)
-    assert L.nlos_forward(None, FAKE, 16, None, FAKE, None, 0, None) == nat.NLOS_EINVAL
-    assert L.nlos_forward(C.byref(p), None, 16, None, FAKE, None, 0, None) == nat.NLOS_EINVAL
-    assert L.nlos_forward(C.byref(p), FAKE, 16, None, None, None, 0, None) == nat.NLOS_EINVAL
-    assert L.nlos_forward(C.byref(p), C.c_void_p(0x10004), 16, None, FAKE, None, 0, None) == nat.NLOS_EINVAL
-    assert L.nlos_forward(C.byref(p), FAKE, -1, None, FAKE, None, 0, None) == nat.NLOS_EINVAL
-    assert L.nlos_forward(C.byref(p), FAKE, (1 << 24) + 1, None, FAKE, None, 0, None) == nat.NLOS_EINVAL
+    assert L.nlos_forward(None, FAKE, 16, None, FAKE, FAKE, 1 << 20, None) == nat.NLOS_EINVAL
+    assert L.nlos_forward(C.byref(p), None, 16, None, FAKE, FAKE, 1 << 20, None) == nat.NLOS_EINVAL
+    assert L.nlos_forward(C.byref(p), FAKE, 16, None, None, FAKE, 1 << 20, None) == nat.NLOS_EINVAL
+    assert L.nlos_forward(C.byref(p), C.c_void_p(0x10004), 16, None, FAKE, FAKE, 1 << 20, None) == nat.NLOS_EINVAL
+    assert L.nlos_forward(C.byref(p), FAKE, -1, None, FAKE, FAKE, 1 << 20, None) == nat.NLOS_EINVAL
+    assert L.nlos_forward(C.byref(p), FAKE, (1 << 24) + 1, None, FAKE, FAKE, 1 << 20, None) == nat.NLOS_EINVAL
     bad_grid = _params(nat)
     bad_grid.relay.nx = 0
-    assert L.nlos_forward(C.byref(bad_grid), FAKE, 16, None, FAKE, None, 0, None) == nat.NLOS_EINVAL
+    assert L.nlos_forward(C.byref(bad_grid), FAKE, 16, None, FAKE, FAKE, 1 << 20, None) == nat.NLOS_EINVAL
     half_laser = _params(nat)
     half_laser.laser.nx = 2   # ny = 0: neither confocal nor a valid laser grid
-    assert L.nlos_forward(C.byref(half_laser), FAKE, 16, None, FAKE, None, 0, None) == nat.NLOS_EINVAL
+    assert L.nlos_forward(C.byref(half_laser), FAKE, 16, None, FAKE, FAKE, 1 << 20, None) == nat.NLOS_EINVAL
+
+
+def test_forward_workspace(nat):
+    L = nat.lib()
+    p = _params(nat)
+    need = C.c_size_t(0)
+    assert L.nlos_forward_workspace_bytes(C.byref(p), 5000, C.byref(need)) == 0
+    assert need.value >= 20 * 32         # one 32-byte summary per 256 records (+ planned pairs)
+    assert L.nlos_forward(C.byref(p), FAKE, 5000, None, FAKE, FAKE, need.value - 1, None) == nat.NLOS_ENOSPC
+    assert L.nlos_forward(C.byref(p), FAKE, 5000, None, FAKE, None, need.value, None) == nat.NLOS_EINVAL
+    assert L.nlos_forward(C.byref(p), FAKE, 5000, None, FAKE, C.c_void_p(0x10008), need.value,
+                          None) == nat.NLOS_EINVAL   # misaligned workspace
 
 
 def test_patches_checks(nat):
@@ -134,7 +146,7 @@ def _gpu_present():
 @pytest.mark.skipif(_gpu_present(), reason="checks the no-device path; a GPU is present")
 def test_no_device_is_reported(nat):
     p = _params(nat)
-    assert nat.lib().nlos_forward(C.byref(p), FAKE, 16, None, FAKE, None, 0, None) == nat.NLOS_ENODEV
+    assert nat.lib().nlos_forward(C.byref(p), FAKE, 16, None, FAKE, FAKE, 1 << 20, None) == nat.NLOS_ENODEV
 
 
 def test_python_layer_rejects_cpu_tensors(nat):
