@@ -171,9 +171,12 @@ int make_plan(const nlos_params* p, int32_t n_patches, int R, nlos::Plan* plan)
     const int64_t L = conf ? 1 : (int64_t)p->laser.nx * p->laser.ny;
     int q_cap = kQueueDefault;
 
-    // u64 bins per histogram row; the flush reuses the area as float rows
-    // padded with R zeros on both sides, so 2 * stride >= tl + 2R
-    auto stride_of = [R](int tl) { return std::max((tl + 1) & ~1, ((tl + 2 * R + 1) / 2 + 1) & ~1); };
+    // u64 bins per histogram row (at least tl),
+    // and reused by the flush as float rows padded with PAD = RM + 8 zeros on
+    // both sides (RM = R rounded up to 4, 8, 16), so 2 * stride >= tl + 2 PAD
+    const int RM = R <= 4 ? 4 : (R <= 8 ? 8 : (R <= 16 ? 16 : R));
+    const int PAD = RM + 8;
+    auto stride_of = [PAD](int tl) { return std::max((tl + 1) & ~1, ((tl + 2 * PAD + 1) / 2 + 1) & ~1); };
     auto units_of = [&](const Cand& c) {
         return ((L + c.tl - 1) / c.tl) * (int64_t)((p->relay.nx + c.tx - 1) / c.tx) *
                (int64_t)((p->relay.ny + c.ty - 1) / c.ty);

@@ -349,32 +349,77 @@ __device__ __forceinline__ void pick_units(const FwdArgs& a, int grp, int* u)
     u[1] = partner != grp ? partner : -1;
 }
 
-// Flush: histograms (fixed point in LDS) -> float rows in LDS -> jitter ->
-// output.  Rows are converted in one pass through registers (at most
-// 160 KB / 8 bytes / 1024 threads = 20 values per thread), the taps are staged
-// in LDS (the guard queue is free by then), and each lane produces 4
-// consecutive outputs with a sliding window of 4 values.
+// Jitter of one row segment: each lane produces V consecutive outputs from a
+// register window of V + 2 RM values (V odd, so lanes read LDS words V apart
+// without bank conflicts); taps zero-padded to radius RM.
+template <int RM>
+__device__ __forceinline__ void jitter_rows(const FwdArgs& a, const Lds& L, const float* F, const float* gp, int NS,
+                                            int P, int PAD, int hb, int t0w, int t1w)
+{
+    constexpr int V = 5;
+    constexpr int K = 2 * RM + 1;
+    float g[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) g[k] = gp[k];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
+    const int nt = t1w - t0w;
+    const int seg = 64 * V;
+    const int nseg = (nt + seg - 1) / seg;
+    for (int sj = wave; sj < NS * nseg; sj += n_waves) {
+        const int j = sj / nseg, sidx = sj - j * nseg;
+        const long long row = L.row[j];
+        if (row < 0) continue;
+        const int t0 = t0w + sidx * seg + lane * V;
+        if (t0 >= t1w) continue;
+        // H[x] = F[j P + PAD + x - hb]; window w[q] = H[t0 - RM + q]
+        const float* h = F + (size_t)j * P + PAD + (t0 - hb) - RM;
+        float w[V + 2 * RM];
+#pragma unroll
+        for (int q = 0; q < V + 2 * RM; ++q) w[q] = h[q];
+        const float gg = L.gg[j];
+        float* out = a.out + (size_t)row * (size_t)a.T + t0;
+#pragma unroll
+        for (int m = 0; m < V; ++m) {
+            // out[t0 + m] = sum_k gp[k] H[t0 + m + RM - k]
+            float acc = 0.f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc = fmaf(g[k], w[m + 2 * RM - k], acc);
+            if (t0 + m < t1w) {
+                if (a.atomic_out)
+                    unsafeAtomicAdd(out + m, acc * gg);
+                else
+                    out[m] = acc * gg;
+            }
+        }
+    }
+}
+
+// Flush: histograms (fixed point in LDS) -> float rows (zero-padded by PAD on
+// both sides, in place) -> Gaussian jitter -> output.  Values are moved
+// through registers (at most 160 KB / 8 bytes / 1024 threads = 20 per thread).
 template <int NS>
 __device__ __forceinline__ void flush(const FwdArgs& a, const Lds& L, float s, int hb, int Tl, int t0w, int t1w)
 {
-    // Float rows padded with R zeros on each side: row j is Fp[j * P, (j+1) * P),
-    // P = Tl + 2R, bin x at Fp[j * P + R + x - hb].  The planner sizes the
-    // histogram area so that NS * P floats fit in it.
     constexpr int kMaxPer = 24;
     const int R = a.R;
-    const int P = Tl + 2 * R;
-    const double inv_s = 1.0 / (double)s;
+    const int RM = R <= 4 ? 4 : (R <= 8 ? 8 : (R <= 16 ? 16 : R));
+    const int PAD = RM + 8;
+    const int P = Tl + 2 * PAD;
+    const float inv_s = 1.0f / s;
     float* F = reinterpret_cast<float*>(L.hist);
-    float* taps = reinterpret_cast<float*>(L.qidx);
-    const int total = NS * Tl;
-    // (row, bin) of flattened index tid + k * blockDim, stepped without divisions
+    float* gp = reinterpret_cast<float*>(L.qidx);   // padded taps [2 RM + 1]
     const int sj = (int)blockDim.x / Tl, st = (int)blockDim.x % Tl;
     float v[kMaxPer];
     {
         int j = (int)threadIdx.x / Tl, t = (int)threadIdx.x % Tl;
 #pragma unroll
         for (int k = 0; k < kMaxPer; ++k) {
-            if (j < NS) v[k] = (float)((double)L.hist[(size_t)j * a.stride + t] * inv_s);
+            if (j < NS) {
+                // exact enough: the sum is < 2^56 and only fp32 precision is kept
+                const u64 x = L.hist[(size_t)j * a.stride + t];
+                const float hi = (float)(uint32_t)(x >> 32), lo = (float)(uint32_t)x;
+                v[k] = fmaf(hi, 4294967296.0f, lo) * inv_s;
+            }
             j += sj;
             t += st;
             if (t >= Tl) {
@@ -388,7 +433,7 @@ __device__ __forceinline__ void flush(const FwdArgs& a, const Lds& L, float s, i
         int j = (int)threadIdx.x / Tl, t = (int)threadIdx.x % Tl;
 #pragma unroll
         for (int k = 0; k < kMaxPer; ++k) {
-            if (j < NS) F[(size_t)j * P + R + t] = v[k];
+            if (j < NS) F[(size_t)j * P + PAD + t] = v[k];
             j += sj;
             t += st;
             if (t >= Tl) {
@@ -397,43 +442,45 @@ __device__ __forceinline__ void flush(const FwdArgs& a, const Lds& L, float s, i
             }
         }
     }
-    for (int i = threadIdx.x; i < NS * 2 * R; i += blockDim.x) {
-        const int j = i / (2 * R), e = i - j * 2 * R;
-        F[(size_t)j * P + (e < R ? e : Tl + e)] = 0.f;
+    for (int i = threadIdx.x; i < NS * 2 * PAD; i += blockDim.x) {
+        const int j = i / (2 * PAD), e = i - j * 2 * PAD;
+        F[(size_t)j * P + (e < PAD ? e : Tl + e)] = 0.f;
     }
-    for (int i = threadIdx.x; i < 2 * R + 1; i += blockDim.x) taps[i] = a.taps[i];
+    for (int k = threadIdx.x; k < 2 * RM + 1; k += blockDim.x) {
+        const int i = k - (RM - R);
+        gp[k] = (i >= 0 && i <= 2 * R) ? a.taps[i] : 0.f;
+    }
     __syncthreads();
-    (void)total;
-
-    const int nt = t1w - t0w;
-    const int sj2 = (int)blockDim.x / nt, st2 = (int)blockDim.x % nt;
-    int j = (int)threadIdx.x / nt, tt = (int)threadIdx.x % nt;
-    for (; j < NS; j += sj2, tt += st2) {
-        if (tt >= nt) {
-            tt -= nt;
-            ++j;
-            if (j >= NS) break;
+    if (RM == 4) {
+        jitter_rows<4>(a, L, F, gp, NS, P, PAD, hb, t0w, t1w);
+    } else if (RM == 8) {
+        jitter_rows<8>(a, L, F, gp, NS, P, PAD, hb, t0w, t1w);
+    } else if (RM == 16) {
+        jitter_rows<16>(a, L, F, gp, NS, P, PAD, hb, t0w, t1w);
+    } else {
+        // wide kernels: one output per lane, generic tap loop
+        const int nt = t1w - t0w;
+        const int sj2 = (int)blockDim.x / nt, st2 = (int)blockDim.x % nt;
+        int j = (int)threadIdx.x / nt, tt = (int)threadIdx.x % nt;
+        for (; j < NS; j += sj2, tt += st2) {
+            if (tt >= nt) {
+                tt -= nt;
+                ++j;
+                if (j >= NS) break;
+            }
+            const long long row = L.row[j];
+            if (row < 0) continue;
+            const int t = t0w + tt;
+            const float* h = F + (size_t)j * P + PAD + (t - hb) + R;   // h[-i] = H[t + R - i]
+            float acc = 0.f;
+            for (int i = 0; i <= 2 * R; ++i) acc = fmaf(gp[i], h[-i], acc);
+            acc *= L.gg[j];
+            float* out = a.out + (size_t)row * (size_t)a.T + t;
+            if (a.atomic_out)
+                unsafeAtomicAdd(out, acc);
+            else
+                *out = acc;
         }
-        const long long row = L.row[j];
-        if (row < 0) continue;
-        const int t = t0w + tt;
-        // out[t] = gg * sum_i taps[i] * H[t + R - i]; H[x] = Fp[j P + R + x - hb]
-        const float* h = F + (size_t)j * P + (t - hb) + 2 * R;   // h[-i] = H[t + R - i]
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-        int i = 0;
-        for (; i + 3 <= 2 * R; i += 4) {
-            a0 = fmaf(taps[i], h[-i], a0);
-            a1 = fmaf(taps[i + 1], h[-i - 1], a1);
-            a2 = fmaf(taps[i + 2], h[-i - 2], a2);
-            a3 = fmaf(taps[i + 3], h[-i - 3], a3);
-        }
-        for (; i <= 2 * R; ++i) a0 = fmaf(taps[i], h[-i], a0);
-        const float acc = ((a0 + a1) + (a2 + a3)) * L.gg[j];
-        float* out = a.out + (size_t)row * (size_t)a.T + t;
-        if (a.atomic_out)
-            unsafeAtomicAdd(out, acc);
-        else
-            *out = acc;
     }
 }
 
