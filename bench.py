@@ -141,7 +141,7 @@ def main():
                        "p99": round(float(np.percentile(step_ms, 99)), 5)},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                     "traffic": None, "kernel": "k_confocal" if sc.laser is None else "k_nonconfocal",
+                     "traffic": None, "kernel": "nlos_forward (k_chunk_stats + k_forward)",
                      "kernel_ms": round(kern_avg, 5), "flops_per_pair": F},
         "cpu_baseline": cpu,
     }
