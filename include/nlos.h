@@ -149,8 +149,8 @@ int nlos_patches_from_depth(const nlos_grid* g, const float* depth, const float*
                             int32_t* n_active, void* ws, size_t ws_bytes, void* stream);
 
 /* Bytes of workspace nlos_forward needs (written to *bytes, host pointer):
- * 32 bytes per block of 1024 records (summaries used to balance the work and
- * bound the pair weights). */
+ * 32 bytes per block of 256 records (summaries used to cull, balance the work
+ * and bound the pair weights), rounded up to 256. */
 int nlos_forward_workspace_bytes(const nlos_params* p, int32_t n_patches, size_t* bytes);
 
 /*
@@ -172,6 +172,65 @@ int nlos_forward_workspace_bytes(const nlos_params* p, int32_t n_patches, size_t
  */
 int nlos_forward(const nlos_params* p, const float* patches, int32_t n_patches,
                  const int32_t* n_active, float* out, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Batched calls: many independent scenes (uneven sizes, time windows, bin
+ * widths, jitter) in one launch per kernel phase, as a serving loop issues
+ * them (Algorithm 1 runs the forward model once per frame of a sequence).
+ * Each request computes exactly what the single call computes for it.
+ *
+ * The library writes a small table (per-request kernel arguments and the
+ * work lists) into host memory and copies it to the start of the device
+ * workspace on `stream` before the kernels:
+ *   table, table_bytes  host buffer of at least *table_bytes of the _sizes
+ *           call, owned by the caller; pinned memory (hipHostMalloc) keeps
+ *           the copy asynchronous.  It must stay untouched until the stream
+ *           has passed the call.  NULL: the library uses a per-thread pageable
+ *           buffer, and the copy may then block the host until the stream
+ *           reaches it.
+ *   ws, ws_bytes  device workspace, 16-byte aligned, at least *ws_bytes of
+ *           the _sizes call; calls sharing it must be ordered on one stream.
+ * Requests of one call must not share an output buffer.  n may be 0 (no-op).
+ * A rejected request rejects the whole call before anything is enqueued.
+ */
+typedef struct nlos_depth_request {
+    nlos_grid grid;          /* lateral grid of the maps */
+    const float* depth;      /* device [nx][ny] */
+    const float* albedo;     /* device [nx][ny] or NULL (0.5) */
+    const uint8_t* mask;     /* device [nx][ny] or NULL (all present) */
+    uint32_t flags;          /* NLOS_F_COSINES */
+    float* patches;          /* device [nx*ny][8] records, 16-byte aligned */
+    int32_t* n_active;       /* device int32[1] */
+} nlos_depth_request;
+
+typedef struct nlos_request {
+    nlos_params params;
+    const float* patches;    /* device [n_patches][8] records */
+    int32_t n_patches;       /* capacity of patches */
+    const int32_t* n_active; /* device int32[1] or NULL (use n_patches) */
+    float* out;              /* device output, layout as for nlos_forward */
+} nlos_request;
+
+/* Table and workspace sizes of nlos_patches_batched (host pointers). */
+int nlos_patches_batched_sizes(const nlos_depth_request* reqs, int32_t n, size_t* table_bytes,
+                               size_t* ws_bytes);
+
+/* nlos_patches_from_depth for every request: three launches in all. */
+int nlos_patches_batched(const nlos_depth_request* reqs, int32_t n, void* table, size_t table_bytes,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* Table and workspace sizes of nlos_forward_batched (host pointers). */
+int nlos_forward_batched_sizes(const nlos_request* reqs, int32_t n, size_t* table_bytes, size_t* ws_bytes);
+
+/*
+ * nlos_forward for every request: one launch of record summaries, one of
+ * output zeroing when a request needs it, and one pair-kernel launch per
+ * kernel variant present (tile shape, confocal or not, cosines, time
+ * windows).  Each request gets a share of the GPU's workgroups in proportion
+ * to its pairs; within a launch the workgroups with the most work start first.
+ */
+int nlos_forward_batched(const nlos_request* reqs, int32_t n, void* table, size_t table_bytes, void* ws,
+                         size_t ws_bytes, void* stream);
 
 /*
  * Test hook: the bin index of every (histogram, record) pair, decided by the

@@ -19,10 +19,12 @@ from typing import Optional
 import torch
 
 from ._native import (NLOS_F_COSINES, NLOS_MAX_BINS, NLOS_MAX_PATCHES, NLOS_MAX_RADIUS,  # noqa: F401
-                      NLOS_RECORD_FLOATS, Grid, NlosError, Params, check, lib, strerror)
+                      NLOS_RECORD_FLOATS, DepthRequest, Grid, NlosError, Params, Request, check, lib,
+                      strerror)
 
 __all__ = ["Grid", "Params", "NlosError", "make_grid", "make_params", "params_of",
-           "patches_from_depth", "forward", "debug_bins", "out_shape", "n_histograms"]
+           "patches_from_depth", "forward", "debug_bins", "out_shape", "n_histograms",
+           "Batcher", "patches_batched", "forward_batched"]
 
 
 def make_grid(g) -> Grid:
@@ -144,3 +146,116 @@ def debug_bins(params: Params, patches: torch.Tensor, n_active: Optional[torch.T
     check(lib().nlos_debug_bins(C.byref(params), _ptr(patches), P, _ptr(n_active), _ptr(bins), _ptr(uf),
                                 _ptr(ue), _stream(stream)), "nlos_debug_bins")
     return (bins, uf, ue) if want_u else bins
+
+
+class Batcher:
+    """Reusable buffers of the batched calls: a device workspace that grows
+    as needed and two pinned host tables used in turn (the table of a call
+    is reused only after an event recorded behind that call has completed),
+    so a loop of batched calls never blocks on its table uploads."""
+
+    def __init__(self, device="cuda"):
+        self.device = torch.device(device)
+        self._ws = {}
+        self._tables = [None, None]
+        self._events = [None, None]
+        self._turn = 0
+
+    def workspace(self, key: str, nbytes: int) -> torch.Tensor:
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        return ws
+
+    def table(self, nbytes: int, stream) -> torch.Tensor:
+        i = self._turn
+        self._turn ^= 1
+        if self._events[i] is not None:
+            self._events[i].synchronize()
+        t = self._tables[i]
+        if t is None or t.numel() < nbytes:
+            t = torch.empty(max(nbytes, 4096), dtype=torch.uint8, pin_memory=True)
+            self._tables[i] = t
+        self._last = i
+        return t
+
+    def mark(self, stream) -> None:
+        ev = torch.cuda.Event()
+        ev.record(stream)
+        self._events[self._last] = ev
+
+
+def patches_batched(maps, batcher: Optional[Batcher] = None, stream=None):
+    """Batched patches_from_depth.  ``maps`` is a list of dicts with keys
+    depth, grid and optionally albedo, mask, cosines, out, n_active.
+    Returns [(records, n_active)] in the same order."""
+    n = len(maps)
+    reqs = (DepthRequest * max(n, 1))()
+    res = []
+    for i, m in enumerate(maps):
+        g = make_grid(m["grid"])
+        depth = _dev(m["depth"], torch.float32, "depth")
+        albedo = _dev(m.get("albedo"), torch.float32, "albedo")
+        mask = _dev(m.get("mask"), torch.uint8, "mask")
+        npx = g.nx * g.ny
+        for t, name in ((depth, "depth"), (albedo, "albedo"), (mask, "mask")):
+            if t is not None and t.numel() != npx:
+                raise ValueError(f"{name} must have {g.nx}x{g.ny} elements")
+        out = m.get("out")
+        if out is None:
+            out = torch.empty((npx, NLOS_RECORD_FLOATS), dtype=torch.float32, device=depth.device)
+        na = m.get("n_active")
+        if na is None:
+            na = torch.empty(1, dtype=torch.int32, device=depth.device)
+        reqs[i] = DepthRequest(g, depth.data_ptr(), None if albedo is None else albedo.data_ptr(),
+                               None if mask is None else mask.data_ptr(),
+                               NLOS_F_COSINES if m.get("cosines", True) else 0, out.data_ptr(), na.data_ptr())
+        res.append((out, na))
+    if n == 0:
+        return res
+    return _run_batched("patches", reqs, n, res, batcher, stream,
+                        lib().nlos_patches_batched_sizes, lib().nlos_patches_batched)
+
+
+def forward_batched(requests, batcher: Optional[Batcher] = None, stream=None):
+    """Batched forward.  ``requests`` is a list of (params, patches, n_active,
+    out) tuples (n_active and out may be None).  Returns the outputs."""
+    n = len(requests)
+    reqs = (Request * max(n, 1))()
+    outs = []
+    for i, (params, patches, n_active, out) in enumerate(requests):
+        _dev(patches, torch.float32, "patches")
+        _dev(n_active, torch.int32, "n_active")
+        if patches.dim() != 2 or patches.shape[1] != NLOS_RECORD_FLOATS:
+            raise ValueError("patches must be [n, 8]")
+        if out is None:
+            out = torch.empty(out_shape(params), dtype=torch.float32, device=patches.device)
+        _dev(out, torch.float32, "out")
+        if out.numel() != n_histograms(params) * params.n_bins:
+            raise ValueError("out has the wrong size")
+        reqs[i] = Request(params, patches.data_ptr(), patches.shape[0],
+                          None if n_active is None else n_active.data_ptr(), out.data_ptr())
+        outs.append(out)
+    if n == 0:
+        return outs
+    return _run_batched("forward", reqs, n, outs, batcher, stream,
+                        lib().nlos_forward_batched_sizes, lib().nlos_forward_batched)
+
+
+def _run_batched(key, reqs, n, result, batcher, stream, sizes_fn, run_fn):
+    tb, wb = C.c_size_t(0), C.c_size_t(0)
+    check(sizes_fn(reqs, n, C.byref(tb), C.byref(wb)), f"{key} batched sizes")
+    st = torch.cuda.current_stream() if stream is None else stream
+    if batcher is None:
+        ws = torch.empty(max(wb.value, 256), dtype=torch.uint8, device="cuda")
+        table = None
+        tptr, tlen = None, 0
+    else:
+        ws = batcher.workspace(key, wb.value)
+        table = batcher.table(tb.value, st)
+        tptr, tlen = C.c_void_p(table.data_ptr()), table.numel()
+    check(run_fn(reqs, n, tptr, tlen, _ptr(ws), ws.numel(), C.c_void_p(st.cuda_stream)), f"{key} batched")
+    if batcher is not None:
+        batcher.mark(st)
+    return result

@@ -36,6 +36,16 @@ class Params(C.Structure):
                 ("fwhm_ps", C.c_double)]
 
 
+class DepthRequest(C.Structure):
+    _fields_ = [("grid", Grid), ("depth", C.c_void_p), ("albedo", C.c_void_p), ("mask", C.c_void_p),
+                ("flags", C.c_uint32), ("patches", C.c_void_p), ("n_active", C.c_void_p)]
+
+
+class Request(C.Structure):
+    _fields_ = [("params", Params), ("patches", C.c_void_p), ("n_patches", C.c_int32),
+                ("n_active", C.c_void_p), ("out", C.c_void_p)]
+
+
 class NlosError(RuntimeError):
     def __init__(self, code: int, where: str, hip: int = 0):
         self.code = code
@@ -60,6 +70,14 @@ SIGNATURES = [
     ("nlos_forward", C.c_int,
      [C.POINTER(Params), C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
       C.c_void_p]),
+    ("nlos_patches_batched_sizes", C.c_int,
+     [C.POINTER(DepthRequest), C.c_int32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    ("nlos_patches_batched", C.c_int,
+     [C.POINTER(DepthRequest), C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("nlos_forward_batched_sizes", C.c_int,
+     [C.POINTER(Request), C.c_int32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    ("nlos_forward_batched", C.c_int,
+     [C.POINTER(Request), C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p]),
     ("nlos_debug_bins", C.c_int,
      [C.POINTER(Params), C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
       C.c_void_p]),

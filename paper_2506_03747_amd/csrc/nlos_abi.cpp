@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "nlos.h"
 #include "nlos_internal.h"
@@ -160,7 +161,7 @@ int64_t stats_count(int32_t n_patches) { return ((int64_t)n_patches + nlos::kSta
 // over a window of bins (time windows).  Patches are split over workgroups
 // when there are fewer workgroups than CUs.  Units are ordered by estimated
 // work inside the kernel when their count keeps that cheap.
-int make_plan(const nlos_params* p, int32_t n_patches, int R, nlos::Plan* plan)
+int make_plan(const nlos_params* p, int32_t n_patches, int R, int64_t target, nlos::Plan* plan)
 {
     const bool conf = is_confocal(p);
     static const Cand conf_c[] = {{1, 4, 4}, {1, 4, 2}, {1, 2, 2}, {1, 2, 1}, {1, 1, 1}};
@@ -186,7 +187,7 @@ int make_plan(const nlos_params* p, int32_t n_patches, int R, nlos::Plan* plan)
         const int slots = 2 * cands[i].tl * cands[i].tx * cands[i].ty;
         if (nlos::lds_bytes_for(slots, stride_of(T), q_cap) > kLdsMax) continue;
         if (largest < 0) largest = i;
-        if ((units_of(cands[i]) + 1) / 2 >= kTargetBlocks) {
+        if ((units_of(cands[i]) + 1) / 2 >= target) {
             chosen = i;
             break;
         }
@@ -227,8 +228,8 @@ int make_plan(const nlos_params* p, int32_t n_patches, int R, nlos::Plan* plan)
     plan->groups = groups;
     const int64_t tiles = groups * n_tw;
     int64_t split = 1;
-    if (tiles < kTargetBlocks) {
-        split = (kTargetBlocks + tiles - 1) / tiles;
+    if (tiles < target) {
+        split = (target + tiles - 1) / tiles;
         const int64_t by_patches = std::max<int64_t>(1, n_patches / nlos::kBlock);
         split = std::min(split, by_patches);
     }
@@ -244,17 +245,241 @@ size_t stats_bytes(int32_t n_patches)
     return ((size_t)stats_count(n_patches) * sizeof(nlos::ChunkStat) + 255) & ~(size_t)255;
 }
 
-int forward_workspace(const nlos_params* p, int32_t n_patches, size_t* bytes, nlos::Plan* plan_out)
+int forward_workspace(const nlos_params* p, int32_t n_patches, size_t* bytes, nlos::Plan* plan_out,
+                      int64_t target = kTargetBlocks)
 {
     float taps[nlos::kMaxTaps];
     int32_t R = 0;
     int rc = jitter_taps(p->fwhm_ps, p->bin_ps, taps, &R);
     if (rc != NLOS_OK) return rc;
     nlos::Plan plan;
-    rc = make_plan(p, n_patches, R, &plan);
+    rc = make_plan(p, n_patches, R, target, &plan);
     if (rc != NLOS_OK) return rc;
     *bytes = stats_bytes(n_patches);
     if (plan_out) *plan_out = plan;
+    return NLOS_OK;
+}
+
+// Checks of one forward request, its plan (for `target` workgroups) and its
+// kernel arguments (all but the summaries pointer); *ws_need = workspace.
+int setup_forward(const nlos_params* p, const float* patches, int32_t n_patches, const int32_t* n_active,
+                  float* out, int64_t target, nlos::FwdArgs* a, nlos::Plan* plan, size_t* ws_need)
+{
+    int rc = params_ok(p);
+    if (rc != NLOS_OK) return rc;
+    if (n_patches < 0 || n_patches > NLOS_MAX_PATCHES || !out) return NLOS_EINVAL;
+    if (n_patches > 0 && !patches) return NLOS_EINVAL;
+    if ((patches && !aligned(patches, 16)) || !aligned(out, 16) || (n_active && !aligned(n_active, 4)))
+        return NLOS_EINVAL;
+    rc = forward_workspace(p, n_patches, ws_need, plan, target);
+    if (rc != NLOS_OK) return rc;
+    rc = fill_args(p, patches, n_patches, n_active, out, a);
+    if (rc != NLOS_OK) return rc;
+    const bool conf = is_confocal(p);
+    a->out_len = n_hist(p) * (int64_t)p->n_bins;
+    a->tiles_l = conf ? 1 : (p->laser.nx * p->laser.ny + plan->tl - 1) / plan->tl;
+    a->tiles_x = (p->relay.nx + plan->tx - 1) / plan->tx;
+    a->tiles_y = (p->relay.ny + plan->ty - 1) / plan->ty;
+    a->n_units = a->tiles_l * a->tiles_x * a->tiles_y;
+    a->pair = plan->pair;
+    a->plan = plan->plan;
+    a->stats = nullptr;
+    a->n_stats = (int32_t)stats_count(n_patches);
+    a->n_split = plan->n_split;
+    a->tw = plan->tw;
+    a->n_tw = plan->n_tw;
+    a->stride = plan->stride;
+    a->q_cap = plan->q_cap;
+    a->atomic_out = plan->n_split > 1 ? 1 : 0;
+    return NLOS_OK;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Host table of a batched forward call, copied as one block to the start of
+// the device workspace: per-request kernel arguments, then the work lists
+// (records summaries, output zeroing, one list per kernel variant).
+struct FwdBatch {
+    struct Group {
+        int tl, tx, ty;
+        bool conf, cos, pair;
+        std::vector<int32_t> req;
+        std::vector<int64_t> first;
+        int64_t n_blocks = 0;
+        size_t lds = 0;
+        size_t req_off = 0, first_off = 0;
+    };
+    std::vector<nlos::FwdArgs> args;
+    std::vector<nlos::Plan> plans;
+    std::vector<Group> groups;
+    std::vector<int32_t> stat_req, fill_req;
+    std::vector<int64_t> stat_first;
+    int64_t stat_blocks = 0;
+    size_t tab_off = 0, stat_req_off = 0, stat_first_off = 0, fill_req_off = 0;
+    size_t table_bytes = 0, ws_bytes = 0;
+    std::vector<size_t> stats_off;
+};
+
+// Plan every request (each gets a share of the GPU's workgroups in proportion
+// to its pairs), group them by kernel variant and order each group by
+// decreasing work per workgroup, so the longest workgroups start first.
+int plan_batch(const nlos_request* reqs, int32_t n, FwdBatch* b)
+{
+    if (n < 0 || (n > 0 && !reqs)) return NLOS_EINVAL;
+    b->args.resize(n);
+    b->plans.resize(n);
+    b->stats_off.resize(n);
+    double total = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if (params_ok(&reqs[i].params) != NLOS_OK) return NLOS_EINVAL;
+        total += (double)n_hist(&reqs[i].params) * (double)std::max(reqs[i].n_patches, 1);
+    }
+    std::vector<double> work(n);
+    for (int i = 0; i < n; ++i) {
+        const nlos_request& r = reqs[i];
+        const double pairs = (double)n_hist(&r.params) * (double)std::max(r.n_patches, 1);
+        const int64_t target = std::max<int64_t>(1, (int64_t)std::ceil(kTargetBlocks * pairs / total));
+        size_t need = 0;
+        const int rc = setup_forward(&r.params, r.patches, r.n_patches, r.n_active, r.out, target, &b->args[i],
+                                     &b->plans[i], &need);
+        if (rc != NLOS_OK) return rc;
+        work[i] = pairs / (double)std::max<int64_t>(1, b->plans[i].n_blocks);
+    }
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+    for (int i : order) {
+        const nlos::Plan& pl = b->plans[i];
+        const bool conf = is_confocal(&reqs[i].params);
+        const bool cos = b->args[i].cosines != 0;
+        FwdBatch::Group* g = nullptr;
+        for (auto& h : b->groups)
+            if (h.tl == pl.tl && h.tx == pl.tx && h.ty == pl.ty && h.conf == conf && h.cos == cos &&
+                h.pair == (pl.pair != 0))
+                g = &h;
+        if (!g) {
+            b->groups.emplace_back();
+            g = &b->groups.back();
+            g->tl = pl.tl;
+            g->tx = pl.tx;
+            g->ty = pl.ty;
+            g->conf = conf;
+            g->cos = cos;
+            g->pair = pl.pair != 0;
+        }
+        if (pl.n_blocks > 0) {
+            g->req.push_back(i);
+            g->first.push_back(g->n_blocks);
+            g->n_blocks += pl.n_blocks;
+            g->lds = std::max(g->lds, pl.lds_bytes);
+        }
+        if (b->args[i].n_stats > 0) {
+            b->stat_req.push_back(i);
+            b->stat_first.push_back(b->stat_blocks);
+            b->stat_blocks += b->args[i].n_stats;
+        }
+        if (b->args[i].atomic_out) b->fill_req.push_back(i);
+    }
+    // table layout
+    size_t off = 0;
+    b->tab_off = off;
+    off = align_up(off + sizeof(nlos::FwdArgs) * (size_t)n, 16);
+    b->stat_req_off = off;
+    off = align_up(off + 4 * b->stat_req.size(), 16);
+    b->stat_first_off = off;
+    off = align_up(off + 8 * b->stat_first.size(), 16);
+    b->fill_req_off = off;
+    off = align_up(off + 4 * b->fill_req.size(), 16);
+    for (auto& g : b->groups) {
+        g.req_off = off;
+        off = align_up(off + 4 * g.req.size(), 16);
+        g.first_off = off;
+        off = align_up(off + 8 * g.first.size(), 16);
+    }
+    b->table_bytes = align_up(off, 256);
+    off = b->table_bytes;
+    for (int i = 0; i < n; ++i) {
+        b->stats_off[i] = off;
+        off = align_up(off + sizeof(nlos::ChunkStat) * (size_t)b->args[i].n_stats, 256);
+    }
+    b->ws_bytes = off;
+    return NLOS_OK;
+}
+
+template <typename T>
+void put(unsigned char* base, size_t off, const std::vector<T>& v)
+{
+    if (!v.empty()) std::memcpy(base + off, v.data(), sizeof(T) * v.size());
+}
+
+thread_local std::vector<unsigned char> g_table;
+
+// Copy `bytes` of host table to the device workspace on `st`; the table is
+// the caller's buffer when given, else this thread's pageable buffer.
+hipError_t upload_table(void* ws, const unsigned char* table, size_t bytes, hipStream_t st)
+{
+    return hipMemcpyAsync(ws, table, bytes, hipMemcpyHostToDevice, st);
+}
+
+// Geometry batch: per-map arguments and the enumeration-block prefix.
+struct GeomBatch {
+    std::vector<nlos::GeomArgs> args;
+    std::vector<int64_t> first;
+    int64_t n_blocks = 0;
+    size_t tab_off = 0, first_off = 0, table_bytes = 0, ws_bytes = 0;
+    std::vector<size_t> counts_off;
+};
+
+int geom_args(const nlos_grid* g, const float* depth, const float* albedo, const uint8_t* mask, uint32_t flags,
+              float* patches, int32_t* n_active, nlos::GeomArgs* a)
+{
+    if (!grid_ok(g) || !depth || !patches || !n_active) return NLOS_EINVAL;
+    if ((int64_t)g->nx * g->ny > NLOS_MAX_PATCHES) return NLOS_EINVAL;
+    if ((flags & ~NLOS_F_COSINES) != 0) return NLOS_EINVAL;
+    if (!aligned(patches, 16) || !aligned(depth, 4) || (albedo && !aligned(albedo, 4)) || !aligned(n_active, 4))
+        return NLOS_EINVAL;
+    std::memset(a, 0, sizeof(*a));
+    a->depth = depth;
+    a->albedo = albedo;
+    a->mask = mask;
+    a->patches = reinterpret_cast<float4*>(patches);
+    a->n_active = n_active;
+    a->ax = axis(g->half_x, g->cx, g->nx);
+    a->ay = axis(g->half_y, g->cy, g->ny);
+    a->hx = (float)a->ax.step;
+    a->hy = (float)a->ay.step;
+    a->bx = (g->nx + nlos::kBlockPx - 1) / nlos::kBlockPx;
+    a->by = (g->ny + nlos::kBlockPx - 1) / nlos::kBlockPx;
+    a->n_enum = (int64_t)nlos::kBlockPx * nlos::kBlockPx * a->bx * a->by;
+    a->n_blocks = (int32_t)((a->n_enum + nlos::kGeomBlock - 1) / nlos::kGeomBlock);
+    a->cosines = (flags & NLOS_F_COSINES) ? 1 : 0;
+    return NLOS_OK;
+}
+
+int plan_geom_batch(const nlos_depth_request* reqs, int32_t n, GeomBatch* b)
+{
+    if (n < 0 || (n > 0 && !reqs)) return NLOS_EINVAL;
+    b->args.resize(n);
+    b->first.resize(n);
+    b->counts_off.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const nlos_depth_request& r = reqs[i];
+        const int rc = geom_args(&r.grid, r.depth, r.albedo, r.mask, r.flags, r.patches, r.n_active, &b->args[i]);
+        if (rc != NLOS_OK) return rc;
+        b->first[i] = b->n_blocks;
+        b->n_blocks += b->args[i].n_blocks;
+    }
+    size_t off = 0;
+    b->tab_off = 0;
+    off = align_up(sizeof(nlos::GeomArgs) * (size_t)n, 16);
+    b->first_off = off;
+    off = align_up(off + 8 * (size_t)n, 256);
+    b->table_bytes = off;
+    for (int i = 0; i < n; ++i) {
+        b->counts_off[i] = off;
+        off = align_up(off + 8 * (size_t)b->args[i].n_blocks, 256);
+    }
+    b->ws_bytes = off;
     return NLOS_OK;
 }
 
@@ -293,37 +518,63 @@ int nlos_patches_from_depth(const nlos_grid* g, const float* depth, const float*
                             const uint8_t* mask, uint32_t flags, float* patches, int32_t* n_active,
                             void* ws, size_t ws_bytes, void* stream)
 {
-    if (!grid_ok(g) || !depth || !patches || !n_active || !ws) return NLOS_EINVAL;
-    if ((int64_t)g->nx * g->ny > NLOS_MAX_PATCHES) return NLOS_EINVAL;
-    if ((flags & ~NLOS_F_COSINES) != 0) return NLOS_EINVAL;
-    if (!aligned(patches, 16) || !aligned(depth, 4) || (albedo && !aligned(albedo, 4)) ||
-        !aligned(n_active, 4) || !aligned(ws, 4))
-        return NLOS_EINVAL;
+    nlos::GeomArgs a;
+    const int rc = geom_args(g, depth, albedo, mask, flags, patches, n_active, &a);
+    if (rc != NLOS_OK) return rc;
+    if (!ws || !aligned(ws, 4)) return NLOS_EINVAL;
     size_t need = 0;
     nlos_patches_workspace_bytes(g, &need);
     if (ws_bytes < need) return NLOS_ENOSPC;
     const int dev = device_check();
     if (dev != NLOS_OK) return dev;
-
-    nlos::GeomArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.depth = depth;
-    a.albedo = albedo;
-    a.mask = mask;
-    a.patches = reinterpret_cast<float4*>(patches);
-    a.n_active = n_active;
-    a.ax = axis(g->half_x, g->cx, g->nx);
-    a.ay = axis(g->half_y, g->cy, g->ny);
-    a.hx = (float)a.ax.step;
-    a.hy = (float)a.ay.step;
-    a.bx = (g->nx + nlos::kBlockPx - 1) / nlos::kBlockPx;
-    a.by = (g->ny + nlos::kBlockPx - 1) / nlos::kBlockPx;
-    a.n_enum = (int64_t)nlos::kBlockPx * nlos::kBlockPx * a.bx * a.by;
-    a.n_blocks = (int32_t)((a.n_enum + nlos::kGeomBlock - 1) / nlos::kGeomBlock);
     a.counts = reinterpret_cast<int32_t*>(ws);
     a.offsets = a.counts + a.n_blocks;
-    a.cosines = (flags & NLOS_F_COSINES) ? 1 : 0;
     const hipError_t e = nlos::launch_geometry(a, (hipStream_t)stream);
+    return e == hipSuccess ? NLOS_OK : hip_fail(e);
+}
+
+int nlos_patches_batched_sizes(const nlos_depth_request* reqs, int32_t n, size_t* table_bytes, size_t* ws_bytes)
+{
+    if (!table_bytes || !ws_bytes) return NLOS_EINVAL;
+    GeomBatch b;
+    const int rc = plan_geom_batch(reqs, n, &b);
+    if (rc != NLOS_OK) return rc;
+    *table_bytes = b.table_bytes;
+    *ws_bytes = b.ws_bytes;
+    return NLOS_OK;
+}
+
+int nlos_patches_batched(const nlos_depth_request* reqs, int32_t n, void* table, size_t table_bytes, void* ws,
+                         size_t ws_bytes, void* stream)
+{
+    GeomBatch b;
+    const int rc = plan_geom_batch(reqs, n, &b);
+    if (rc != NLOS_OK) return rc;
+    if (n == 0) return NLOS_OK;
+    if (!ws || !aligned(ws, 16)) return NLOS_EINVAL;
+    if (ws_bytes < b.ws_bytes || (table && table_bytes < b.table_bytes)) return NLOS_ENOSPC;
+    const int dev = device_check();
+    if (dev != NLOS_OK) return dev;
+    unsigned char* wsb = static_cast<unsigned char*>(ws);
+    for (int i = 0; i < n; ++i) {
+        b.args[i].counts = reinterpret_cast<int32_t*>(wsb + b.counts_off[i]);
+        b.args[i].offsets = b.args[i].counts + b.args[i].n_blocks;
+    }
+    unsigned char* host = static_cast<unsigned char*>(table);
+    if (!host) {
+        g_table.resize(b.table_bytes);
+        host = g_table.data();
+    }
+    std::memcpy(host + b.tab_off, b.args.data(), sizeof(nlos::GeomArgs) * (size_t)n);
+    put(host, b.first_off, b.first);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = upload_table(ws, host, b.table_bytes, st);
+    if (e != hipSuccess) return hip_fail(e);
+    nlos::GeomList gl;
+    gl.tab = reinterpret_cast<const nlos::GeomArgs*>(wsb + b.tab_off);
+    gl.first = reinterpret_cast<const int64_t*>(wsb + b.first_off);
+    gl.n = n;
+    e = nlos::launch_geometry_batch(gl, b.n_blocks, st);
     return e == hipSuccess ? NLOS_OK : hip_fail(e);
 }
 
@@ -337,49 +588,92 @@ int nlos_forward_workspace_bytes(const nlos_params* p, int32_t n_patches, size_t
 int nlos_forward(const nlos_params* p, const float* patches, int32_t n_patches, const int32_t* n_active,
                  float* out, void* ws, size_t ws_bytes, void* stream)
 {
-    int rc = params_ok(p);
-    if (rc != NLOS_OK) return rc;
-    if (n_patches < 0 || n_patches > NLOS_MAX_PATCHES || !out) return NLOS_EINVAL;
-    if (n_patches > 0 && !patches) return NLOS_EINVAL;
-    if ((patches && !aligned(patches, 16)) || !aligned(out, 16) || (n_active && !aligned(n_active, 4)) ||
-        (ws && !aligned(ws, 16)))
-        return NLOS_EINVAL;
-    size_t need = 0;
+    nlos::FwdArgs a;
     nlos::Plan plan;
-    rc = forward_workspace(p, n_patches, &need, &plan);
+    size_t need = 0;
+    int rc = setup_forward(p, patches, n_patches, n_active, out, kTargetBlocks, &a, &plan, &need);
     if (rc != NLOS_OK) return rc;
     if (ws_bytes < need) return NLOS_ENOSPC;
     if (need > 0 && !ws) return NLOS_EINVAL;
-    nlos::FwdArgs a;
-    rc = fill_args(p, patches, n_patches, n_active, out, &a);
-    if (rc != NLOS_OK) return rc;
+    if (ws && !aligned(ws, 16)) return NLOS_EINVAL;
     const int dev = device_check();
     if (dev != NLOS_OK) return dev;
-    const bool conf = is_confocal(p);
-    a.tiles_l = conf ? 1 : (p->laser.nx * p->laser.ny + plan.tl - 1) / plan.tl;
-    a.tiles_x = (p->relay.nx + plan.tx - 1) / plan.tx;
-    a.tiles_y = (p->relay.ny + plan.ty - 1) / plan.ty;
-    a.n_units = a.tiles_l * a.tiles_x * a.tiles_y;
-    a.pair = plan.pair;
-    a.plan = plan.plan;
-    a.stats = reinterpret_cast<const nlos::ChunkStat*>(ws);
-    a.n_stats = (int32_t)stats_count(n_patches);
-
-    a.n_split = plan.n_split;
-    a.tw = plan.tw;
-    a.n_tw = plan.n_tw;
-    a.stride = plan.stride;
-    a.q_cap = plan.q_cap;
-    a.atomic_out = plan.n_split > 1 ? 1 : 0;
+    a.stats = reinterpret_cast<nlos::ChunkStat*>(ws);
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = nlos::launch_stats(a, reinterpret_cast<nlos::ChunkStat*>(ws), st);
+    hipError_t e = nlos::launch_stats(a, a.stats, st);
     if (e != hipSuccess) return hip_fail(e);
     if (a.atomic_out) {
-        e = nlos::launch_fill(out, (size_t)n_hist(p) * (size_t)p->n_bins, st);
+        e = nlos::launch_fill(out, (size_t)a.out_len, st);
         if (e != hipSuccess) return hip_fail(e);
     }
-    e = nlos::launch_forward(a, plan, conf, st);
+    e = nlos::launch_forward(a, plan, is_confocal(p), st);
     return e == hipSuccess ? NLOS_OK : hip_fail(e);
+}
+
+int nlos_forward_batched_sizes(const nlos_request* reqs, int32_t n, size_t* table_bytes, size_t* ws_bytes)
+{
+    if (!table_bytes || !ws_bytes) return NLOS_EINVAL;
+    FwdBatch b;
+    const int rc = plan_batch(reqs, n, &b);
+    if (rc != NLOS_OK) return rc;
+    *table_bytes = b.table_bytes;
+    *ws_bytes = b.ws_bytes;
+    return NLOS_OK;
+}
+
+int nlos_forward_batched(const nlos_request* reqs, int32_t n, void* table, size_t table_bytes, void* ws,
+                         size_t ws_bytes, void* stream)
+{
+    FwdBatch b;
+    const int rc = plan_batch(reqs, n, &b);
+    if (rc != NLOS_OK) return rc;
+    if (n == 0) return NLOS_OK;
+    if (!ws || !aligned(ws, 16)) return NLOS_EINVAL;
+    if (ws_bytes < b.ws_bytes || (table && table_bytes < b.table_bytes)) return NLOS_ENOSPC;
+    const int dev = device_check();
+    if (dev != NLOS_OK) return dev;
+    unsigned char* wsb = static_cast<unsigned char*>(ws);
+    for (int i = 0; i < n; ++i) b.args[i].stats = reinterpret_cast<nlos::ChunkStat*>(wsb + b.stats_off[i]);
+    unsigned char* host = static_cast<unsigned char*>(table);
+    if (!host) {
+        g_table.resize(b.table_bytes);
+        host = g_table.data();
+    }
+    std::memcpy(host + b.tab_off, b.args.data(), sizeof(nlos::FwdArgs) * (size_t)n);
+    put(host, b.stat_req_off, b.stat_req);
+    put(host, b.stat_first_off, b.stat_first);
+    put(host, b.fill_req_off, b.fill_req);
+    for (const auto& g : b.groups) {
+        put(host, g.req_off, g.req);
+        put(host, g.first_off, g.first);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = upload_table(ws, host, b.table_bytes, st);
+    if (e != hipSuccess) return hip_fail(e);
+    const nlos::FwdArgs* tab = reinterpret_cast<const nlos::FwdArgs*>(wsb + b.tab_off);
+    nlos::BatchList bl;
+    bl.tab = tab;
+    bl.req = reinterpret_cast<const int32_t*>(wsb + b.stat_req_off);
+    bl.first = reinterpret_cast<const int64_t*>(wsb + b.stat_first_off);
+    bl.n = (int32_t)b.stat_req.size();
+    e = nlos::launch_stats_batch(bl, b.stat_blocks, st);
+    if (e != hipSuccess) return hip_fail(e);
+    if (!b.fill_req.empty()) {
+        bl.req = reinterpret_cast<const int32_t*>(wsb + b.fill_req_off);
+        bl.first = nullptr;
+        bl.n = (int32_t)b.fill_req.size();
+        e = nlos::launch_fill_batch(bl, st);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    for (const auto& g : b.groups) {
+        if (g.req.empty()) continue;
+        bl.req = reinterpret_cast<const int32_t*>(wsb + g.req_off);
+        bl.first = reinterpret_cast<const int64_t*>(wsb + g.first_off);
+        bl.n = (int32_t)g.req.size();
+        e = nlos::launch_forward_batch(bl, g.n_blocks, g.lds, g.tl, g.tx, g.ty, g.conf, g.cos, g.pair, st);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    return NLOS_OK;
 }
 
 int nlos_debug_bins(const nlos_params* p, const float* patches, int32_t n_patches, const int32_t* n_active,

@@ -145,11 +145,28 @@ __device__ __forceinline__ float block_max(float v, float* red)
     return m;
 }
 
+// Device buffers named by the arguments are global memory; saying so keeps
+// the accesses global (not flat) when the pointer itself was loaded from a
+// table, so they do not share the LDS wait counter.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p)
+{
+    return (__attribute__((address_space(1))) T*)p;
+}
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float4 load4(const float4* p, size_t i)
+{
+    const v4f v = gmem(reinterpret_cast<const v4f*>(p))[i];
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
 __device__ __forceinline__ int active_count(const FwdArgs& a)
 {
     int n = a.n_cap;
     if (a.n_active) {
-        n = *a.n_active;
+        n = *gmem(a.n_active);
         n = n < 0 ? 0 : (n > a.n_cap ? a.n_cap : n);
     }
     return n;
@@ -162,7 +179,7 @@ __device__ __attribute__((noinline)) void guard_overflow(u64* hist_row, const fl
                                                          float wlx, float wly, float wdx, float wdy,
                                                          double o, double inv, int hb, int Tl, uint32_t inc)
 {
-    const float4 A = patches[2 * (size_t)p];
+    const float4 A = load4(patches, 2 * (size_t)p);
     const int kl = exact_bin(A.x, A.y, A.z, wlx, wly, wdx, wdy, o, inv) - hb;
     if ((unsigned)kl < (unsigned)Tl) lds_add(hist_row + kl, inc);
 }
@@ -189,7 +206,7 @@ __device__ __forceinline__ void guard_drain(const Lds& L, const FwdArgs& a, int 
     for (uint32_t i = threadIdx.x; i < nq; i += blockDim.x) {
         const uint32_t e = L.qidx[i];
         const int p = (int)(e >> 8), j = (int)(e & 255u);
-        const float4 A = a.patches[2 * (size_t)p];
+        const float4 A = load4(a.patches, 2 * (size_t)p);
         const int kl = exact_bin(A.x, A.y, A.z, L.wlx[j], L.wly[j], L.wdx[j], L.wdy[j], L.so[j], a.inv) - hb;
         if ((unsigned)kl < (unsigned)Tl) lds_add(L.hist + (size_t)j * a.stride + kl, L.qinc[i]);
     }
@@ -202,21 +219,21 @@ __device__ __forceinline__ void load_patch(const FwdArgs& a, int p, int pe, floa
     *A = make_float4(a.dummy_x, 0.f, 1.f, 0.f);
     *B = make_float4(0.f, 0.f, -1.f, 0.f);
     if (p < pe) {
-        *A = a.patches[2 * (size_t)p];
-        *B = a.patches[2 * (size_t)p + 1];
+        *A = load4(a.patches, 2 * (size_t)p);
+        *B = load4(a.patches, 2 * (size_t)p + 1);
     }
 }
 
 // ---------------------------------------------------------------------------
 // Record summaries: one workgroup per kStatBlock consecutive records.
-__global__ void __launch_bounds__(kStatBlock) k_chunk_stats(const FwdArgs a, ChunkStat* st)
+__device__ __forceinline__ void chunk_stats_body(const FwdArgs& a, ChunkStat* st, int blk)
 {
     __shared__ float red[6][kStatBlock / 64];
     const int n_act = active_count(a);
-    const int p = (int)blockIdx.x * kStatBlock + (int)threadIdx.x;
+    const int p = blk * kStatBlock + (int)threadIdx.x;
     float v[6] = {3.0e38f, 3.0e38f, 3.0e38f, 3.0e38f, 3.0e38f, 0.f};   // x0, -x1, y0, -y1, z0, amax
     if (p < n_act) {
-        const float4 A = a.patches[2 * (size_t)p];
+        const float4 A = load4(a.patches, 2 * (size_t)p);
         v[0] = A.x;
         v[1] = -A.x;
         v[2] = A.y;
@@ -246,10 +263,15 @@ __global__ void __launch_bounds__(kStatBlock) k_chunk_stats(const FwdArgs a, Chu
         c.y1 = -r[3];
         c.z0 = r[4];
         c.amax = r[5];
-        c.count = max(0, min(kStatBlock, n_act - (int)blockIdx.x * kStatBlock));
+        c.count = max(0, min(kStatBlock, n_act - blk * kStatBlock));
         c.pad = 0;
-        st[blockIdx.x] = c;
+        st[blk] = c;
     }
+}
+
+__global__ void __launch_bounds__(kStatBlock) k_chunk_stats(const FwdArgs a, ChunkStat* st)
+{
+    chunk_stats_body(a, st, (int)blockIdx.x);
 }
 
 // Wall rectangles of unit u (approximate fp32 grid coordinates; only used for
@@ -303,7 +325,16 @@ template <bool CONF, int TL, int TX, int TY>
 __device__ float unit_weight_bound(const FwdArgs& a, int u, int i)
 {
     const UnitRect R = unit_rect<CONF, TL, TX, TY>(a, u);
-    const ChunkStat c = a.stats[i];
+    const v4f c0 = gmem(reinterpret_cast<const v4f*>(a.stats))[2 * (size_t)i];
+    const v4f c1 = gmem(reinterpret_cast<const v4f*>(a.stats))[2 * (size_t)i + 1];
+    ChunkStat c;
+    c.x0 = c0.x;
+    c.x1 = c0.y;
+    c.y0 = c0.z;
+    c.y1 = c0.w;
+    c.z0 = c1.x;
+    c.amax = c1.y;
+    c.count = __float_as_int(c1.z);
     if (c.count <= 0) return 0.f;
     const float z2 = c.z0 * c.z0;
     const float rd2 = rect_rect_d2(R.dx0, R.dx1, R.dy0, R.dy1, c.x0, c.x1, c.y0, c.y1) + z2;
@@ -377,7 +408,7 @@ __device__ __forceinline__ void jitter_rows(const FwdArgs& a, const Lds& L, cons
 #pragma unroll
         for (int q = 0; q < V + 2 * RM; ++q) w[q] = h[q];
         const float gg = L.gg[j];
-        float* out = a.out + (size_t)row * (size_t)a.T + t0;
+        __attribute__((address_space(1))) float* out = gmem(a.out) + (size_t)row * (size_t)a.T + t0;
 #pragma unroll
         for (int m = 0; m < V; ++m) {
             // out[t0 + m] = sum_k gp[k] H[t0 + m + RM - k]
@@ -386,7 +417,7 @@ __device__ __forceinline__ void jitter_rows(const FwdArgs& a, const Lds& L, cons
             for (int k = 0; k < K; ++k) acc = fmaf(g[k], w[m + 2 * RM - k], acc);
             if (t0 + m < t1w) {
                 if (a.atomic_out)
-                    unsafeAtomicAdd(out + m, acc * gg);
+                    unsafeAtomicAdd((float*)(out + m), acc * gg);
                 else
                     out[m] = acc * gg;
             }
@@ -475,9 +506,9 @@ __device__ __forceinline__ void flush(const FwdArgs& a, const Lds& L, float s, i
             float acc = 0.f;
             for (int i = 0; i <= 2 * R; ++i) acc = fmaf(gp[i], h[-i], acc);
             acc *= L.gg[j];
-            float* out = a.out + (size_t)row * (size_t)a.T + t;
+            __attribute__((address_space(1))) float* out = gmem(a.out) + (size_t)row * (size_t)a.T + t;
             if (a.atomic_out)
-                unsafeAtomicAdd(out, acc);
+                unsafeAtomicAdd((float*)out, acc);
             else
                 *out = acc;
         }
@@ -488,7 +519,7 @@ __device__ __forceinline__ void flush(const FwdArgs& a, const Lds& L, float s, i
 // The pair kernel.  Slot j of the workgroup: unit k = j / NH, then within the
 // unit (laser l, column c, row r) with j % NH = (l * TX + c) * TY + r.
 template <bool CONF, int TL, int TX, int TY, bool COS, bool WIN, bool PAIR>
-__global__ void __launch_bounds__(kBlock) k_forward(const FwdArgs a)
+__device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
 {
     constexpr int ND = TX * TY;
     constexpr int NH = TL * ND;
@@ -498,7 +529,7 @@ __global__ void __launch_bounds__(kBlock) k_forward(const FwdArgs a)
     const Lds L = lds_layout(smem, NS, a.stride, a.q_cap);
     const int n_act = active_count(a);
 
-    int id = (int)blockIdx.x;
+    int id = block_id;
     const int split = id % a.n_split;
     id /= a.n_split;
     const int twi = id % a.n_tw;
@@ -720,6 +751,38 @@ __global__ void __launch_bounds__(kBlock) k_forward(const FwdArgs a)
     flush<NS>(a, L, s, hb, Tl, t0w, t1w);
 }
 
+template <bool CONF, int TL, int TX, int TY, bool COS, bool WIN, bool PAIR>
+__global__ void __launch_bounds__(kBlock) k_forward(const FwdArgs a)
+{
+    forward_body<CONF, TL, TX, TY, COS, WIN, PAIR>(a, (int)blockIdx.x);
+}
+
+// Request of workgroup `block` in a batch: the last i with first[i] <= block
+// (first[] ascending, first[0] = 0); uniform across the workgroup.
+__device__ __forceinline__ int batch_slot(const int64_t* first, int n, int64_t block)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= block) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Batched pair kernel: one launch over the workgroups of every request of one
+// kernel variant, requests ordered by decreasing work per workgroup.
+// The table is a separate restrict-qualified argument: nothing the kernel
+// stores can alias it, so its fields are read once with scalar loads.
+template <bool CONF, int TL, int TX, int TY, bool COS, bool WIN, bool PAIR>
+__global__ void __launch_bounds__(kBlock)
+    k_forward_batch(const FwdArgs* __restrict__ tab, const int32_t* __restrict__ req,
+                    const int64_t* __restrict__ first, int n)
+{
+    const int i = batch_slot(first, n, (int64_t)blockIdx.x);
+    const FwdArgs& a = tab[req[i]];
+    forward_body<CONF, TL, TX, TY, COS, WIN, PAIR>(a, (int)((int64_t)blockIdx.x - first[i]));
+}
+
 // ---------------------------------------------------------------------------
 // Bin export (test hook): same device functions and decision rule.
 __global__ void __launch_bounds__(256) k_debug_bins(const DebugArgs d)
@@ -789,6 +852,23 @@ __global__ void k_fill(float* out, size_t n)
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = 0.f;
 }
 
+__global__ void __launch_bounds__(kStatBlock) k_chunk_stats_batch(const BatchList b)
+{
+    const int i = batch_slot(b.first, b.n, (int64_t)blockIdx.x);
+    const FwdArgs& a = b.tab[b.req[i]];
+    chunk_stats_body(a, a.stats, (int)((int64_t)blockIdx.x - b.first[i]));
+}
+
+// Zero the outputs of the listed requests (those accumulated with atomics):
+// blockIdx.y selects the entry, kFillBlocksPerRequest blocks stride over it.
+__global__ void __launch_bounds__(256) k_fill_batch(const BatchList b)
+{
+    const FwdArgs& a = b.tab[b.req[blockIdx.y]];
+    const size_t n = (size_t)a.out_len;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) a.out[i] = 0.f;
+}
+
 // ---------------------------------------------------------------------------
 // Launchers.
 template <typename K>
@@ -838,6 +918,63 @@ hipError_t launch_forward(const FwdArgs& a, const Plan& plan, bool confocal, hip
         if (plan.tl == 1 && plan.tx == 1 && plan.ty == 1) return launch_shape<false, 1, 1, 1>(a, plan, st);
     }
     return hipErrorInvalidValue;
+}
+
+template <typename K>
+static hipError_t launch_kb(K kern, const BatchList& b, int64_t n_blocks, size_t lds_bytes, hipStream_t st)
+{
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds_bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)n_blocks), dim3(kBlock), lds_bytes, st, b.tab, b.req, b.first, b.n);
+    return hipGetLastError();
+}
+
+template <bool CONF, int TL, int TX, int TY>
+static hipError_t launch_shape_batch(const BatchList& b, int64_t n_blocks, size_t lds, bool cos, bool pair,
+                                     hipStream_t st)
+{
+    if (pair) {
+        return cos ? launch_kb(k_forward_batch<CONF, TL, TX, TY, true, false, true>, b, n_blocks, lds, st)
+                   : launch_kb(k_forward_batch<CONF, TL, TX, TY, false, false, true>, b, n_blocks, lds, st);
+    }
+    return cos ? launch_kb(k_forward_batch<CONF, TL, TX, TY, true, true, false>, b, n_blocks, lds, st)
+               : launch_kb(k_forward_batch<CONF, TL, TX, TY, false, true, false>, b, n_blocks, lds, st);
+}
+
+hipError_t launch_forward_batch(const BatchList& b, int64_t n_blocks, size_t lds, int tl, int tx, int ty,
+                                bool confocal, bool cos, bool pair, hipStream_t st)
+{
+    if (n_blocks <= 0) return hipSuccess;
+    if (n_blocks > 0x7fffffff) return hipErrorInvalidValue;
+    if (confocal) {
+        if (tx == 4 && ty == 4) return launch_shape_batch<true, 1, 4, 4>(b, n_blocks, lds, cos, pair, st);
+        if (tx == 4 && ty == 2) return launch_shape_batch<true, 1, 4, 2>(b, n_blocks, lds, cos, pair, st);
+        if (tx == 2 && ty == 2) return launch_shape_batch<true, 1, 2, 2>(b, n_blocks, lds, cos, pair, st);
+        if (tx == 2 && ty == 1) return launch_shape_batch<true, 1, 2, 1>(b, n_blocks, lds, cos, pair, st);
+        if (tx == 1 && ty == 1) return launch_shape_batch<true, 1, 1, 1>(b, n_blocks, lds, cos, pair, st);
+    } else {
+        if (tl == 2 && tx == 2 && ty == 2) return launch_shape_batch<false, 2, 2, 2>(b, n_blocks, lds, cos, pair, st);
+        if (tl == 2 && tx == 1 && ty == 2) return launch_shape_batch<false, 2, 1, 2>(b, n_blocks, lds, cos, pair, st);
+        if (tl == 1 && tx == 1 && ty == 2) return launch_shape_batch<false, 1, 1, 2>(b, n_blocks, lds, cos, pair, st);
+        if (tl == 1 && tx == 1 && ty == 1) return launch_shape_batch<false, 1, 1, 1>(b, n_blocks, lds, cos, pair, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_stats_batch(const BatchList& b, int64_t n_blocks, hipStream_t st)
+{
+    if (n_blocks <= 0) return hipSuccess;
+    if (n_blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_chunk_stats_batch, dim3((unsigned)n_blocks), dim3(kStatBlock), 0, st, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_batch(const BatchList& b, hipStream_t st)
+{
+    if (b.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_batch, dim3(kFillBlocksPerRequest, (unsigned)b.n), dim3(256), 0, st, b);
+    return hipGetLastError();
 }
 
 hipError_t launch_stats(const FwdArgs& a, ChunkStat* stats, hipStream_t st)

@@ -43,17 +43,19 @@ __device__ __forceinline__ bool is_present(const GeomArgs& a, int64_t idx)
     return m && rho > 0.f && isfinite(z) && z > 0.f;
 }
 
-__global__ void __launch_bounds__(kGeomBlock) k_geom_count(const GeomArgs a)
+__device__ __forceinline__ void count_body(const GeomArgs& a, int blk)
 {
-    const int64_t e = (int64_t)blockIdx.x * kGeomBlock + threadIdx.x;
+    const int64_t e = (int64_t)blk * kGeomBlock + threadIdx.x;
     int ix = 0, iy = 0;
     bool p = enum_pixel(a, e, &ix, &iy);
     if (p) p = is_present(a, (int64_t)ix * a.ay.n + iy);
     const int cnt = __syncthreads_count(p);
-    if (threadIdx.x == 0) a.counts[blockIdx.x] = cnt;
+    if (threadIdx.x == 0) a.counts[blk] = cnt;
 }
 
-__global__ void __launch_bounds__(1024) k_geom_scan(const GeomArgs a)
+__global__ void __launch_bounds__(kGeomBlock) k_geom_count(const GeomArgs a) { count_body(a, (int)blockIdx.x); }
+
+__device__ __forceinline__ void scan_body(const GeomArgs& a)
 {
     __shared__ int part[1024];
     const int n = a.n_blocks;
@@ -78,6 +80,8 @@ __global__ void __launch_bounds__(1024) k_geom_scan(const GeomArgs a)
     if (threadIdx.x == 1023) *a.n_active = part[1023];
 }
 
+__global__ void __launch_bounds__(1024) k_geom_scan(const GeomArgs a) { scan_body(a); }
+
 // Derivative of the depth map along one axis (central inside, one-sided at
 // the borders, 0 for a single sample); `d` points at sample i, stride between
 // samples in elements.
@@ -89,10 +93,10 @@ __device__ __forceinline__ float deriv(const float* d, int n, int i, int64_t str
     return (d[stride] - d[-stride]) / (2.f * h);
 }
 
-__global__ void __launch_bounds__(kGeomBlock) k_geom_scatter(const GeomArgs a)
+__device__ __forceinline__ void scatter_body(const GeomArgs& a, int blk)
 {
     __shared__ int wave_cnt[kGeomBlock / 64];
-    const int64_t e = (int64_t)blockIdx.x * kGeomBlock + threadIdx.x;
+    const int64_t e = (int64_t)blk * kGeomBlock + threadIdx.x;
     int ix = 0, iy = 0;
     bool p = enum_pixel(a, e, &ix, &iy);
     const int64_t idx = (int64_t)ix * a.ay.n + iy;
@@ -103,7 +107,7 @@ __global__ void __launch_bounds__(kGeomBlock) k_geom_scatter(const GeomArgs a)
     if (lane == 0) wave_cnt[wave] = __popcll(bal);
     __syncthreads();
     if (!p) return;
-    int off = a.offsets[blockIdx.x];
+    int off = a.offsets[blk];
     for (int w = 0; w < wave; ++w) off += wave_cnt[w];
     off += rank;
 
@@ -118,6 +122,34 @@ __global__ void __launch_bounds__(kGeomBlock) k_geom_scatter(const GeomArgs a)
     a.patches[2 * (int64_t)off + 1] = make_float4(gx / len, gy / len, -1.f / len, __int_as_float((int)idx));
 }
 
+__global__ void __launch_bounds__(kGeomBlock) k_geom_scatter(const GeomArgs a) { scatter_body(a, (int)blockIdx.x); }
+
+// Batched geometry: the enumeration blocks of all depth maps in one launch
+// per phase (count, scan with one workgroup per map, scatter).
+__device__ __forceinline__ int geom_slot(const GeomList& g, int64_t block)
+{
+    int lo = 0, hi = g.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (g.first[mid] <= block) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(kGeomBlock) k_geom_count_batch(const GeomList g)
+{
+    const int i = geom_slot(g, (int64_t)blockIdx.x);
+    count_body(g.tab[i], (int)((int64_t)blockIdx.x - g.first[i]));
+}
+
+__global__ void __launch_bounds__(1024) k_geom_scan_batch(const GeomList g) { scan_body(g.tab[blockIdx.x]); }
+
+__global__ void __launch_bounds__(kGeomBlock) k_geom_scatter_batch(const GeomList g)
+{
+    const int i = geom_slot(g, (int64_t)blockIdx.x);
+    scatter_body(g.tab[i], (int)((int64_t)blockIdx.x - g.first[i]));
+}
+
 hipError_t launch_geometry(const GeomArgs& a, hipStream_t st)
 {
     if (a.n_blocks <= 0) return hipErrorInvalidValue;
@@ -128,6 +160,20 @@ hipError_t launch_geometry(const GeomArgs& a, hipStream_t st)
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_geom_scatter, dim3(a.n_blocks), dim3(kGeomBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_geometry_batch(const GeomList& g, int64_t n_blocks, hipStream_t st)
+{
+    if (g.n <= 0 || n_blocks <= 0) return hipSuccess;
+    if (n_blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_geom_count_batch, dim3((unsigned)n_blocks), dim3(kGeomBlock), 0, st, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_geom_scan_batch, dim3((unsigned)g.n), dim3(1024), 0, st, g);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_geom_scatter_batch, dim3((unsigned)n_blocks), dim3(kGeomBlock), 0, st, g);
     return hipGetLastError();
 }
 

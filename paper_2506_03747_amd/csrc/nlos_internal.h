@@ -45,6 +45,7 @@ struct ChunkStat {
     float x0, x1, y0, y1, z0, amax;
     int32_t count, pad;
 };
+static_assert(sizeof(ChunkStat) == 32, "summaries are read as two float4");
 constexpr int kStatBlock = 256;
 
 // Arguments of the pair kernels (confocal and non-confocal).
@@ -53,6 +54,7 @@ struct FwdArgs {
     const int32_t* n_active;   // nullable
     int32_t n_cap;
     float* out;
+    int64_t out_len;           // floats in out
     Axis rx, ry;               // relay (detector) grid
     Axis lx, ly;               // laser grid (non-confocal)
     double cx, cy, s;          // device position (cx, cy, s)
@@ -68,7 +70,7 @@ struct FwdArgs {
     int32_t n_units;           // tiles_l * tiles_x * tiles_y
     int32_t pair;              // 1: a workgroup owns two units
     int32_t plan;              // 1: units paired by a torus shift of half the unit grid
-    const ChunkStat* stats;    // [n_stats] summaries of the records
+    ChunkStat* stats;          // [n_stats] summaries of the records
     int32_t n_stats;
     int32_t n_split;           // patch ranges per unit pair
     int32_t tw, n_tw;          // output time window per workgroup, and count
@@ -78,6 +80,21 @@ struct FwdArgs {
     int32_t cosines;
     int32_t R;
     float taps[kMaxTaps];
+};
+
+// Work list of a batched launch: workgroup b runs request req[i] with local
+// workgroup index b - first[i], where i is the last entry with first[i] <= b.
+struct BatchList {
+    const FwdArgs* tab;        // device table of per-request arguments
+    const int32_t* req;        // [n] request of each entry
+    const int64_t* first;      // [n] first workgroup of each entry (ascending)
+    int32_t n;
+};
+
+struct GeomList {
+    const GeomArgs* tab;       // device table, one entry per depth map
+    const int64_t* first;      // [n] first enumeration block of each map
+    int32_t n;
 };
 
 // Debug/test hook arguments.
@@ -112,5 +129,13 @@ hipError_t launch_forward(const FwdArgs& a, const Plan& plan, bool confocal, hip
 hipError_t launch_stats(const FwdArgs& a, ChunkStat* stats, hipStream_t st);
 hipError_t launch_fill(float* out, size_t n, hipStream_t st);
 hipError_t launch_debug(const DebugArgs& a, hipStream_t st);
+
+// Batched launches (one launch each over all requests of the list).
+hipError_t launch_geometry_batch(const GeomList& g, int64_t n_blocks, hipStream_t st);
+hipError_t launch_stats_batch(const BatchList& b, int64_t n_blocks, hipStream_t st);
+constexpr int kFillBlocksPerRequest = 64;
+hipError_t launch_fill_batch(const BatchList& b, hipStream_t st);
+hipError_t launch_forward_batch(const BatchList& b, int64_t n_blocks, size_t lds_bytes, int tl, int tx, int ty,
+                                bool confocal, bool cosines, bool pair, hipStream_t st);
 
 }  // namespace nlos

@@ -31,6 +31,7 @@ __all__ = [
     "cfg1",
     "cfg2",
     "cfg3",
+    "cfg4_request",
     "cfg4_requests",
     "cfg5",
     "pshape",
@@ -152,30 +153,32 @@ def cfg3(seed: int = 3, det: int = 128, las: int = 8, n_bins: int = 2048) -> Sce
                  standoff_m=2.0, bin_ps=4.0, n_bins=n_bins, fwhm_ps=30.0, seed=seed)
 
 
-def cfg4_requests(n_requests: int = 256, seed: int = 4,
-                  max_scan: int = 128, max_patch: int = 262144):
-    """Batched serving mix: confocal requests with scan sizes U{32..128}^2,
-    patch counts U[4k, 262k] (rounded to a square grid), T in {512,1024,2048},
-    bin 4-16 ps, FWHM 30-70 ps, depths chosen so arrivals land in the window."""
-    out = []
-    for i in range(n_requests):
-        rng = np.random.default_rng(seed + i)
-        ns = int(rng.integers(32, max_scan + 1))
-        p = int(rng.integers(4096, max_patch + 1))
-        npg = max(2, int(round(np.sqrt(p))))
-        T = int(rng.choice([512, 1024, 2048]))
-        bin_ps = float(rng.uniform(4.0, 16.0))
-        fwhm = float(rng.uniform(30.0, 70.0))
-        window_m = 299792458.0 * T * bin_ps * 1e-12
-        zlo, zhi = 0.2 * window_m / 2, 0.6 * window_m / 2
-        z = zlo + (zhi - zlo) * _minmax(_smooth(rng.standard_normal((npg, npg)), npg / 16.0))
-        albedo = rng.uniform(0.0, 1.0, (npg, npg))
-        mask = _blob_mask(rng, (npg, npg), npg / 16.0)
-        out.append(Scene(f"cfg4[{i}]", grid(ns, ns, 1.0), None, grid(npg, npg, 1.0),
-                         z.astype(np.float32), albedo.astype(np.float32), mask,
-                         standoff_m=0.0, bin_ps=bin_ps, n_bins=T, fwhm_ps=fwhm,
-                         seed=seed + i))
-    return out
+def cfg4_request(i: int, seed: int = 4, max_scan: int = 128, max_patch: int = 262144) -> Scene:
+    """Request i of the batched serving mix (seed seed + i): confocal, scan
+    size U{32..128}^2 on a 2x2 m wall, patch count U[4k, 262k] rounded to a
+    square grid, T in {512, 1024, 2048}, bin 4-16 ps, FWHM 30-70 ps, depths in
+    [0.2, 0.6] of the window's half path length so arrivals land in the window,
+    albedo U[0,1], blob mask."""
+    rng = np.random.default_rng(seed + i)
+    ns = int(rng.integers(32, max_scan + 1))
+    p = int(rng.integers(4096, max_patch + 1))
+    npg = max(2, int(round(np.sqrt(p))))
+    T = int(rng.choice([512, 1024, 2048]))
+    bin_ps = float(rng.uniform(4.0, 16.0))
+    fwhm = float(rng.uniform(30.0, 70.0))
+    window_m = 299792458.0 * T * bin_ps * 1e-12
+    zlo, zhi = 0.2 * window_m / 2, 0.6 * window_m / 2
+    z = zlo + (zhi - zlo) * _minmax(_smooth(rng.standard_normal((npg, npg)), npg / 16.0))
+    albedo = rng.uniform(0.0, 1.0, (npg, npg))
+    mask = _blob_mask(rng, (npg, npg), npg / 16.0)
+    return Scene(f"cfg4[{i}]", grid(ns, ns, 1.0), None, grid(npg, npg, 1.0),
+                 z.astype(np.float32), albedo.astype(np.float32), mask,
+                 standoff_m=0.0, bin_ps=bin_ps, n_bins=T, fwhm_ps=fwhm, seed=seed + i)
+
+
+def cfg4_requests(n_requests: int = 256, seed: int = 4, max_scan: int = 128, max_patch: int = 262144):
+    """The batched serving mix: requests 0 .. n_requests-1 of cfg4_request."""
+    return [cfg4_request(i, seed, max_scan, max_patch) for i in range(n_requests)]
 
 
 def cfg5(seed: int = 5) -> Scene:

@@ -26,7 +26,7 @@ def declared_functions():
 
 def test_exports_every_declared_symbol(nat):
     names = declared_functions()
-    assert len(names) == 8, names
+    assert len(names) == 12, names
     for n in names:
         assert hasattr(nat.lib(), n), n
     bound = {s[0] for s in nat.SIGNATURES}
@@ -60,6 +60,63 @@ def test_struct_layout_matches_header(nat, tmp_path):
     want = [C.sizeof(G), G.half_x.offset, G.cy.offset, C.sizeof(P), P.laser.offset, P.standoff_m.offset,
             P.n_bins.offset, P.flags.offset, P.fwhm_ps.offset]
     assert got == want
+
+
+def test_request_struct_layout_matches_header(nat, tmp_path):
+    prog = tmp_path / "req.c"
+    prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "nlos.h"\n'
+                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
+                    'sizeof(nlos_depth_request), offsetof(nlos_depth_request, depth),'
+                    'offsetof(nlos_depth_request, albedo), offsetof(nlos_depth_request, mask),'
+                    'offsetof(nlos_depth_request, flags), offsetof(nlos_depth_request, patches),'
+                    'offsetof(nlos_depth_request, n_active),'
+                    'sizeof(nlos_request), offsetof(nlos_request, patches), offsetof(nlos_request, n_patches),'
+                    'offsetof(nlos_request, n_active), offsetof(nlos_request, out), offsetof(nlos_request, params));'
+                    'return 0;}\n')
+    exe = tmp_path / "req"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    D, R = nat.DepthRequest, nat.Request
+    want = [C.sizeof(D), D.depth.offset, D.albedo.offset, D.mask.offset, D.flags.offset, D.patches.offset,
+            D.n_active.offset, C.sizeof(R), R.patches.offset, R.n_patches.offset, R.n_active.offset,
+            R.out.offset, R.params.offset]
+    assert got == want
+
+
+def test_batched_checks(nat):
+    """Host-side checks of the batched calls: sizes, a bad request rejects the
+    whole call, a short workspace or table gives NLOS_ENOSPC, n = 0 is a no-op."""
+    L = nat.lib()
+    reqs = (nat.Request * 3)()
+    for i in range(3):
+        reqs[i] = nat.Request(_params(nat, n_bins=64 * (i + 1)), 0x10000, 1000 * (i + 1), None, 0x20000)
+    tb, wb = C.c_size_t(0), C.c_size_t(0)
+    assert L.nlos_forward_batched_sizes(reqs, 3, C.byref(tb), C.byref(wb)) == 0
+    assert tb.value >= 3 * 1024 and wb.value > tb.value   # argument table, then record summaries
+    assert tb.value % 256 == 0
+    assert L.nlos_forward_batched(reqs, 3, None, 0, FAKE, wb.value - 1, None) == nat.NLOS_ENOSPC
+    table = (C.c_ubyte * tb.value)()
+    assert L.nlos_forward_batched(reqs, 3, table, tb.value - 1, FAKE, wb.value, None) == nat.NLOS_ENOSPC
+    assert L.nlos_forward_batched(reqs, 3, table, tb.value, None, wb.value, None) == nat.NLOS_EINVAL
+    assert L.nlos_forward_batched(reqs, 0, None, 0, None, 0, None) == 0
+    assert L.nlos_forward_batched(None, 2, None, 0, FAKE, 1 << 30, None) == nat.NLOS_EINVAL
+    reqs[1].params.bin_ps = 0.0
+    assert L.nlos_forward_batched_sizes(reqs, 3, C.byref(tb), C.byref(wb)) == nat.NLOS_EINVAL
+    assert L.nlos_forward_batched(reqs, 3, None, 0, FAKE, 1 << 30, None) == nat.NLOS_EINVAL
+    reqs[1].params.bin_ps = 16.0
+    reqs[2].out = None
+    assert L.nlos_forward_batched(reqs, 3, None, 0, FAKE, 1 << 30, None) == nat.NLOS_EINVAL
+
+    g = nat.Grid(64, 64, 0.5, 0.5, 0.0, 0.0)
+    maps = (nat.DepthRequest * 2)()
+    maps[0] = nat.DepthRequest(g, 0x10000, None, None, 1, 0x20000, 0x30000)
+    maps[1] = nat.DepthRequest(nat.Grid(300, 17, 0.5, 0.5, 0.0, 0.0), 0x10000, None, None, 1, 0x20000, 0x30000)
+    assert L.nlos_patches_batched_sizes(maps, 2, C.byref(tb), C.byref(wb)) == 0
+    assert wb.value > tb.value
+    assert L.nlos_patches_batched(maps, 2, None, 0, FAKE, wb.value - 1, None) == nat.NLOS_ENOSPC
+    assert L.nlos_patches_batched(maps, 0, None, 0, None, 0, None) == 0
+    maps[1].flags = 4
+    assert L.nlos_patches_batched(maps, 2, None, 0, FAKE, 1 << 30, None) == nat.NLOS_EINVAL
 
 
 def _params(nat, **kw):
