@@ -46,6 +46,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=256,
+                    help="requests of the serving mix for the batched-vs-plain latency leg (0: skip)")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replayed step timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs the operator on a single MI355X "
@@ -98,6 +101,10 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
+    graph = None
+    if not args.no_graph:
+        graph = graph_leg(step, stream, args.steps, pairs)
+
     kern_ms = np.array([a.elapsed_time(b) for a, b in evs])
     step_ms = np.array([step_ev[i].elapsed_time(step_ev[i + 1]) for i in range(args.steps)])
     ms_per_step = wall * 1e3 / args.steps
@@ -144,8 +151,73 @@ def main():
                      "traffic": None, "kernel": "nlos_forward (k_chunk_stats + k_forward)",
                      "kernel_ms": round(kern_avg, 5), "flops_per_pair": F},
         "cpu_baseline": cpu,
+        "graph": graph,
+        "serving": serving_leg(args.serving_requests) if args.serving_requests > 0 else None,
     }
     print(json.dumps(line), flush=True)
+
+
+def graph_leg(step, stream, steps, pairs):
+    """The same step captured once in a HIP graph and replayed."""
+    import torch
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        step()                      # warm-up on the capture stream
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=side):
+            step()
+    torch.cuda.synchronize()
+    for _ in range(5):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return {"ms_per_step": round(ms, 5), "gpairs_s": round(pairs / (ms * 1e-3) / 1e9, 3)}
+
+
+def serving_leg(n_req):
+    """Batched vs plain serving of the uneven request mix: requests 0..n-1 of
+    the serving mix (confocal, scan 32..128 squared, 4k..262k patches, T of
+    512/1024/2048), Poisson arrivals at 1.5x the measured plain capacity, 2 GiB
+    HBM budget for requests in flight.  Latency = tick completion on the GPU
+    minus arrival."""
+    import torch
+    import scenes
+    from paper_2506_03747_amd import n_histograms, params_of, serving
+
+    reqs = [scenes.cfg4_request(i) for i in range(n_req)]
+    pairs = 0
+    for r in reqs:
+        present = (r.mask != 0) & (r.albedo > 0) & np.isfinite(r.depth) & (r.depth > 0)
+        pairs += n_histograms(params_of(r)) * int(present.sum())
+    staged = [serving.Server.stage(r) for r in reqs]
+    budget = 2 << 30
+    out = {"workload": f"serving mix: requests 0..{n_req - 1} (seed 4+i), confocal, scan U{{32..128}}^2, "
+                       f"U[4k,262k] patches, T in {{512,1024,2048}}, 4-16 ps bins, 30-70 ps FWHM",
+           "requests": n_req, "pairs": pairs, "hbm_budget_bytes": budget}
+    # warm-up of both paths, then the plain capacity with every request waiting
+    for mode in ("plain", "batched"):
+        serving.Server(budget, mode=mode).serve(reqs[:8], np.zeros(8), staged=staged[:8])
+    sat = serving.Server(budget, mode="plain").serve(reqs, np.zeros(n_req), staged=staged)
+    cap = n_req / (sat.makespan_ms * 1e-3)
+    rate = 1.5 * cap
+    out["plain_capacity_req_s"] = round(cap, 2)
+    out["arrival_rate_req_s"] = round(rate, 2)
+    arrivals = serving.poisson_arrivals(n_req, rate, seed=4)
+    for mode in ("plain", "batched"):
+        res = serving.Server(budget, mode=mode).serve(reqs, arrivals, staged=staged)
+        out[mode] = {"p50_ms": round(res.percentile(50), 3), "p99_ms": round(res.percentile(99), 3),
+                     "makespan_ms": round(res.makespan_ms, 3),
+                     "gpairs_s": round(pairs / (res.makespan_ms * 1e-3) / 1e9, 3),
+                     "ticks": res.ticks, "mean_batch": round(float(np.mean(res.batch_sizes)), 2),
+                     "peak_bytes": res.peak_bytes}
+    torch.cuda.synchronize()
+    return out
 
 
 if __name__ == "__main__":

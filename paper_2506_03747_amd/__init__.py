@@ -149,16 +149,17 @@ def debug_bins(params: Params, patches: torch.Tensor, n_active: Optional[torch.T
 
 
 class Batcher:
-    """Reusable buffers of the batched calls: a device workspace that grows
-    as needed and two pinned host tables used in turn (the table of a call
-    is reused only after an event recorded behind that call has completed),
-    so a loop of batched calls never blocks on its table uploads."""
+    """Reusable buffers of the batched calls: a device workspace per call kind
+    that grows as needed, and ``n_tables`` pinned host tables used in turn
+    (a table is reused only after an event recorded behind the call that
+    last used it has completed), so a loop of batched calls does not block
+    on its table uploads."""
 
-    def __init__(self, device="cuda"):
+    def __init__(self, device="cuda", n_tables: int = 2):
         self.device = torch.device(device)
         self._ws = {}
-        self._tables = [None, None]
-        self._events = [None, None]
+        self._tables = [None] * max(1, int(n_tables))
+        self._events = [None] * len(self._tables)
         self._turn = 0
 
     def workspace(self, key: str, nbytes: int) -> torch.Tensor:
@@ -170,7 +171,7 @@ class Batcher:
 
     def table(self, nbytes: int, stream) -> torch.Tensor:
         i = self._turn
-        self._turn ^= 1
+        self._turn = (i + 1) % len(self._tables)
         if self._events[i] is not None:
             self._events[i].synchronize()
         t = self._tables[i]
