@@ -8,6 +8,8 @@ no FMA contraction); this module only compiles it and marshals arrays.
 Functions follow arXiv 2506.03747: Section 2 Eq. (1) (forward model),
 Section 2 depth-to-volume mapping / Algorithm 1 step 2.1 (patches from a
 depth map), Section 2 temporal jitter / Algorithm 1 step 2.3 (Gaussian taps).
+The smooth forward and its gradient (a continuous Gaussian time response so
+that the depth has a gradient) are a reading: the paper bins hard.
 """
 from __future__ import annotations
 
@@ -73,6 +75,15 @@ def _bind(lib):
                                    C.c_void_p, C.c_void_p, C.c_void_p]
     lib.oracle_forward.restype = C.c_int32
     lib.oracle_num_threads.restype = C.c_int
+    lib.oracle_patches_f64.argtypes = [C.POINTER(Grid), dp, C.c_void_p, C.c_void_p, C.c_int32, dp]
+    lib.oracle_patches_f64.restype = C.c_int32
+    lib.oracle_smooth_radius.argtypes = [C.c_double, C.c_double]
+    lib.oracle_smooth_radius.restype = C.c_int32
+    lib.oracle_forward_smooth.argtypes = [C.POINTER(Params), dp, C.c_int32, C.c_void_p, C.c_int32, dp]
+    lib.oracle_forward_smooth.restype = C.c_int32
+    lib.oracle_smooth_grad.argtypes = [C.POINTER(Params), C.POINTER(Grid), dp, C.c_void_p, C.c_void_p, dp,
+                                       dp, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.oracle_smooth_grad.restype = C.c_int32
     return lib
 
 
@@ -171,3 +182,70 @@ def forward(scene, rec: np.ndarray | None = None, subset=None, want_hist=False,
     if want_bins:
         out["bins"] = bins
     return out
+
+
+def _maps64(scene, depth64=None, albedo64=None):
+    d = np.ascontiguousarray(scene.depth if depth64 is None else depth64, np.float64)
+    a = None
+    if albedo64 is not None:
+        a = np.ascontiguousarray(albedo64, np.float64)
+    elif scene.albedo is not None:
+        a = np.ascontiguousarray(scene.albedo, np.float64)
+    m = None if scene.mask is None else np.ascontiguousarray(scene.mask, np.uint8)
+    return d, a, m
+
+
+def patches_f64(scene, depth64=None, albedo64=None, lib=None) -> np.ndarray:
+    """Records from fp64 maps (defaults: the scene's fp32 maps, promoted)."""
+    lib = lib or load()
+    g = scene.patch_grid
+    d, a, m = _maps64(scene, depth64, albedo64)
+    rec = np.zeros((g["nx"] * g["ny"], 8), np.float64)
+    lib.oracle_patches_f64(C.byref(make_grid(g)), _dptr(d), None if a is None else a.ctypes.data,
+                           None if m is None else m.ctypes.data, 1 if scene.cosines else 0, _dptr(rec))
+    return rec
+
+
+def smooth_radius(fwhm_ps: float, bin_ps: float, lib=None) -> int:
+    return int((lib or load()).oracle_smooth_radius(float(fwhm_ps), float(bin_ps)))
+
+
+def forward_smooth(scene, rec: np.ndarray | None = None, subset=None, lib=None) -> np.ndarray:
+    """Smooth-response histograms [n_out, T] (fp64)."""
+    lib = lib or load()
+    if rec is None:
+        rec = patches(scene, lib)
+    rec = np.ascontiguousarray(rec, np.float64)
+    n_total = scene.n_laser * scene.n_scan
+    sub = None if subset is None else np.ascontiguousarray(subset, np.int32)
+    n_out = n_total if sub is None else sub.shape[0]
+    tau = np.zeros((n_out, int(scene.n_bins)), np.float64)
+    rc = lib.oracle_forward_smooth(C.byref(make_params(scene)), _dptr(rec), rec.shape[0],
+                                   None if sub is None else sub.ctypes.data, 0 if sub is None else n_out,
+                                   _dptr(tau))
+    if rc != 0:
+        raise ValueError("oracle_forward_smooth rejected its arguments")
+    return tau
+
+
+def smooth_grad(scene, y: np.ndarray, depth64=None, albedo64=None, lib=None) -> dict:
+    """Loss 1/2 ||tau_s - y||^2 and its gradient with respect to the depth and
+    albedo maps (and each record), all fp64."""
+    lib = lib or load()
+    g = scene.patch_grid
+    d, a, m = _maps64(scene, depth64, albedo64)
+    npx = g["nx"] * g["ny"]
+    yy = np.ascontiguousarray(y, np.float64).reshape(-1)
+    if yy.size != scene.n_laser * scene.n_scan * int(scene.n_bins):
+        raise ValueError("target has the wrong size")
+    loss = C.c_double(0.0)
+    gd = np.zeros(npx, np.float64)
+    ga = np.zeros(npx, np.float64)
+    gr = np.zeros((npx, 8), np.float64)
+    rc = lib.oracle_smooth_grad(C.byref(make_params(scene)), C.byref(make_grid(g)), _dptr(d),
+                                None if a is None else a.ctypes.data, None if m is None else m.ctypes.data,
+                                _dptr(yy), C.byref(loss), gd.ctypes.data, ga.ctypes.data, gr.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_smooth_grad rejected its arguments")
+    return {"loss": loss.value, "grad_depth": gd.reshape(g["nx"], g["ny"]),
+            "grad_albedo": ga.reshape(g["nx"], g["ny"]), "grad_rec": gr}

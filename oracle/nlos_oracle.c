@@ -43,6 +43,7 @@
 #include <string.h>
 
 #define ORACLE_C_LIGHT 299792458.0 /* m/s, exact SI value */
+#define ORACLE_PI 3.14159265358979323846
 
 typedef struct {
     int32_t nx, ny;
@@ -96,26 +97,26 @@ double oracle_inv_bin(double bin_ps) { return 1.0 / (ORACLE_C_LIGHT * (bin_ps * 
 
 /* Derivative of the depth map along one axis at index i (n samples, spacing
  * h): central difference inside, one-sided at the two borders, 0 if n == 1. */
-static double deriv(const float* d, int32_t n, int64_t stride, int32_t i, double h)
+static double deriv(const double* d, int32_t n, int64_t stride, int32_t i, double h)
 {
     if (n < 2) return 0.0;
-    if (i == 0) return ((double)d[stride] - (double)d[0]) / h;
-    if (i == n - 1) return ((double)d[(int64_t)(n - 1) * stride] - (double)d[(int64_t)(n - 2) * stride]) / h;
-    return ((double)d[(int64_t)(i + 1) * stride] - (double)d[(int64_t)(i - 1) * stride]) / (2.0 * h);
+    if (i == 0) return (d[stride] - d[0]) / h;
+    if (i == n - 1) return (d[(int64_t)(n - 1) * stride] - d[(int64_t)(n - 2) * stride]) / h;
+    return (d[(int64_t)(i + 1) * stride] - d[(int64_t)(i - 1) * stride]) / (2.0 * h);
 }
 
 /*
  * Depth (+ albedo) map -> patch records (Section 2 depth-to-volume mapping;
- * Algorithm 1 step 2.1).  Maps are [nx][ny] (x major).  A null albedo means
- * 0.5 everywhere, as in the paper.  A patch is present when its mask entry is
- * nonzero (or the mask is null), its albedo is > 0 and its depth is finite and
- * > 0.  Output per pixel, 8 doubles:
+ * Algorithm 1 step 2.1), maps in fp64.  Maps are [nx][ny] (x major).  A null
+ * albedo means 0.5 everywhere, as in the paper.  A patch is present when its
+ * mask entry is nonzero (or the mask is null), its albedo is > 0 and its
+ * depth is finite and > 0.  Output per pixel, 8 doubles:
  *   px, py, pz, a, n_x, n_y, n_z, present
  * with a = albedo * area; area = dx dy sqrt(1 + D_x^2 + D_y^2) with cosines,
  * dx dy without; n = (D_x, D_y, -1) / sqrt(1 + D_x^2 + D_y^2) (towards the wall).
  */
-int32_t oracle_patches(const oracle_grid* g, const float* depth, const float* albedo,
-                       const uint8_t* mask, int32_t cosines, double* rec)
+int32_t oracle_patches_f64(const oracle_grid* g, const double* depth, const double* albedo,
+                           const uint8_t* mask, int32_t cosines, double* rec)
 {
     const int32_t nx = g->nx, ny = g->ny;
     const double hx = (2.0 * g->half_x) / (double)nx;
@@ -124,8 +125,8 @@ int32_t oracle_patches(const oracle_grid* g, const float* depth, const float* al
     for (int32_t ix = 0; ix < nx; ++ix) {
         for (int32_t iy = 0; iy < ny; ++iy) {
             const int64_t idx = (int64_t)ix * ny + iy;
-            const double z = (double)depth[idx];
-            const double rho = albedo ? (double)albedo[idx] : 0.5;
+            const double z = depth[idx];
+            const double rho = albedo ? albedo[idx] : 0.5;
             const int present = (!mask || mask[idx] != 0) && rho > 0.0 && isfinite(z) && z > 0.0;
             const double gx = deriv(depth + iy, nx, ny, ix, hx);
             const double gy = deriv(depth + (int64_t)ix * ny, ny, 1, iy, hy);
@@ -143,6 +144,25 @@ int32_t oracle_patches(const oracle_grid* g, const float* depth, const float* al
         }
     }
     return present_count;
+}
+
+/* The same from fp32 maps (the product's input precision): every fp32 value
+ * is exactly representable in fp64, so this is oracle_patches_f64 of them. */
+int32_t oracle_patches(const oracle_grid* g, const float* depth, const float* albedo,
+                       const uint8_t* mask, int32_t cosines, double* rec)
+{
+    const int64_t n = (int64_t)g->nx * g->ny;
+    double* d = (double*)malloc(sizeof(double) * (size_t)n);
+    double* a = albedo ? (double*)malloc(sizeof(double) * (size_t)n) : NULL;
+    if (!d || (albedo && !a)) { free(d); free(a); return -1; }
+    for (int64_t i = 0; i < n; ++i) {
+        d[i] = (double)depth[i];
+        if (a) a[i] = (double)albedo[i];
+    }
+    const int32_t r = oracle_patches_f64(g, d, a, mask, cosines, rec);
+    free(d);
+    free(a);
+    return r;
 }
 
 /*
@@ -295,4 +315,285 @@ int32_t oracle_forward(const oracle_params* prm, const double* rec, int32_t P,
     free(rx);
     free(lx);
     return err;
+}
+
+/* ------------------------------------------------------------------------
+ * Smooth time response and its gradient (the differentiable forward; a
+ * reading, since the paper bins hard).  Each pair adds w * N(k + 1/2 - u) to
+ * bin k, where N is the normalised continuous Gaussian in bin units with the
+ * jitter's sigma (sigma = FWHM / (2 sqrt(2 ln 2)) / dt, Section 2 temporal
+ * jitter), over the bins within Rs = ceil(6 sigma) of floor(u) that lie in
+ * [0, T).  Loss L = 1/2 sum_{h,k} (tau_s[h][k] - y[h][k])^2.
+ * ------------------------------------------------------------------------ */
+
+static double smooth_sigma(double fwhm_ps, double bin_ps)
+{
+    return fwhm_ps / (2.0 * sqrt(2.0 * log(2.0))) / bin_ps;
+}
+
+/* Support radius Rs = ceil(6 sigma) in bins, or -1 if FWHM <= 0. */
+int32_t oracle_smooth_radius(double fwhm_ps, double bin_ps)
+{
+    if (!(fwhm_ps > 0.0) || !(bin_ps > 0.0)) return -1;
+    const double r = ceil(6.0 * smooth_sigma(fwhm_ps, bin_ps));
+    return r > 1.0e6 ? -1 : (int32_t)r;
+}
+
+static double gauss(double x, double sigma)
+{
+    return exp(-(x * x) / (2.0 * sigma * sigma)) / (sigma * sqrt(2.0 * ORACLE_PI));
+}
+
+/* One (laser point, detector point, patch) pair: arrival u (bins), weight w,
+ * and the derivatives of w and u with respect to the patch depth pz and of w
+ * with respect to the patch normal (dw_dn[3]) and the patch factor a (w_a).
+ * gg = g_l g_d (stand-off leg weights), o = leg offsets (m).
+ * With cosines w = a gg pz^2 c_l c_d / (r_l^4 r_d^4), c = max(0, -n . (p - w)),
+ * which is a gg cw_l cp_l cp_d cw_d / (r_l^2 r_d^2) with cw = pz / r and
+ * cp = c / r; without, w = a gg / (r_l^2 r_d^2). */
+static void pair_eval(const double* q, double wlx, double wly, double wdx, double wdy, double o,
+                      double gg, double inv, int cosines, double* u, double* w, double* w_a,
+                      double* dw_dpz, double* dw_dn, double* du_dpz)
+{
+    const double px = q[0], py = q[1], pz = q[2];
+    const double alx = px - wlx, aly = py - wly, alz = pz;
+    const double adx = px - wdx, ady = py - wdy, adz = pz;
+    const double r_l = sqrt((alx * alx + aly * aly) + alz * alz);
+    const double r_d = sqrt((adx * adx + ady * ady) + adz * adz);
+    *u = ((r_l + r_d) + o) * inv;
+    *du_dpz = inv * (pz / r_l + pz / r_d);
+    const double rl2 = r_l * r_l, rd2 = r_d * r_d;
+    if (cosines) {
+        double c_l = -(q[4] * alx + q[5] * aly + q[6] * alz);
+        double c_d = -(q[4] * adx + q[5] * ady + q[6] * adz);
+        if (c_l <= 0.0 || c_d <= 0.0) {
+            *w = *w_a = *dw_dpz = 0.0;
+            dw_dn[0] = dw_dn[1] = dw_dn[2] = 0.0;
+            return;
+        }
+        const double den = (rl2 * rl2) * (rd2 * rd2);
+        const double F = pz * pz * c_l * c_d / den;
+        /* dc/dpz = -n_z; d(r^4)/dpz = 4 r^2 pz */
+        const double dF_dpz = (2.0 * pz * c_l * c_d - pz * pz * q[6] * c_d - pz * pz * c_l * q[6]) / den
+                              - F * (4.0 * pz / rl2 + 4.0 * pz / rd2);
+        /* dc_l/dn = -(p - w_l), dc_d/dn = -(p - w_d) */
+        const double k = pz * pz / den;
+        dw_dn[0] = q[3] * gg * k * (-alx * c_d - adx * c_l);
+        dw_dn[1] = q[3] * gg * k * (-aly * c_d - ady * c_l);
+        dw_dn[2] = q[3] * gg * k * (-alz * c_d - adz * c_l);
+        *w_a = gg * F;
+        *w = q[3] * gg * F;
+        *dw_dpz = q[3] * gg * dF_dpz;
+    } else {
+        const double F = 1.0 / (rl2 * rd2);
+        *w_a = gg * F;
+        *w = q[3] * gg * F;
+        *dw_dpz = -(*w) * (2.0 * pz / rl2 + 2.0 * pz / rd2);
+        dw_dn[0] = dw_dn[1] = dw_dn[2] = 0.0;
+    }
+}
+
+/* Bin range [k_lo, k_hi] of a pair's smooth response clipped to [0, T). */
+static int smooth_range(double u, int32_t Rs, int32_t T, int32_t* k_lo, int32_t* k_hi)
+{
+    const double k0 = floor(u);
+    const double lo = k0 - (double)Rs, hi = k0 + (double)Rs;
+    if (hi < 0.0 || lo > (double)(T - 1)) return 0;
+    *k_lo = lo < 0.0 ? 0 : (int32_t)lo;
+    *k_hi = hi > (double)(T - 1) ? T - 1 : (int32_t)hi;
+    return 1;
+}
+
+/* Wall points and leg terms of histogram h (as in oracle_forward). */
+static void hist_setup(const oracle_params* prm, const double* rx, const double* lx, int64_t h, double* wlx,
+                       double* wly, double* wdx, double* wdy, double* o, double* gg)
+{
+    const oracle_grid* rg = &prm->relay;
+    const int confocal = prm->laser.nx <= 0 || prm->laser.ny <= 0;
+    const oracle_grid* lg = confocal ? rg : &prm->laser;
+    const int64_t S = (int64_t)rg->nx * rg->ny;
+    const int64_t l = h / S, d = h % S;
+    *wdx = rx[d / rg->ny];
+    *wdy = rx[rg->nx + d % rg->ny];
+    if (confocal) { *wlx = *wdx; *wly = *wdy; }
+    else { *wlx = lx[l / lg->ny]; *wly = lx[lg->nx + l % lg->ny]; }
+    double o_l, g_l, o_d, g_d;
+    standoff_leg(*wlx, *wly, rg->cx, rg->cy, prm->standoff_m, &o_l, &g_l);
+    standoff_leg(*wdx, *wdy, rg->cx, rg->cy, prm->standoff_m, &o_d, &g_d);
+    *o = o_l + o_d;
+    *gg = g_l * g_d;
+}
+
+/*
+ * Smooth forward: tau_s[h][k] = sum_p w_hp N(k + 1/2 - u_hp) over the support
+ * above.  Layout and `subset` as in oracle_forward.  Returns 0 or -1.
+ */
+int32_t oracle_forward_smooth(const oracle_params* prm, const double* rec, int32_t P,
+                              const int32_t* subset, int32_t n_subset, double* tau)
+{
+    const oracle_grid* rg = &prm->relay;
+    const int confocal = prm->laser.nx <= 0 || prm->laser.ny <= 0;
+    const oracle_grid* lg = confocal ? rg : &prm->laser;
+    const int64_t S = (int64_t)rg->nx * rg->ny;
+    const int64_t L = confocal ? 1 : (int64_t)lg->nx * lg->ny;
+    const int64_t n_out = subset ? n_subset : L * S;
+    const int32_t T = prm->n_bins;
+    const int32_t Rs = oracle_smooth_radius(prm->fwhm_ps, prm->bin_ps);
+    if (T < 1 || !(prm->bin_ps > 0.0) || prm->standoff_m < 0.0 || P < 0 || Rs < 0 || !tau) return -1;
+    const double sigma = smooth_sigma(prm->fwhm_ps, prm->bin_ps);
+    const double inv = oracle_inv_bin(prm->bin_ps);
+    double* rx = (double*)malloc(sizeof(double) * (size_t)(rg->nx + rg->ny));
+    double* lx = (double*)malloc(sizeof(double) * (size_t)(lg->nx + lg->ny));
+    if (!rx || !lx) { free(rx); free(lx); return -1; }
+    oracle_grid_coords(rg, rx, rx + rg->nx);
+    oracle_grid_coords(lg, lx, lx + lg->nx);
+    int32_t err = 0;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t oi = 0; oi < n_out; ++oi) {
+        const int64_t h = subset ? subset[oi] : oi;
+        if (h < 0 || h >= L * S) { err = -1; continue; }
+        double wlx, wly, wdx, wdy, o, gg;
+        hist_setup(prm, rx, lx, h, &wlx, &wly, &wdx, &wdy, &o, &gg);
+        double* out = tau + oi * T;
+        for (int32_t k = 0; k < T; ++k) out[k] = 0.0;
+        for (int32_t p = 0; p < P; ++p) {
+            const double* q = rec + (int64_t)p * 8;
+            if (q[7] == 0.0) continue;
+            double u, w, w_a, dw_dpz, dw_dn[3], du_dpz;
+            pair_eval(q, wlx, wly, wdx, wdy, o, gg, inv, prm->cosines, &u, &w, &w_a, &dw_dpz, dw_dn, &du_dpz);
+            int32_t k_lo, k_hi;
+            if (w == 0.0 || !smooth_range(u, Rs, T, &k_lo, &k_hi)) continue;
+            for (int32_t k = k_lo; k <= k_hi; ++k) out[k] += w * gauss(((double)k + 0.5) - u, sigma);
+        }
+    }
+    free(rx);
+    free(lx);
+    return err;
+}
+
+/*
+ * Gradient of L with respect to the depth and albedo maps (fp64 maps, as
+ * oracle_patches_f64), by the chain rule through each pair's weight and
+ * arrival, the patch records, and the central-difference normals and areas.
+ *   y            target [L*S][T].
+ *   loss         L (host double).
+ *   grad_depth   [nx][ny] (nullable);  grad_albedo [nx][ny] (nullable): with a
+ *                null albedo map, the gradient with respect to that constant
+ *                0.5 map.
+ *   grad_rec     [nx*ny][8] (nullable): dL/d(pz, a, n_x, n_y, n_z) of each
+ *                present pixel's record at entries 2..6, zeros elsewhere.
+ * The support of each pair's response moves with floor(u); that step is not
+ * differentiated (its contribution is below the Gaussian tail at 6 sigma).
+ */
+int32_t oracle_smooth_grad(const oracle_params* prm, const oracle_grid* g, const double* depth,
+                           const double* albedo, const uint8_t* mask, const double* y, double* loss,
+                           double* grad_depth, double* grad_albedo, double* grad_rec)
+{
+    const oracle_grid* rg = &prm->relay;
+    const int confocal = prm->laser.nx <= 0 || prm->laser.ny <= 0;
+    const oracle_grid* lg = confocal ? rg : &prm->laser;
+    const int64_t H = (int64_t)rg->nx * rg->ny * (confocal ? 1 : (int64_t)lg->nx * lg->ny);
+    const int32_t T = prm->n_bins;
+    const int32_t Rs = oracle_smooth_radius(prm->fwhm_ps, prm->bin_ps);
+    if (Rs < 0 || T < 1 || !y || !loss) return -1;
+    const int32_t nx = g->nx, ny = g->ny;
+    const int64_t npx = (int64_t)nx * ny;
+    const double hx = (2.0 * g->half_x) / (double)nx;
+    const double hy = (2.0 * g->half_y) / (double)ny;
+    const double sigma = smooth_sigma(prm->fwhm_ps, prm->bin_ps);
+    const double inv = oracle_inv_bin(prm->bin_ps);
+
+    double* rec = (double*)malloc(sizeof(double) * 8 * (size_t)npx);
+    double* tau = (double*)malloc(sizeof(double) * (size_t)(H * T));
+    double* gr = (double*)calloc((size_t)npx * 8, sizeof(double));
+    double* rx = (double*)malloc(sizeof(double) * (size_t)(rg->nx + rg->ny));
+    double* lx = (double*)malloc(sizeof(double) * (size_t)(lg->nx + lg->ny));
+    if (!rec || !tau || !gr || !rx || !lx) { free(rec); free(tau); free(gr); free(rx); free(lx); return -1; }
+    oracle_patches_f64(g, depth, albedo, mask, prm->cosines, rec);
+    int32_t rc = oracle_forward_smooth(prm, rec, (int32_t)npx, NULL, 0, tau);
+    if (rc != 0) { free(rec); free(tau); free(gr); free(rx); free(lx); return rc; }
+    /* residual and loss */
+    double L2 = 0.0;
+    for (int64_t i = 0; i < H * T; ++i) {
+        tau[i] -= y[i];
+        L2 += tau[i] * tau[i];
+    }
+    *loss = 0.5 * L2;
+    oracle_grid_coords(rg, rx, rx + rg->nx);
+    oracle_grid_coords(lg, lx, lx + lg->nx);
+
+    /* record gradients: for each present patch, sum over every histogram */
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t p = 0; p < npx; ++p) {
+        const double* q = rec + p * 8;
+        if (q[7] == 0.0) continue;
+        double gpz = 0.0, ga = 0.0, gn[3] = {0.0, 0.0, 0.0};
+        for (int64_t h = 0; h < H; ++h) {
+            double wlx, wly, wdx, wdy, o, gg;
+            hist_setup(prm, rx, lx, h, &wlx, &wly, &wdx, &wdy, &o, &gg);
+            double u, w, w_a, dw_dpz, dw_dn[3], du_dpz;
+            pair_eval(q, wlx, wly, wdx, wdy, o, gg, inv, prm->cosines, &u, &w, &w_a, &dw_dpz, dw_dn, &du_dpz);
+            int32_t k_lo, k_hi;
+            if (!smooth_range(u, Rs, T, &k_lo, &k_hi)) continue;
+            const double* r = tau + h * T;
+            double G0 = 0.0, G1 = 0.0;   /* sum r N(x), sum r (x / sigma^2) N(x) */
+            for (int32_t k = k_lo; k <= k_hi; ++k) {
+                const double x = ((double)k + 0.5) - u;
+                const double nv = gauss(x, sigma);
+                G0 += r[k] * nv;
+                G1 += r[k] * (x / (sigma * sigma)) * nv;
+            }
+            /* dL/dw = G0, dL/du = w G1 */
+            gpz += G0 * dw_dpz + w * G1 * du_dpz;
+            ga += G0 * w_a;
+            gn[0] += G0 * dw_dn[0];
+            gn[1] += G0 * dw_dn[1];
+            gn[2] += G0 * dw_dn[2];
+        }
+        double* o8 = gr + p * 8;
+        o8[2] = gpz;
+        o8[3] = ga;
+        o8[4] = gn[0];
+        o8[5] = gn[1];
+        o8[6] = gn[2];
+    }
+
+    /* records -> maps: pz = D; a = rho * area(gx, gy); n = (gx, gy, -1) / len */
+    if (grad_depth) for (int64_t i = 0; i < npx; ++i) grad_depth[i] = 0.0;
+    if (grad_albedo) for (int64_t i = 0; i < npx; ++i) grad_albedo[i] = 0.0;
+    for (int32_t ix = 0; ix < nx; ++ix) {
+        for (int32_t iy = 0; iy < ny; ++iy) {
+            const int64_t idx = (int64_t)ix * ny + iy;
+            if (rec[idx * 8 + 7] == 0.0) continue;
+            const double* o8 = gr + idx * 8;
+            const double rho = albedo ? albedo[idx] : 0.5;
+            const double gx = deriv(depth + iy, nx, ny, ix, hx);
+            const double gy = deriv(depth + (int64_t)ix * ny, ny, 1, iy, hy);
+            const double len = sqrt(1.0 + gx * gx + gy * gy);
+            if (grad_albedo) grad_albedo[idx] = o8[3] * hx * hy * (prm->cosines ? len : 1.0);
+            if (!grad_depth) continue;
+            grad_depth[idx] += o8[2];
+            if (!prm->cosines) continue;
+            /* dn/dgx = e_x / len - (gx, gy, -1) gx / len^3 (and likewise gy);
+             * d(area)/dgx = dx dy gx / len */
+            const double l3 = len * len * len;
+            const double dot = o8[4] * gx + o8[5] * gy - o8[6];
+            const double dL_dgx = o8[4] / len - dot * gx / l3 + o8[3] * rho * hx * hy * gx / len;
+            const double dL_dgy = o8[5] / len - dot * gy / l3 + o8[3] * rho * hx * hy * gy / len;
+            /* derivative stencils of deriv() */
+            if (nx >= 2) {
+                if (ix == 0) { grad_depth[idx + ny] += dL_dgx / hx; grad_depth[idx] -= dL_dgx / hx; }
+                else if (ix == nx - 1) { grad_depth[idx] += dL_dgx / hx; grad_depth[idx - ny] -= dL_dgx / hx; }
+                else { grad_depth[idx + ny] += dL_dgx / (2.0 * hx); grad_depth[idx - ny] -= dL_dgx / (2.0 * hx); }
+            }
+            if (ny >= 2) {
+                if (iy == 0) { grad_depth[idx + 1] += dL_dgy / hy; grad_depth[idx] -= dL_dgy / hy; }
+                else if (iy == ny - 1) { grad_depth[idx] += dL_dgy / hy; grad_depth[idx - 1] -= dL_dgy / hy; }
+                else { grad_depth[idx + 1] += dL_dgy / (2.0 * hy); grad_depth[idx - 1] -= dL_dgy / (2.0 * hy); }
+            }
+        }
+    }
+    if (grad_rec) memcpy(grad_rec, gr, sizeof(double) * 8 * (size_t)npx);
+    free(rec); free(tau); free(gr); free(rx); free(lx);
+    return 0;
 }

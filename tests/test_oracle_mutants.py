@@ -37,6 +37,55 @@ MUTANTS = [
 ]
 
 
+# planted mistakes in the smooth forward and its gradient, checked against
+# the smooth pins
+SMOOTH_MUTANTS = [
+    ("smooth_unnormalised", "/ (sigma * sqrt(2.0 * ORACLE_PI))", ""),
+    ("smooth_no_half_offset", "((double)k + 0.5) - u", "((double)k) - u"),
+    ("smooth_support_2_sigma", "ceil(6.0 * smooth_sigma", "ceil(2.0 * smooth_sigma"),
+    ("smooth_sigma_fwhm", "return fwhm_ps / (2.0 * sqrt(2.0 * log(2.0))) / bin_ps;", "return fwhm_ps / bin_ps;"),
+    ("grad_arrival_sign", "gpz += G0 * dw_dpz + w * G1 * du_dpz;", "gpz += G0 * dw_dpz - w * G1 * du_dpz;"),
+    ("grad_drop_arrival", "gpz += G0 * dw_dpz + w * G1 * du_dpz;", "gpz += G0 * dw_dpz;"),
+    ("grad_one_leg_arrival", "*du_dpz = inv * (pz / r_l + pz / r_d);", "*du_dpz = inv * (pz / r_l);"),
+    ("grad_drop_normal_projection", "const double dL_dgx = o8[4] / len - dot * gx / l3",
+     "const double dL_dgx = o8[4] / len"),
+    ("grad_drop_area_term", "+ o8[3] * rho * hx * hy * gy / len;", ";"),
+    ("grad_border_stencil", "if (ix == 0) { grad_depth[idx + ny] += dL_dgx / hx; grad_depth[idx] -= dL_dgx / hx; }",
+     "if (ix == 0) { grad_depth[idx + ny] += dL_dgx / (2.0 * hx); grad_depth[idx] -= dL_dgx / (2.0 * hx); }"),
+    ("grad_albedo_projected_area", "grad_albedo[idx] = o8[3] * hx * hy * (prm->cosines ? len : 1.0);",
+     "grad_albedo[idx] = o8[3] * hx * hy;"),
+    ("grad_drop_patch_cosine_depth", "- pz * pz * q[6] * c_d - pz * pz * c_l * q[6]", ""),
+    ("grad_normal_sign", "dw_dn[0] = q[3] * gg * k * (-alx * c_d - adx * c_l);",
+     "dw_dn[0] = q[3] * gg * k * (alx * c_d - adx * c_l);"),
+    ("grad_inverse_square_power", "- F * (4.0 * pz / rl2 + 4.0 * pz / rd2);", "- F * (2.0 * pz / rl2 + 2.0 * pz / rd2);"),
+]
+
+
+def _run_smooth_pins(lib):
+    import pins_smooth
+    failures = []
+    for pin in pins_smooth.SMOOTH_PINS:
+        try:
+            pin(lib)
+        except Exception as e:  # noqa: BLE001 - any failure counts
+            failures.append((pin.__name__, type(e).__name__))
+    return failures
+
+
+@pytest.mark.parametrize("name,old,new", SMOOTH_MUTANTS, ids=[m[0] for m in SMOOTH_MUTANTS])
+def test_smooth_mutant_is_caught(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation site for {name} not found"
+    path = str(tmp_path / "mut.c")
+    with open(path, "w") as f:
+        f.write(src.replace(old, new))
+    so = str(tmp_path / "libmut.so")
+    oracle.compile_library(path, so)
+    failures = _run_smooth_pins(oracle.load(so))
+    assert failures, f"mutant {name} passed every smooth pin"
+    print(name, "caught by", failures)
+
+
 def _run_pins(lib):
     failures = []
     for pin in pins.FAST_PINS:
