@@ -233,6 +233,62 @@ int nlos_forward_batched(const nlos_request* reqs, int32_t n, void* table, size_
                          size_t ws_bytes, void* stream);
 
 /*
+ * Smooth time response and its adjoint (confocal only).  The hard forward
+ * bins each arrival, so its output does not vary smoothly with the patch
+ * depths.  The smooth forward gives every pair the continuous, normalised
+ * Gaussian response of the detector jitter (Section 2, temporal jitter;
+ * sigma = FWHM / (2 sqrt(2 ln 2)) / dt bins) instead of hard binning plus
+ * blur:
+ *     tau_s[s][k] = sum_p w_sp N(k + 1/2 - u_sp)  for |k - floor(u_sp)| <= Rs,
+ * Rs = ceil(6 sigma), 0 <= k < T, with w and u exactly as in nlos_forward.
+ * Arrivals outside the window still reach in-window bins within Rs.
+ * Requires fwhm_ps > 0 and sigma * 6 <= 1024 bins; one T-bin histogram of
+ * 64-bit bins must fit in LDS (T <= ~20000).
+ */
+int nlos_forward_smooth_workspace_bytes(const nlos_params* p, int32_t n_patches, size_t* bytes);
+
+/* Smooth forward; arguments as nlos_forward (confocal output [nx][ny][T]). */
+int nlos_forward_smooth(const nlos_params* p, const float* patches, int32_t n_patches,
+                        const int32_t* n_active, float* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace of nlos_adjoint: per-record partial gradients (fp64) of each
+ * range of scan points. */
+int nlos_adjoint_workspace_bytes(const nlos_params* p, int32_t n_patches, size_t* bytes);
+
+/*
+ * Adjoint of the smooth forward with respect to the patch records: given the
+ * upstream gradient G = dL/dtau_s (device float [nx][ny][T], 16-byte
+ * aligned), writes for every record p (device float [n_patches][8], 16-byte
+ * aligned)
+ *     { 0, 0, dL/dz, dL/da, dL/dn_x, dL/dn_y, dL/dn_z, 0 }
+ * (records past *n_active get zeros).  Per pair dL/dw = sum_k G N(x_k) and
+ * dL/du = w sum_k G (x_k / sigma^2) N(x_k), x_k = k + 1/2 - u, chained
+ * through w(z, n, a) and u(z).  The step of the support with floor(u) is
+ * not differentiated (below the tail at 6 sigma).  Deterministic: partial
+ * sums per scan range are added in a fixed order.
+ */
+int nlos_adjoint(const nlos_params* p, const float* patches, int32_t n_patches, const int32_t* n_active,
+                 const float* grad_out, float* grad_patches, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace of nlos_patches_adjoint: 12 bytes per pixel. */
+int nlos_patches_adjoint_workspace_bytes(const nlos_grid* g, size_t* bytes);
+
+/*
+ * Adjoint of nlos_patches_from_depth: record gradients (from nlos_adjoint,
+ * records as written by nlos_patches_from_depth for the same maps and flags)
+ * -> gradients of the depth map (device float [nx][ny], every pixel: a
+ * masked pixel's depth still enters its neighbours' normals) and of the
+ * albedo map (device float [nx][ny] or NULL; zero where no record).  The
+ * chain runs through z = D, n = (D_x, D_y, -1) / len and a = albedo * area,
+ * area = dx dy len with NLOS_F_COSINES (dx dy without), and the central /
+ * one-sided differences that give D_x and D_y.  The mask is not needed:
+ * each record carries its pixel index.
+ */
+int nlos_patches_adjoint(const nlos_grid* g, const float* depth, const float* albedo, uint32_t flags,
+                         const float* patches, const int32_t* n_active, const float* grad_patches,
+                         float* grad_depth, float* grad_albedo, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Test hook: the bin index of every (histogram, record) pair, decided by the
  * same device functions and the same fp32-then-fp64 rule as nlos_forward.
  *   bins    device int32 [H][n_patches], H = histograms of the output

@@ -84,6 +84,8 @@ def _bind(lib):
     lib.oracle_smooth_grad.argtypes = [C.POINTER(Params), C.POINTER(Grid), dp, C.c_void_p, C.c_void_p, dp,
                                        dp, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.oracle_smooth_grad.restype = C.c_int32
+    lib.oracle_adjoint_records.argtypes = [C.POINTER(Params), dp, C.c_int32, dp, C.c_void_p, C.c_int32, dp]
+    lib.oracle_adjoint_records.restype = C.c_int32
     return lib
 
 
@@ -249,3 +251,24 @@ def smooth_grad(scene, y: np.ndarray, depth64=None, albedo64=None, lib=None) -> 
         raise ValueError("oracle_smooth_grad rejected its arguments")
     return {"loss": loss.value, "grad_depth": gd.reshape(g["nx"], g["ny"]),
             "grad_albedo": ga.reshape(g["nx"], g["ny"]), "grad_rec": gr}
+
+
+def adjoint_records(scene, G: np.ndarray, rec: np.ndarray | None = None, subset=None, lib=None) -> np.ndarray:
+    """Record gradients [n, 8] (d/d(pz, a, n_x, n_y, n_z) at 2..6) of the
+    smooth forward for upstream gradient G [L*S, T], for the records in
+    ``subset`` (default all)."""
+    lib = lib or load()
+    if rec is None:
+        rec = patches(scene, lib)
+    rec = np.ascontiguousarray(rec, np.float64)
+    GG = np.ascontiguousarray(G, np.float64).reshape(-1)
+    if GG.size != scene.n_laser * scene.n_scan * int(scene.n_bins):
+        raise ValueError("upstream gradient has the wrong size")
+    sub = None if subset is None else np.ascontiguousarray(subset, np.int32)
+    n = rec.shape[0] if sub is None else sub.shape[0]
+    out = np.zeros((n, 8), np.float64)
+    rc = lib.oracle_adjoint_records(C.byref(make_params(scene)), _dptr(rec), rec.shape[0], _dptr(GG),
+                                    None if sub is None else sub.ctypes.data, 0 if sub is None else n, _dptr(out))
+    if rc != 0:
+        raise ValueError("oracle_adjoint_records rejected its arguments")
+    return out

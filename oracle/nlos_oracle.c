@@ -471,6 +471,82 @@ int32_t oracle_forward_smooth(const oracle_params* prm, const double* rec, int32
     return err;
 }
 
+/* dL/d(pz, a, n_x, n_y, n_z) of one present record q, summed over every
+ * histogram, for upstream gradient G = dL/dtau_s [H][T]: per pair
+ * dL/dw = G0 = sum_k G N(x_k) and dL/du = w G1, G1 = sum_k G (x_k / sigma^2)
+ * N(x_k), x_k = k + 1/2 - u.  Written to o8[2..6]. */
+static void record_grad(const oracle_params* prm, const double* rx, const double* lx, int64_t H,
+                        const double* q, const double* G, int32_t Rs, double sigma, double inv, double* o8)
+{
+    const int32_t T = prm->n_bins;
+    double gpz = 0.0, ga = 0.0, gn[3] = {0.0, 0.0, 0.0};
+    for (int64_t h = 0; h < H; ++h) {
+        double wlx, wly, wdx, wdy, o, gg;
+        hist_setup(prm, rx, lx, h, &wlx, &wly, &wdx, &wdy, &o, &gg);
+        double u, w, w_a, dw_dpz, dw_dn[3], du_dpz;
+        pair_eval(q, wlx, wly, wdx, wdy, o, gg, inv, prm->cosines, &u, &w, &w_a, &dw_dpz, dw_dn, &du_dpz);
+        int32_t k_lo, k_hi;
+        if (!smooth_range(u, Rs, T, &k_lo, &k_hi)) continue;
+        const double* r = G + h * T;
+        double G0 = 0.0, G1 = 0.0;
+        for (int32_t k = k_lo; k <= k_hi; ++k) {
+            const double x = ((double)k + 0.5) - u;
+            const double nv = gauss(x, sigma);
+            G0 += r[k] * nv;
+            G1 += r[k] * (x / (sigma * sigma)) * nv;
+        }
+        /* dL/dw = G0, dL/du = w G1 */
+        gpz += G0 * dw_dpz + w * G1 * du_dpz;
+        ga += G0 * w_a;
+        gn[0] += G0 * dw_dn[0];
+        gn[1] += G0 * dw_dn[1];
+        gn[2] += G0 * dw_dn[2];
+    }
+    o8[2] = gpz;
+    o8[3] = ga;
+    o8[4] = gn[0];
+    o8[5] = gn[1];
+    o8[6] = gn[2];
+}
+
+/*
+ * Record gradients for an arbitrary upstream gradient G [L*S][T] (the adjoint
+ * of the smooth forward with respect to the records), for the records listed
+ * in `subset` (nullable: all P).  grad_rec [n][8]: entries 2..6 as above,
+ * zeros elsewhere and for absent records.  Returns 0 or -1.
+ */
+int32_t oracle_adjoint_records(const oracle_params* prm, const double* rec, int32_t P, const double* G,
+                               const int32_t* subset, int32_t n_subset, double* grad_rec)
+{
+    const oracle_grid* rg = &prm->relay;
+    const int confocal = prm->laser.nx <= 0 || prm->laser.ny <= 0;
+    const oracle_grid* lg = confocal ? rg : &prm->laser;
+    const int64_t H = (int64_t)rg->nx * rg->ny * (confocal ? 1 : (int64_t)lg->nx * lg->ny);
+    const int32_t Rs = oracle_smooth_radius(prm->fwhm_ps, prm->bin_ps);
+    if (Rs < 0 || prm->n_bins < 1 || !G || !grad_rec || P < 0) return -1;
+    const int64_t n = subset ? n_subset : P;
+    double* rx = (double*)malloc(sizeof(double) * (size_t)(rg->nx + rg->ny));
+    double* lx = (double*)malloc(sizeof(double) * (size_t)(lg->nx + lg->ny));
+    if (!rx || !lx) { free(rx); free(lx); return -1; }
+    oracle_grid_coords(rg, rx, rx + rg->nx);
+    oracle_grid_coords(lg, lx, lx + lg->nx);
+    const double sigma = smooth_sigma(prm->fwhm_ps, prm->bin_ps);
+    const double inv = oracle_inv_bin(prm->bin_ps);
+    int32_t err = 0;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t p = subset ? subset[i] : i;
+        double* o8 = grad_rec + i * 8;
+        for (int k = 0; k < 8; ++k) o8[k] = 0.0;
+        if (p < 0 || p >= P) { err = -1; continue; }
+        if (rec[p * 8 + 7] == 0.0) continue;
+        record_grad(prm, rx, lx, H, rec + p * 8, G, Rs, sigma, inv, o8);
+    }
+    free(rx);
+    free(lx);
+    return err;
+}
+
 /*
  * Gradient of L with respect to the depth and albedo maps (fp64 maps, as
  * oracle_patches_f64), by the chain rule through each pair's weight and
@@ -525,37 +601,8 @@ int32_t oracle_smooth_grad(const oracle_params* prm, const oracle_grid* g, const
     /* record gradients: for each present patch, sum over every histogram */
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t p = 0; p < npx; ++p) {
-        const double* q = rec + p * 8;
-        if (q[7] == 0.0) continue;
-        double gpz = 0.0, ga = 0.0, gn[3] = {0.0, 0.0, 0.0};
-        for (int64_t h = 0; h < H; ++h) {
-            double wlx, wly, wdx, wdy, o, gg;
-            hist_setup(prm, rx, lx, h, &wlx, &wly, &wdx, &wdy, &o, &gg);
-            double u, w, w_a, dw_dpz, dw_dn[3], du_dpz;
-            pair_eval(q, wlx, wly, wdx, wdy, o, gg, inv, prm->cosines, &u, &w, &w_a, &dw_dpz, dw_dn, &du_dpz);
-            int32_t k_lo, k_hi;
-            if (!smooth_range(u, Rs, T, &k_lo, &k_hi)) continue;
-            const double* r = tau + h * T;
-            double G0 = 0.0, G1 = 0.0;   /* sum r N(x), sum r (x / sigma^2) N(x) */
-            for (int32_t k = k_lo; k <= k_hi; ++k) {
-                const double x = ((double)k + 0.5) - u;
-                const double nv = gauss(x, sigma);
-                G0 += r[k] * nv;
-                G1 += r[k] * (x / (sigma * sigma)) * nv;
-            }
-            /* dL/dw = G0, dL/du = w G1 */
-            gpz += G0 * dw_dpz + w * G1 * du_dpz;
-            ga += G0 * w_a;
-            gn[0] += G0 * dw_dn[0];
-            gn[1] += G0 * dw_dn[1];
-            gn[2] += G0 * dw_dn[2];
-        }
-        double* o8 = gr + p * 8;
-        o8[2] = gpz;
-        o8[3] = ga;
-        o8[4] = gn[0];
-        o8[5] = gn[1];
-        o8[6] = gn[2];
+        if (rec[p * 8 + 7] == 0.0) continue;
+        record_grad(prm, rx, lx, H, rec + p * 8, tau, Rs, sigma, inv, gr + p * 8);
     }
 
     /* records -> maps: pz = D; a = rho * area(gx, gy); n = (gx, gy, -1) / len */

@@ -7,6 +7,7 @@ tensors are rejected (there is no CPU fallback).
 
     patches, n_active = patches_from_depth(depth, grid, albedo, mask)
     tau = forward(params, patches, n_active)         # [nx, ny, T] fp32
+    tau_s = smooth_transient(depth, albedo, grid, params, mask)   # differentiable
 
 Grids are dicts ``dict(nx, ny, half_x, half_y, cx, cy)`` (metres, cell-centred
 on the wall plane z = 0); maps are [nx, ny] (x major).
@@ -24,7 +25,8 @@ from ._native import (NLOS_F_COSINES, NLOS_MAX_BINS, NLOS_MAX_PATCHES, NLOS_MAX_
 
 __all__ = ["Grid", "Params", "NlosError", "make_grid", "make_params", "params_of",
            "patches_from_depth", "forward", "debug_bins", "out_shape", "n_histograms",
-           "Batcher", "patches_batched", "forward_batched"]
+           "Batcher", "patches_batched", "forward_batched", "forward_smooth", "adjoint", "patches_adjoint",
+           "SmoothTransient", "smooth_transient"]
 
 
 def make_grid(g) -> Grid:
@@ -260,3 +262,108 @@ def _run_batched(key, reqs, n, result, batcher, stream, sizes_fn, run_fn):
     if batcher is not None:
         batcher.mark(st)
     return result
+
+
+def _ws(nbytes: int, device):
+    return torch.empty(max(int(nbytes), 16), dtype=torch.uint8, device=device)
+
+
+def forward_smooth(params: Params, patches: torch.Tensor, n_active: Optional[torch.Tensor] = None,
+                   out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Smooth-response histograms (continuous Gaussian per pair), confocal
+    [nx, ny, T]."""
+    _dev(patches, torch.float32, "patches")
+    _dev(n_active, torch.int32, "n_active")
+    if patches.dim() != 2 or patches.shape[1] != NLOS_RECORD_FLOATS:
+        raise ValueError("patches must be [n, 8]")
+    if out is None:
+        out = torch.empty(out_shape(params), dtype=torch.float32, device=patches.device)
+    _dev(out, torch.float32, "out")
+    if out.numel() != n_histograms(params) * params.n_bins:
+        raise ValueError("out has the wrong size")
+    need = C.c_size_t(0)
+    check(lib().nlos_forward_smooth_workspace_bytes(C.byref(params), patches.shape[0], C.byref(need)),
+          "nlos_forward_smooth_workspace_bytes")
+    ws = _ws(need.value, patches.device)
+    check(lib().nlos_forward_smooth(C.byref(params), _ptr(patches), patches.shape[0], _ptr(n_active), _ptr(out),
+                                    _ptr(ws), ws.numel(), _stream(stream)), "nlos_forward_smooth")
+    return out
+
+
+def adjoint(params: Params, patches: torch.Tensor, n_active: Optional[torch.Tensor], grad_out: torch.Tensor,
+            out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Record gradients [n, 8] ({0, 0, dz, da, dn_x, dn_y, dn_z, 0}) of the
+    smooth forward for the upstream gradient ``grad_out`` [nx, ny, T]."""
+    _dev(patches, torch.float32, "patches")
+    _dev(n_active, torch.int32, "n_active")
+    _dev(grad_out, torch.float32, "grad_out")
+    if grad_out.numel() != n_histograms(params) * params.n_bins:
+        raise ValueError("grad_out has the wrong size")
+    if out is None:
+        out = torch.empty((patches.shape[0], NLOS_RECORD_FLOATS), dtype=torch.float32, device=patches.device)
+    _dev(out, torch.float32, "out")
+    need = C.c_size_t(0)
+    check(lib().nlos_adjoint_workspace_bytes(C.byref(params), patches.shape[0], C.byref(need)),
+          "nlos_adjoint_workspace_bytes")
+    ws = _ws(need.value, patches.device)
+    check(lib().nlos_adjoint(C.byref(params), _ptr(patches), patches.shape[0], _ptr(n_active), _ptr(grad_out),
+                             _ptr(out), _ptr(ws), ws.numel(), _stream(stream)), "nlos_adjoint")
+    return out
+
+
+def patches_adjoint(grid, depth: torch.Tensor, albedo: Optional[torch.Tensor], patches: torch.Tensor,
+                    n_active: Optional[torch.Tensor], grad_rec: torch.Tensor, cosines: bool = True,
+                    want_albedo: bool = True, stream=None):
+    """Record gradients -> (grad_depth [nx, ny], grad_albedo [nx, ny] or None)."""
+    g = make_grid(grid)
+    _dev(depth, torch.float32, "depth")
+    _dev(albedo, torch.float32, "albedo")
+    _dev(patches, torch.float32, "patches")
+    _dev(n_active, torch.int32, "n_active")
+    _dev(grad_rec, torch.float32, "grad_rec")
+    npx = g.nx * g.ny
+    if depth.numel() != npx or patches.shape[0] != npx or grad_rec.shape[0] != npx:
+        raise ValueError("maps, records and record gradients must cover the grid")
+    gd = torch.empty((g.nx, g.ny), dtype=torch.float32, device=depth.device)
+    ga = torch.empty((g.nx, g.ny), dtype=torch.float32, device=depth.device) if want_albedo else None
+    need = C.c_size_t(0)
+    check(lib().nlos_patches_adjoint_workspace_bytes(C.byref(g), C.byref(need)),
+          "nlos_patches_adjoint_workspace_bytes")
+    ws = _ws(need.value, depth.device)
+    check(lib().nlos_patches_adjoint(C.byref(g), _ptr(depth), _ptr(albedo), NLOS_F_COSINES if cosines else 0,
+                                     _ptr(patches), _ptr(n_active), _ptr(grad_rec), _ptr(gd), _ptr(ga), _ptr(ws),
+                                     ws.numel(), _stream(stream)), "nlos_patches_adjoint")
+    return gd, ga
+
+
+class SmoothTransient(torch.autograd.Function):
+    """tau_s = smooth forward of the depth (and albedo) maps; backward by the
+    hand-written adjoint kernels (record gradients, then the depth stencil)."""
+
+    @staticmethod
+    def forward(ctx, depth, albedo, grid, params, mask):
+        cos = bool(params.flags & NLOS_F_COSINES)
+        depth = depth.contiguous()
+        albedo = None if albedo is None else albedo.contiguous()
+        rec, n = patches_from_depth(depth, grid, albedo, mask, cosines=cos)
+        tau = forward_smooth(params, rec, n)
+        ctx.grid, ctx.params, ctx.cos = grid, params, cos
+        ctx.has_albedo = albedo is not None
+        ctx.save_for_backward(depth, albedo if albedo is not None else depth, rec, n)
+        return tau
+
+    @staticmethod
+    def backward(ctx, grad_tau):
+        depth, albedo, rec, n = ctx.saved_tensors
+        if not ctx.has_albedo:
+            albedo = None
+        grad_rec = adjoint(ctx.params, rec, n, grad_tau.contiguous())
+        gd, ga = patches_adjoint(ctx.grid, depth, albedo, rec, n, grad_rec, cosines=ctx.cos,
+                                 want_albedo=ctx.has_albedo and ctx.needs_input_grad[1])
+        return gd, ga, None, None, None
+
+
+def smooth_transient(depth: torch.Tensor, albedo: Optional[torch.Tensor], grid, params: Params,
+                     mask: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Differentiable smooth forward of depth and albedo maps (confocal)."""
+    return SmoothTransient.apply(depth, albedo, grid, params, mask)

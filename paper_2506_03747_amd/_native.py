@@ -78,6 +78,17 @@ SIGNATURES = [
      [C.POINTER(Request), C.c_int32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     ("nlos_forward_batched", C.c_int,
      [C.POINTER(Request), C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("nlos_forward_smooth_workspace_bytes", C.c_int, [C.POINTER(Params), C.c_int32, C.POINTER(C.c_size_t)]),
+    ("nlos_forward_smooth", C.c_int,
+     [C.POINTER(Params), C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("nlos_adjoint_workspace_bytes", C.c_int, [C.POINTER(Params), C.c_int32, C.POINTER(C.c_size_t)]),
+    ("nlos_adjoint", C.c_int,
+     [C.POINTER(Params), C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+      C.c_void_p]),
+    ("nlos_patches_adjoint_workspace_bytes", C.c_int, [C.POINTER(Grid), C.POINTER(C.c_size_t)]),
+    ("nlos_patches_adjoint", C.c_int,
+     [C.POINTER(Grid), C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+      C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     ("nlos_debug_bins", C.c_int,
      [C.POINTER(Params), C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
       C.c_void_p]),

@@ -483,6 +483,100 @@ int plan_geom_batch(const nlos_depth_request* reqs, int32_t n, GeomBatch* b)
     return NLOS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Smooth forward and adjoint (confocal).
+constexpr int kSmoothMaxRadius = 1024;
+
+int smooth_setup(const nlos_params* p, const float* patches, int32_t n_patches, const int32_t* n_active,
+                 nlos::SmoothArgs* a)
+{
+    int rc = params_ok(p);
+    if (rc != NLOS_OK) return rc;
+    if (!is_confocal(p) || !(p->fwhm_ps > 0.0)) return NLOS_EINVAL;
+    if (n_patches < 0 || n_patches > NLOS_MAX_PATCHES) return NLOS_EINVAL;
+    if (n_patches > 0 && !patches) return NLOS_EINVAL;
+    if ((patches && !aligned(patches, 16)) || (n_active && !aligned(n_active, 4))) return NLOS_EINVAL;
+    std::memset(a, 0, sizeof(*a));
+    const double sigma = p->fwhm_ps / (2.0 * std::sqrt(2.0 * std::log(2.0))) / p->bin_ps;
+    const double rs = std::ceil(6.0 * sigma);
+    if (!(rs <= (double)kSmoothMaxRadius) || !(sigma > 1e-3)) return NLOS_EINVAL;
+    a->patches = reinterpret_cast<const float4*>(patches);
+    a->n_active = n_active;
+    a->n_cap = n_patches;
+    a->rx = axis(p->relay.half_x, p->relay.cx, p->relay.nx);
+    a->ry = axis(p->relay.half_y, p->relay.cy, p->relay.ny);
+    a->cx = p->relay.cx;
+    a->cy = p->relay.cy;
+    a->s = p->standoff_m;
+    a->inv = 1.0 / (kC * (p->bin_ps * 1e-12));
+    a->sigma = (float)sigma;
+    a->norm = (float)(1.0 / (sigma * std::sqrt(2.0 * 3.14159265358979323846)));
+    a->inv_s2 = (float)(1.0 / (sigma * sigma));
+    a->c1 = (float)std::exp(-1.0 / (sigma * sigma));
+    a->T = p->n_bins;
+    a->Rs = (int32_t)rs;
+    a->cosines = (p->flags & NLOS_F_COSINES) ? 1 : 0;
+    return NLOS_OK;
+}
+
+struct SmoothPlan {
+    int tx, ty;
+    int64_t tiles, n_blocks;
+    size_t lds;
+};
+
+size_t smooth_lds(int nh, int stride) { return (size_t)nh * stride * 8 + (size_t)nh * 12 + 64 * 4 + 64; }
+
+int smooth_plan(const nlos_params* p, int32_t n_patches, SmoothPlan* sp, int* split)
+{
+    static const int shapes[5][2] = {{4, 4}, {4, 2}, {2, 2}, {2, 1}, {1, 1}};
+    const int T = p->n_bins;
+    int chosen = -1, largest = -1;
+    for (int i = 0; i < 5; ++i) {
+        if (smooth_lds(shapes[i][0] * shapes[i][1], T) > kLdsMax) continue;
+        if (largest < 0) largest = i;
+        const int64_t tiles = (int64_t)((p->relay.nx + shapes[i][0] - 1) / shapes[i][0]) *
+                              ((p->relay.ny + shapes[i][1] - 1) / shapes[i][1]);
+        if (tiles >= kTargetBlocks) {
+            chosen = i;
+            break;
+        }
+    }
+    if (chosen < 0) chosen = largest;
+    if (chosen < 0) return NLOS_EINVAL;   // one histogram of T bins does not fit in LDS
+    sp->tx = shapes[chosen][0];
+    sp->ty = shapes[chosen][1];
+    sp->tiles = (int64_t)((p->relay.nx + sp->tx - 1) / sp->tx) * ((p->relay.ny + sp->ty - 1) / sp->ty);
+    int64_t sv = 1;
+    if (sp->tiles < kTargetBlocks) {
+        sv = (kTargetBlocks + sp->tiles - 1) / sp->tiles;
+        sv = std::min<int64_t>(sv, std::max<int64_t>(1, n_patches / nlos::kBlock));
+    }
+    *split = (int)sv;
+    sp->n_blocks = sp->tiles * sv;
+    sp->lds = smooth_lds(sp->tx * sp->ty, T);
+    return NLOS_OK;
+}
+
+// Scan ranges of the adjoint: enough workgroups to fill the GPU twice.
+int adjoint_split(const nlos_params* p, int32_t n_patches)
+{
+    const int64_t S = (int64_t)p->relay.nx * p->relay.ny;
+    const int64_t pbk = std::max<int64_t>(1, ((int64_t)n_patches + nlos::kBlock - 1) / nlos::kBlock);
+    int64_t sv = (2 * kTargetBlocks + pbk - 1) / pbk;
+    sv = std::max<int64_t>(1, std::min<int64_t>(sv, std::min<int64_t>(S, 65535)));
+    return (int)sv;
+}
+
+int adjoint_rows(int T)
+{
+    const int64_t fixed = 32 * 24 + 256;
+    const int64_t rows = (int64_t)(kLdsMax - fixed) / (4 * (int64_t)T);
+    return (int)std::min<int64_t>(32, rows);
+}
+
+size_t adjoint_lds(int rows, int T) { return (((size_t)rows * T * 4 + 15) & ~(size_t)15) + (size_t)rows * 24; }
+
 }  // namespace
 
 extern "C" {
@@ -674,6 +768,146 @@ int nlos_forward_batched(const nlos_request* reqs, int32_t n, void* table, size_
         if (e != hipSuccess) return hip_fail(e);
     }
     return NLOS_OK;
+}
+
+int nlos_forward_smooth_workspace_bytes(const nlos_params* p, int32_t n_patches, size_t* bytes)
+{
+    nlos::SmoothArgs a;
+    if (!bytes) return NLOS_EINVAL;
+    int rc = smooth_setup(p, nullptr, 0, nullptr, &a);
+    if (rc != NLOS_OK) return rc;
+    if (n_patches < 0 || n_patches > NLOS_MAX_PATCHES) return NLOS_EINVAL;
+    SmoothPlan sp;
+    int split = 1;
+    rc = smooth_plan(p, n_patches, &sp, &split);
+    if (rc != NLOS_OK) return rc;
+    *bytes = stats_bytes(n_patches);
+    return NLOS_OK;
+}
+
+int nlos_forward_smooth(const nlos_params* p, const float* patches, int32_t n_patches, const int32_t* n_active,
+                        float* out, void* ws, size_t ws_bytes, void* stream)
+{
+    nlos::SmoothArgs a;
+    int rc = smooth_setup(p, patches, n_patches, n_active, &a);
+    if (rc != NLOS_OK) return rc;
+    if (!out || !aligned(out, 16)) return NLOS_EINVAL;
+    SmoothPlan sp;
+    int split = 1;
+    rc = smooth_plan(p, n_patches, &sp, &split);
+    if (rc != NLOS_OK) return rc;
+    const size_t need = stats_bytes(n_patches);
+    if (ws_bytes < need) return NLOS_ENOSPC;
+    if (need > 0 && (!ws || !aligned(ws, 16))) return NLOS_EINVAL;
+    const int dev = device_check();
+    if (dev != NLOS_OK) return dev;
+    a.out = out;
+    a.tiles_x = (p->relay.nx + sp.tx - 1) / sp.tx;
+    a.tiles_y = (p->relay.ny + sp.ty - 1) / sp.ty;
+    a.n_split = split;
+    a.stride = p->n_bins;
+    a.atomic_out = split > 1 ? 1 : 0;
+    a.stats = reinterpret_cast<nlos::ChunkStat*>(ws);
+    a.n_stats = (int32_t)stats_count(n_patches);
+    hipStream_t st = (hipStream_t)stream;
+    // record summaries through the hard forward's kernel (same records)
+    nlos::FwdArgs fa;
+    std::memset(&fa, 0, sizeof(fa));
+    fa.patches = a.patches;
+    fa.n_active = a.n_active;
+    fa.n_cap = a.n_cap;
+    fa.n_stats = a.n_stats;
+    hipError_t e = nlos::launch_stats(fa, a.stats, st);
+    if (e != hipSuccess) return hip_fail(e);
+    if (a.atomic_out) {
+        e = nlos::launch_fill(out, (size_t)n_hist(p) * (size_t)p->n_bins, st);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    e = nlos::launch_smooth(a, sp.tx, sp.ty, sp.n_blocks, sp.lds, st);
+    return e == hipSuccess ? NLOS_OK : hip_fail(e);
+}
+
+int nlos_adjoint_workspace_bytes(const nlos_params* p, int32_t n_patches, size_t* bytes)
+{
+    nlos::SmoothArgs a;
+    if (!bytes) return NLOS_EINVAL;
+    int rc = smooth_setup(p, nullptr, 0, nullptr, &a);
+    if (rc != NLOS_OK) return rc;
+    if (n_patches < 0 || n_patches > NLOS_MAX_PATCHES || adjoint_rows(p->n_bins) < 1) return NLOS_EINVAL;
+    *bytes = (size_t)adjoint_split(p, n_patches) * (size_t)n_patches * nlos::kAdjStride * sizeof(double);
+    return NLOS_OK;
+}
+
+int nlos_adjoint(const nlos_params* p, const float* patches, int32_t n_patches, const int32_t* n_active,
+                 const float* grad_out, float* grad_patches, void* ws, size_t ws_bytes, void* stream)
+{
+    nlos::SmoothArgs a;
+    int rc = smooth_setup(p, patches, n_patches, n_active, &a);
+    if (rc != NLOS_OK) return rc;
+    if (!grad_out || !aligned(grad_out, 16) || !grad_patches || !aligned(grad_patches, 16)) return NLOS_EINVAL;
+    const int rows = adjoint_rows(p->n_bins);
+    if (rows < 1) return NLOS_EINVAL;
+    size_t need = 0;
+    rc = nlos_adjoint_workspace_bytes(p, n_patches, &need);
+    if (rc != NLOS_OK) return rc;
+    if (ws_bytes < need) return NLOS_ENOSPC;
+    if (need > 0 && (!ws || !aligned(ws, 16))) return NLOS_EINVAL;
+    const int dev = device_check();
+    if (dev != NLOS_OK) return dev;
+    a.grad_out = grad_out;
+    a.partial = static_cast<double*>(ws);
+    a.n_split = adjoint_split(p, n_patches);
+    a.rows = rows;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t pbk = ((int64_t)n_patches + nlos::kBlock - 1) / nlos::kBlock;
+    hipError_t e = nlos::launch_adjoint(a, pbk, adjoint_lds(rows, p->n_bins), st);
+    if (e != hipSuccess) return hip_fail(e);
+    e = nlos::launch_adjoint_reduce(a, grad_patches, st);
+    return e == hipSuccess ? NLOS_OK : hip_fail(e);
+}
+
+int nlos_patches_adjoint_workspace_bytes(const nlos_grid* g, size_t* bytes)
+{
+    if (!grid_ok(g) || !bytes) return NLOS_EINVAL;
+    if ((int64_t)g->nx * g->ny > NLOS_MAX_PATCHES) return NLOS_EINVAL;
+    *bytes = (size_t)3 * (size_t)g->nx * (size_t)g->ny * sizeof(float);
+    return NLOS_OK;
+}
+
+int nlos_patches_adjoint(const nlos_grid* g, const float* depth, const float* albedo, uint32_t flags,
+                         const float* patches, const int32_t* n_active, const float* grad_patches,
+                         float* grad_depth, float* grad_albedo, void* ws, size_t ws_bytes, void* stream)
+{
+    size_t need = 0;
+    int rc = nlos_patches_adjoint_workspace_bytes(g, &need);
+    if (rc != NLOS_OK) return rc;
+    if (!depth || !patches || !grad_patches || !grad_depth || (flags & ~NLOS_F_COSINES) != 0) return NLOS_EINVAL;
+    if (!aligned(patches, 16) || !aligned(grad_patches, 16) || !aligned(depth, 4) || !aligned(grad_depth, 4) ||
+        (albedo && !aligned(albedo, 4)) || (grad_albedo && !aligned(grad_albedo, 4)) ||
+        (n_active && !aligned(n_active, 4)))
+        return NLOS_EINVAL;
+    if (ws_bytes < need) return NLOS_ENOSPC;
+    if (!ws || !aligned(ws, 4)) return NLOS_EINVAL;
+    const int dev = device_check();
+    if (dev != NLOS_OK) return dev;
+    nlos::GradMapArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.depth = depth;
+    a.albedo = albedo;
+    a.patches = reinterpret_cast<const float4*>(patches);
+    a.n_active = n_active;
+    a.n_cap = (int32_t)((int64_t)g->nx * g->ny);
+    a.grad_rec = grad_patches;
+    a.grad_depth = grad_depth;
+    a.grad_albedo = grad_albedo;
+    a.scratch = static_cast<float*>(ws);
+    a.ax = axis(g->half_x, g->cx, g->nx);
+    a.ay = axis(g->half_y, g->cy, g->ny);
+    a.hx = (float)a.ax.step;
+    a.hy = (float)a.ay.step;
+    a.cosines = (flags & NLOS_F_COSINES) ? 1 : 0;
+    const hipError_t e = nlos::launch_grad_maps(a, (hipStream_t)stream);
+    return e == hipSuccess ? NLOS_OK : hip_fail(e);
 }
 
 int nlos_debug_bins(const nlos_params* p, const float* patches, int32_t n_patches, const int32_t* n_active,

@@ -97,6 +97,49 @@ struct GeomList {
     int32_t n;
 };
 
+// Smooth time response (continuous Gaussian) and its adjoint, confocal.
+struct SmoothArgs {
+    const float4* patches;
+    const int32_t* n_active;   // nullable
+    int32_t n_cap;
+    float* out;                // forward: [S][T]
+    const float* grad_out;     // adjoint: upstream gradient [S][T]
+    double* partial;           // adjoint: [n_split][n_cap][5] per-split record gradients
+    Axis rx, ry;
+    double cx, cy, s;          // device position
+    double inv;                // bins per metre
+    float sigma;               // bins
+    float norm;                // 1 / (sigma sqrt(2 pi))
+    float inv_s2;              // 1 / sigma^2
+    float c1;                  // exp(-1 / sigma^2)
+    int32_t T;
+    int32_t Rs;                // support radius, bins
+    int32_t tiles_x, tiles_y;  // forward: scan tiles
+    int32_t n_split;           // forward: patch ranges per tile; adjoint: scan ranges
+    int32_t stride;            // forward: u64 bins per LDS row
+    int32_t rows;              // adjoint: rows staged in LDS at a time
+    int32_t atomic_out;
+    int32_t cosines;
+    ChunkStat* stats;
+    int32_t n_stats;
+};
+
+// Record gradients -> map gradients (depth-stencil adjoint).
+struct GradMapArgs {
+    const float* depth;
+    const float* albedo;       // nullable -> 0.5
+    const float4* patches;
+    const int32_t* n_active;   // nullable
+    int32_t n_cap;
+    const float* grad_rec;     // [n_cap][8]: d/d(pz, a, n_x, n_y, n_z) at 2..6
+    float* grad_depth;
+    float* grad_albedo;        // nullable
+    float* scratch;            // [3][nx * ny]: d/dpz, d/dD_x, d/dD_y per pixel
+    Axis ax, ay;
+    float hx, hy;
+    int32_t cosines;
+};
+
 // Debug/test hook arguments.
 struct DebugArgs {
     FwdArgs f;
@@ -129,6 +172,12 @@ hipError_t launch_forward(const FwdArgs& a, const Plan& plan, bool confocal, hip
 hipError_t launch_stats(const FwdArgs& a, ChunkStat* stats, hipStream_t st);
 hipError_t launch_fill(float* out, size_t n, hipStream_t st);
 hipError_t launch_debug(const DebugArgs& a, hipStream_t st);
+
+hipError_t launch_smooth(const SmoothArgs& a, int tx, int ty, int64_t n_blocks, size_t lds, hipStream_t st);
+hipError_t launch_adjoint(const SmoothArgs& a, int64_t patch_blocks, size_t lds, hipStream_t st);
+hipError_t launch_adjoint_reduce(const SmoothArgs& a, float* grad_rec, hipStream_t st);
+hipError_t launch_grad_maps(const GradMapArgs& g, hipStream_t st);
+constexpr int kAdjStride = 5;   // doubles per record in the adjoint partials
 
 // Batched launches (one launch each over all requests of the list).
 hipError_t launch_geometry_batch(const GeomList& g, int64_t n_blocks, hipStream_t st);

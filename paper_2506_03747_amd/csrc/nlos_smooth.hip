@@ -1,0 +1,503 @@
+// Smooth time response and its adjoint (confocal), gfx950.
+//
+// The hard forward bins each pair's arrival; its gradient with respect to
+// depth is zero almost everywhere.  The smooth forward gives each pair the
+// continuous Gaussian response of the detector jitter (Section 2, temporal
+// jitter; sigma = FWHM / (2 sqrt(2 ln 2)) / dt in bins):
+//     tau_s[s][k] = sum_p w_sp N(k + 1/2 - u_sp),  |k - floor(u_sp)| <= Rs,
+// Rs = ceil(6 sigma), N the normalised Gaussian.  The weight w and arrival u
+// are those of the hard forward (Eq. (1) with the cosine and stand-off
+// extensions).  Arrivals are computed in fp64: an fp32 distance puts u off by
+// ~1e-4 bins at u ~ 1000, which would move the Gaussian samples by ~1e-5.
+//
+// k_smooth       forward: a workgroup owns a tile of scan points (LDS rows of
+//                64-bit fixed-point bins), a lane one patch; 2 Rs + 1 LDS
+//                adds per pair, Gaussian samples by a three-exponential
+//                recurrence.
+// k_adjoint      gather: a lane owns one patch and loops over a range of scan
+//                points whose upstream-gradient rows are staged in LDS; per
+//                pair G0 = sum g N(x), G1 = sum g (x / sigma^2) N(x) give
+//                dL/dw = G0 and dL/du = w G1; per-record partial gradients
+//                (fp64) per scan range, summed in a fixed order afterwards.
+// k_grad_scatter / k_grad_gather   record gradients -> depth and albedo maps
+//                through the central-difference normals and true areas.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "nlos_device.h"
+#include "nlos_internal.h"
+
+namespace nlos {
+
+namespace {
+
+typedef unsigned long long u64s;
+
+__device__ __forceinline__ int smooth_active(const SmoothArgs& a)
+{
+    int n = a.n_cap;
+    if (a.n_active) {
+        n = *a.n_active;
+        n = n < 0 ? 0 : (n > a.n_cap ? a.n_cap : n);
+    }
+    return n;
+}
+
+// Weight, arrival and their patch derivatives of one confocal pair.
+struct PairS {
+    float w;        // weight
+    float w_a;      // w / a
+    float dw_dz;    // dw / dpz
+    float dwn;      // dw / dn = dwn * (dx, dy, pz)
+    float du_dz;    // du / dpz (bins per metre)
+    double u;       // arrival (bins), fp64
+};
+
+__device__ __forceinline__ PairS pair_smooth(float4 A, float4 B, float wx, float wy, double o, float gg,
+                                             double inv, bool cosines, bool derivs)
+{
+    PairS r;
+    const float dx = A.x - wx, dy = A.y - wy, pz = A.z;
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, pz * pz));
+    const float ri2 = 1.0f / r2;
+    const float ri4 = ri2 * ri2;
+    // fp64 arrival from the same fp32 coordinates: ((r + r) + o) * inv
+    const double ex = (double)A.x - (double)wx, ey = (double)A.y - (double)wy, ez = (double)pz;
+    const double rd = sqrt((ex * ex + ey * ey) + ez * ez);
+    r.u = ((rd + rd) + o) * inv;
+    if (cosines) {
+        // w = a gg pz^2 c^2 / r^8, c = -n.(p - w) clamped at 0
+        const float c = fmaxf(-(B.x * dx + B.y * dy + B.z * pz), 0.f);
+        const float k = gg * pz * pz * ri4 * ri4;
+        r.w_a = k * c * c;
+        r.w = A.w * r.w_a;
+        if (derivs) {
+            r.dw_dz = A.w * k * (2.f * c * c / pz - 2.f * c * B.z) - r.w * 8.f * pz * ri2;
+            r.dwn = -2.f * A.w * k * c;
+        }
+    } else {
+        r.w_a = gg * ri4;
+        r.w = A.w * r.w_a;
+        if (derivs) {
+            r.dw_dz = -r.w * 4.f * pz * ri2;
+            r.dwn = 0.f;
+        }
+    }
+    if (derivs) r.du_dz = (float)inv * 2.f * pz * sqrtf(ri2);
+    return r;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Smooth forward.
+template <int TX, int TY, bool COS>
+__global__ void __launch_bounds__(kBlock) k_smooth(const SmoothArgs a)
+{
+    constexpr int NH = TX * TY;
+    extern __shared__ __align__(16) unsigned char smem[];
+    u64s* hist = reinterpret_cast<u64s*>(smem);
+    double* so = reinterpret_cast<double*>(smem + (size_t)NH * a.stride * 8);
+    float* sg = reinterpret_cast<float*>(so + NH);
+    float* red = sg + NH;
+    const int n_act = smooth_active(a);
+    const int split = (int)(blockIdx.x % a.n_split);
+    const int tile = (int)(blockIdx.x / a.n_split);
+    const int tx0 = (tile / a.tiles_y) * TX, ty0 = (tile % a.tiles_y) * TY;
+    const int chunk = (n_act + a.n_split - 1) / a.n_split;
+    const int pb = min(n_act, split * chunk), pe = min(n_act, pb + chunk);
+
+    for (int i = threadIdx.x; i < NH * a.stride; i += blockDim.x) hist[i] = 0ull;
+    if (threadIdx.x < NH) {
+        const int j = threadIdx.x;
+        const int ix = min(tx0 + j / TY, a.rx.n - 1), iy = min(ty0 + j % TY, a.ry.n - 1);
+        double off, g;
+        device_leg(canon(a.rx, ix), canon(a.ry, iy), a.cx, a.cy, a.s, &off, &g);
+        so[j] = off + off;
+        sg[j] = (float)(g * g);
+    }
+    float wx[TX], wy[TY];
+#pragma unroll
+    for (int c = 0; c < TX; ++c) wx[c] = canon(a.rx, min(tx0 + c, a.rx.n - 1));
+#pragma unroll
+    for (int r = 0; r < TY; ++r) wy[r] = canon(a.ry, min(ty0 + r, a.ry.n - 1));
+    // weight bound over the record summaries: a_max / r_min^4 (every cosine
+    // factor and stand-off weight is at most 1) -> fixed-point scale
+    float wb = 0.f;
+    {
+        const float x0 = fminf(wx[0], wx[TX - 1]), x1 = fmaxf(wx[0], wx[TX - 1]);
+        const float y0 = fminf(wy[0], wy[TY - 1]), y1 = fmaxf(wy[0], wy[TY - 1]);
+        for (int i = threadIdx.x; i < a.n_stats; i += blockDim.x) {
+            const ChunkStat c = a.stats[i];
+            if (c.count <= 0) continue;
+            const float ddx = fmaxf(fmaxf(x0 - c.x1, c.x0 - x1), 0.f);
+            const float ddy = fmaxf(fmaxf(y0 - c.y1, c.y0 - y1), 0.f);
+            const float r2 = fmaf(ddx, ddx, fmaf(ddy, ddy, c.z0 * c.z0));
+            wb = fmaxf(wb, c.amax / (r2 * r2));
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) wb = fmaxf(wb, __shfl_xor(wb, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = wb;
+    __syncthreads();
+    float W = 0.f;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) W = fmaxf(W, red[w]);
+    const float s = W > 0.f ? 2147483648.0f / (W * a.norm) : 1.0f;   // increments <= 2^31
+    const float sn = s * a.norm;
+    const int T = a.T, Rs = a.Rs;
+    const float inv_s2 = a.inv_s2, c1 = a.c1;
+
+    for (int base = pb; base < pe; base += blockDim.x) {
+        const int p = base + (int)threadIdx.x;
+        if (p >= pe) continue;
+        const float4 A = a.patches[2 * (size_t)p];
+        const float4 B = a.patches[2 * (size_t)p + 1];
+#pragma unroll
+        for (int c = 0; c < TX; ++c) {
+#pragma unroll
+            for (int r = 0; r < TY; ++r) {
+                const int j = c * TY + r;
+                if (tx0 + c >= a.rx.n || ty0 + r >= a.ry.n) continue;
+                const PairS q = pair_smooth(A, B, wx[c], wy[r], so[j], sg[j], a.inv, COS, false);
+                const double k0d = floor(q.u);
+                if (q.w <= 0.f || k0d + Rs < 0.0 || k0d - Rs > (double)(T - 1)) continue;
+                const int k0 = (int)k0d;
+                const float f = (float)(q.u - k0d);
+                const float x0 = 0.5f - f;
+                const float amp = q.w * sn;
+                u64s* row = hist + (size_t)j * a.stride;
+                // centre and upward: e_{m+1} = e_m q_m, q_{m+1} = q_m c1
+                float e = __expf(-0.5f * x0 * x0 * inv_s2);
+                const float e0 = e;
+                float qm = __expf(-(1.0f - f) * inv_s2);
+                for (int m = 0; m <= Rs; ++m) {
+                    const int k = k0 + m;
+                    if (k >= T) break;
+                    if (k >= 0) {
+                        const uint32_t inc = (uint32_t)fmaf(amp, e, 0.5f);
+                        if (inc) __hip_atomic_fetch_add(row + k, (u64s)inc, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                    e *= qm;
+                    qm *= c1;
+                }
+                // downward: e_{m-1} = e_m d_m, d_{m-1} = d_m c1
+                e = e0;
+                float dm = __expf(-f * inv_s2);
+                for (int m = -1; m >= -Rs; --m) {
+                    e *= dm;
+                    dm *= c1;
+                    const int k = k0 + m;
+                    if (k < 0) break;
+                    if (k < T) {
+                        const uint32_t inc = (uint32_t)fmaf(amp, e, 0.5f);
+                        if (inc) __hip_atomic_fetch_add(row + k, (u64s)inc, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const float inv_s = 1.0f / s;
+    for (int i = threadIdx.x; i < NH * T; i += blockDim.x) {
+        const int j = i / T, t = i - j * T;
+        const int ix = tx0 + j / TY, iy = ty0 + j % TY;
+        if (ix >= a.rx.n || iy >= a.ry.n) continue;
+        const u64s x = hist[(size_t)j * a.stride + t];
+        const float v = fmaf((float)(uint32_t)(x >> 32), 4294967296.0f, (float)(uint32_t)x) * inv_s;
+        float* o = a.out + ((size_t)ix * a.ry.n + iy) * (size_t)T + t;
+        if (a.atomic_out)
+            unsafeAtomicAdd(o, v);
+        else
+            *o = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint gather.
+template <bool COS>
+__global__ void __launch_bounds__(kBlock) k_adjoint(const SmoothArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int T = a.T, Rs = a.Rs, NR = a.rows;
+    float* rowbuf = reinterpret_cast<float*>(smem);                        // [NR][T]
+    double* so = reinterpret_cast<double*>(smem + (((size_t)NR * T * 4 + 15) & ~(size_t)15));
+    float* swx = reinterpret_cast<float*>(so + NR);
+    float* swy = swx + NR;
+    float* sg = swy + NR;
+    const int n_act = smooth_active(a);
+    const int p = (int)blockIdx.x * (int)blockDim.x + (int)threadIdx.x;
+    const int split = (int)blockIdx.y;
+    const int S = a.rx.n * a.ry.n;
+    const int per = (S + a.n_split - 1) / a.n_split;
+    const int s0 = min(S, split * per), s1 = min(S, s0 + per);
+    const bool live = p < n_act;
+    float4 A = make_float4(0.f, 0.f, 1.f, 0.f), B = make_float4(0.f, 0.f, -1.f, 0.f);
+    if (live) {
+        A = a.patches[2 * (size_t)p];
+        B = a.patches[2 * (size_t)p + 1];
+    }
+    double gz = 0.0, ga = 0.0, gnx = 0.0, gny = 0.0, gnz = 0.0;
+    const float inv_s2 = a.inv_s2, c1 = a.c1;
+
+    for (int j0 = s0; j0 < s1; j0 += NR) {
+        const int nr = min(NR, s1 - j0);
+        __syncthreads();
+        // stage rows [j0, j0 + nr) of the upstream gradient (float4 when aligned)
+        if ((T & 3) == 0) {
+            const float4* src = reinterpret_cast<const float4*>(a.grad_out + (size_t)j0 * T);
+            float4* dst = reinterpret_cast<float4*>(rowbuf);
+            for (int i = threadIdx.x; i < nr * (T >> 2); i += blockDim.x) dst[i] = src[i];
+        } else {
+            const float* src = a.grad_out + (size_t)j0 * T;
+            for (int i = threadIdx.x; i < nr * T; i += blockDim.x) rowbuf[i] = src[i];
+        }
+        if (threadIdx.x < nr) {
+            const int h = j0 + threadIdx.x;
+            const float wx = canon(a.rx, h / a.ry.n), wy = canon(a.ry, h % a.ry.n);
+            double off, g;
+            device_leg(wx, wy, a.cx, a.cy, a.s, &off, &g);
+            so[threadIdx.x] = off + off;
+            swx[threadIdx.x] = wx;
+            swy[threadIdx.x] = wy;
+            sg[threadIdx.x] = (float)(g * g);
+        }
+        __syncthreads();
+        if (!live) continue;
+        for (int jj = 0; jj < nr; ++jj) {
+            const PairS q = pair_smooth(A, B, swx[jj], swy[jj], so[jj], sg[jj], a.inv, COS, true);
+            const double k0d = floor(q.u);
+            if (k0d + Rs < 0.0 || k0d - Rs > (double)(T - 1)) continue;
+            const int k0 = (int)k0d;
+            const float f = (float)(q.u - k0d);
+            const float* g = rowbuf + (size_t)jj * T;
+            // G0 = sum g N(x), G1 = sum g x N(x), x = m + 1/2 - f (N without
+            // its normalisation; applied below)
+            float G0 = 0.f, G1 = 0.f;
+            const float x0 = 0.5f - f;
+            float e = __expf(-0.5f * x0 * x0 * inv_s2);
+            const float e0 = e;
+            float qm = __expf(-(1.0f - f) * inv_s2);
+            for (int m = 0; m <= Rs; ++m) {
+                const int k = k0 + m;
+                if (k >= T) break;
+                if (k >= 0) {
+                    const float gv = g[k] * e;
+                    G0 += gv;
+                    G1 = fmaf(gv, x0 + (float)m, G1);
+                }
+                e *= qm;
+                qm *= c1;
+            }
+            e = e0;
+            float dm = __expf(-f * inv_s2);
+            for (int m = -1; m >= -Rs; --m) {
+                e *= dm;
+                dm *= c1;
+                const int k = k0 + m;
+                if (k < 0) break;
+                if (k < T) {
+                    const float gv = g[k] * e;
+                    G0 += gv;
+                    G1 = fmaf(gv, x0 + (float)m, G1);
+                }
+            }
+            G0 *= a.norm;
+            G1 *= a.norm * inv_s2;
+            // dL/dw = G0, dL/du = w G1
+            const float dz = fmaf(G0, q.dw_dz, q.w * G1 * q.du_dz);
+            gz += (double)dz;
+            ga += (double)(G0 * q.w_a);
+            if (COS) {
+                const float gn = G0 * q.dwn;
+                gnx += (double)(gn * (A.x - swx[jj]));
+                gny += (double)(gn * (A.y - swy[jj]));
+                gnz += (double)(gn * A.z);
+            }
+        }
+    }
+    if (live) {
+        double* o = a.partial + ((size_t)split * a.n_cap + p) * kAdjStride;
+        o[0] = gz;
+        o[1] = ga;
+        o[2] = gnx;
+        o[3] = gny;
+        o[4] = gnz;
+    }
+}
+
+// Sum the per-split partials in split order -> grad_rec [n_cap][8] floats
+// {0, 0, dL/dpz, dL/da, dL/dn_x, dL/dn_y, dL/dn_z, 0}; zeros past n_active.
+__global__ void __launch_bounds__(256) k_adjoint_reduce(const SmoothArgs a, float* grad_rec)
+{
+    const int n_act = smooth_active(a);
+    const int p = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (p >= a.n_cap) return;
+    double g[kAdjStride] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (p < n_act) {
+        for (int sp = 0; sp < a.n_split; ++sp) {
+            const double* q = a.partial + ((size_t)sp * a.n_cap + p) * kAdjStride;
+#pragma unroll
+            for (int k = 0; k < kAdjStride; ++k) g[k] += q[k];
+        }
+    }
+    float4* o = reinterpret_cast<float4*>(grad_rec + (size_t)p * 8);
+    o[0] = make_float4(0.f, 0.f, (float)g[0], (float)g[1]);
+    o[1] = make_float4((float)g[2], (float)g[3], (float)g[4], 0.f);
+}
+
+// ---------------------------------------------------------------------------
+// Record gradients -> maps.
+__device__ __forceinline__ float deriv_f(const float* d, int n, int i, int64_t stride, float h)
+{
+    if (n < 2) return 0.f;
+    if (i == 0) return (d[stride] - d[0]) / h;
+    if (i == n - 1) return (d[0] - d[-stride]) / h;
+    return (d[stride] - d[-stride]) / (2.f * h);
+}
+
+__global__ void k_grad_zero(const GradMapArgs g, int64_t npx)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npx; i += stride) {
+        g.scratch[i] = 0.f;
+        g.scratch[npx + i] = 0.f;
+        g.scratch[2 * npx + i] = 0.f;
+        if (g.grad_albedo) g.grad_albedo[i] = 0.f;
+    }
+}
+
+// Per record: dL/dpz as is; dL/dD_x, dL/dD_y through n = (D_x, D_y, -1)/len
+// and a = rho dx dy len (cosines); dL/drho = dL/da * area.  Written to the
+// record's own pixel, so no two records collide.
+__global__ void __launch_bounds__(256) k_grad_scatter(const GradMapArgs g, int64_t npx)
+{
+    int n = g.n_cap;
+    if (g.n_active) {
+        n = *g.n_active;
+        n = n < 0 ? 0 : (n > g.n_cap ? g.n_cap : n);
+    }
+    const int p = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (p >= n) return;
+    const int idx = __float_as_int(g.patches[2 * (size_t)p + 1].w);
+    const int ix = idx / g.ay.n, iy = idx % g.ay.n;
+    const float* D = g.depth + idx;
+    const float gx = deriv_f(D, g.ax.n, ix, g.ay.n, g.hx);
+    const float gy = deriv_f(D, g.ay.n, iy, 1, g.hy);
+    const float len = sqrtf(1.f + gx * gx + gy * gy);
+    const float rho = g.albedo ? g.albedo[idx] : 0.5f;
+    const float* q = g.grad_rec + (size_t)p * 8;
+    const float dpz = q[2], da = q[3], dnx = q[4], dny = q[5], dnz = q[6];
+    const float area = g.hx * g.hy * (g.cosines ? len : 1.f);
+    if (g.grad_albedo) g.grad_albedo[idx] = da * area;
+    g.scratch[idx] = dpz;
+    if (g.cosines) {
+        const float il = 1.f / len;
+        const float il3 = il * il * il;
+        const float dot = dnx * gx + dny * gy - dnz;
+        const float darea = da * rho * g.hx * g.hy * il;
+        g.scratch[npx + idx] = dnx * il - dot * gx * il3 + darea * gx;
+        g.scratch[2 * npx + idx] = dny * il - dot * gy * il3 + darea * gy;
+    }
+}
+
+// Coefficient of D[i] in the derivative at sample i' (|i - i'| <= 1) of an
+// axis of n samples with spacing h (central inside, one-sided at borders).
+__device__ __forceinline__ float stencil(int n, int ip, int i, float h)
+{
+    if (n < 2) return 0.f;
+    if (ip == 0) return (i == 1 ? 1.f : (i == 0 ? -1.f : 0.f)) / h;
+    if (ip == n - 1) return (i == n - 1 ? 1.f : (i == n - 2 ? -1.f : 0.f)) / h;
+    return (i == ip + 1 ? 1.f : (i == ip - 1 ? -1.f : 0.f)) / (2.f * h);
+}
+
+__global__ void __launch_bounds__(256) k_grad_gather(const GradMapArgs g, int64_t npx)
+{
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= npx) return;
+    const int nx = g.ax.n, ny = g.ay.n;
+    const int ix = (int)(idx / ny), iy = (int)(idx % ny);
+    float v = g.scratch[idx];
+    const float* sx = g.scratch + npx;
+    const float* sy = g.scratch + 2 * npx;
+    for (int d = -1; d <= 1; ++d) {
+        const int jx = ix + d;
+        if (jx >= 0 && jx < nx) v = fmaf(sx[(int64_t)jx * ny + iy], stencil(nx, jx, ix, g.hx), v);
+        const int jy = iy + d;
+        if (jy >= 0 && jy < ny) v = fmaf(sy[(int64_t)ix * ny + jy], stencil(ny, jy, iy, g.hy), v);
+    }
+    g.grad_depth[idx] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+template <int TX, int TY>
+static hipError_t launch_smooth_shape(const SmoothArgs& a, int64_t n_blocks, size_t lds, hipStream_t st)
+{
+    const void* k = a.cosines ? (const void*)k_smooth<TX, TY, true> : (const void*)k_smooth<TX, TY, false>;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (a.cosines)
+        hipLaunchKernelGGL((k_smooth<TX, TY, true>), dim3((unsigned)n_blocks), dim3(kBlock), lds, st, a);
+    else
+        hipLaunchKernelGGL((k_smooth<TX, TY, false>), dim3((unsigned)n_blocks), dim3(kBlock), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_smooth(const SmoothArgs& a, int tx, int ty, int64_t n_blocks, size_t lds, hipStream_t st)
+{
+    if (n_blocks <= 0) return hipSuccess;
+    if (n_blocks > 0x7fffffff) return hipErrorInvalidValue;
+    if (tx == 4 && ty == 4) return launch_smooth_shape<4, 4>(a, n_blocks, lds, st);
+    if (tx == 4 && ty == 2) return launch_smooth_shape<4, 2>(a, n_blocks, lds, st);
+    if (tx == 2 && ty == 2) return launch_smooth_shape<2, 2>(a, n_blocks, lds, st);
+    if (tx == 2 && ty == 1) return launch_smooth_shape<2, 1>(a, n_blocks, lds, st);
+    if (tx == 1 && ty == 1) return launch_smooth_shape<1, 1>(a, n_blocks, lds, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_adjoint(const SmoothArgs& a, int64_t patch_blocks, size_t lds, hipStream_t st)
+{
+    if (patch_blocks > 0) {
+        if (patch_blocks > 0x7fffffff || a.n_split > 65535) return hipErrorInvalidValue;
+        const void* k = a.cosines ? (const void*)k_adjoint<true> : (const void*)k_adjoint<false>;
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        const dim3 grid((unsigned)patch_blocks, (unsigned)a.n_split);
+        if (a.cosines)
+            hipLaunchKernelGGL(k_adjoint<true>, grid, dim3(kBlock), lds, st, a);
+        else
+            hipLaunchKernelGGL(k_adjoint<false>, grid, dim3(kBlock), lds, st, a);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_adjoint_reduce(const SmoothArgs& a, float* grad_rec, hipStream_t st)
+{
+    if (a.n_cap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adjoint_reduce, dim3((unsigned)((a.n_cap + 255) / 256)), dim3(256), 0, st, a, grad_rec);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_maps(const GradMapArgs& g, hipStream_t st)
+{
+    const int64_t npx = (int64_t)g.ax.n * g.ay.n;
+    int64_t zb = (npx + 255) / 256;
+    if (zb > 8192) zb = 8192;
+    hipLaunchKernelGGL(k_grad_zero, dim3((unsigned)zb), dim3(256), 0, st, g, npx);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (g.n_cap > 0) {
+        hipLaunchKernelGGL(k_grad_scatter, dim3((unsigned)((g.n_cap + 255) / 256)), dim3(256), 0, st, g, npx);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_grad_gather, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, st, g, npx);
+    return hipGetLastError();
+}
+
+}  // namespace nlos

@@ -150,3 +150,40 @@ def pin_grad_depth_fd(lib):
 
 
 SMOOTH_PINS = [pin_smooth_single_patch, pin_smooth_mass, pin_grad_albedo_fd, pin_grad_depth_fd]
+
+
+def pin_adjoint_records_fd(lib):
+    """Adjoint identity on the records themselves: for a random upstream
+    gradient G, sum(G * dtau_s/dq) by central differences of the smooth
+    forward in each record field q (pz with Richardson; a and n enter
+    polynomially of degree <= 2, so their differences are exact up to
+    rounding) equals the record gradient."""
+    rng = np.random.default_rng(5)
+    for kw in (dict(seed=41), dict(seed=42, cosines=False, standoff_m=0.5), dict(seed=43, laser=(2, 2))):
+        sc = smooth_scene(**kw)
+        rec = oracle.patches_f64(sc, lib=lib)
+        G = rng.standard_normal((sc.n_laser * sc.n_scan, sc.n_bins))
+        present = np.nonzero(rec[:, 7])[0]
+        sub = present[[0, len(present) // 2, len(present) - 1]]
+        gr = oracle.adjoint_records(sc, G, rec, subset=sub, lib=lib)
+
+        def dot(r):
+            return float(np.sum(G * oracle.forward_smooth(sc, r, lib=lib)))
+
+        for i, p in enumerate(sub):
+            for field, h in ((2, 2e-5), (3, 1e-3), (4, 1e-2), (5, 1e-2), (6, 1e-2)):
+                if field >= 4 and not sc.cosines:
+                    assert gr[i, field] == 0.0
+                    continue
+
+                def cd(hh):
+                    rp, rm = rec.copy(), rec.copy()
+                    rp[p, field] += hh
+                    rm[p, field] -= hh
+                    return (dot(rp) - dot(rm)) / (2 * hh)
+                fd = (4 * cd(h / 2) - cd(h)) / 3 if field == 2 else cd(h)
+                scale = np.abs(gr[:, 2:7]).max()
+                assert abs(fd - gr[i, field]) <= 2e-6 * scale, (kw, p, field, fd, gr[i, field])
+
+
+SMOOTH_PINS.append(pin_adjoint_records_fd)

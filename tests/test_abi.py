@@ -26,7 +26,7 @@ def declared_functions():
 
 def test_exports_every_declared_symbol(nat):
     names = declared_functions()
-    assert len(names) == 12, names
+    assert len(names) == 18, names
     for n in names:
         assert hasattr(nat.lib(), n), n
     bound = {s[0] for s in nat.SIGNATURES}
@@ -214,3 +214,34 @@ def test_python_layer_rejects_cpu_tensors(nat):
         nl.forward(p, torch.zeros(16, 8))
     with pytest.raises(TypeError):
         nl.patches_from_depth(torch.zeros(4, 4), dict(nx=4, ny=4, half_x=0.5, half_y=0.5))
+
+
+def test_smooth_and_adjoint_checks(nat):
+    """Host-side checks of the smooth forward and the adjoints."""
+    L = nat.lib()
+    p = _params(nat)
+    need = C.c_size_t(0)
+    assert L.nlos_forward_smooth_workspace_bytes(C.byref(p), 5000, C.byref(need)) == 0
+    assert need.value >= 20 * 32
+    assert L.nlos_forward_smooth(C.byref(p), FAKE, 5000, None, FAKE, FAKE, need.value - 1, None) == nat.NLOS_ENOSPC
+    nojit = _params(nat, fwhm_ps=0.0)                 # the smooth response needs a jitter width
+    assert L.nlos_forward_smooth(C.byref(nojit), FAKE, 16, None, FAKE, FAKE, 1 << 20, None) == nat.NLOS_EINVAL
+    nc = _params(nat)
+    nc.laser = nat.Grid(2, 2, 0.5, 0.5, 0.0, 0.0)      # confocal only
+    assert L.nlos_forward_smooth(C.byref(nc), FAKE, 16, None, FAKE, FAKE, 1 << 20, None) == nat.NLOS_EINVAL
+    assert L.nlos_adjoint_workspace_bytes(C.byref(nc), 16, C.byref(need)) == nat.NLOS_EINVAL
+    assert L.nlos_adjoint_workspace_bytes(C.byref(p), 5000, C.byref(need)) == 0
+    assert need.value >= 5000 * 5 * 8                 # fp64 partials per record and scan range
+    assert L.nlos_adjoint(C.byref(p), FAKE, 5000, None, FAKE, FAKE, FAKE, need.value - 1, None) == nat.NLOS_ENOSPC
+    assert L.nlos_adjoint(C.byref(p), FAKE, 5000, None, None, FAKE, FAKE, need.value, None) == nat.NLOS_EINVAL
+    assert L.nlos_adjoint(C.byref(p), FAKE, 5000, None, FAKE, C.c_void_p(0x10004), FAKE, need.value,
+                          None) == nat.NLOS_EINVAL
+    g = nat.Grid(64, 64, 0.5, 0.5, 0.0, 0.0)
+    assert L.nlos_patches_adjoint_workspace_bytes(C.byref(g), C.byref(need)) == 0
+    assert need.value == 3 * 4 * 64 * 64
+    assert L.nlos_patches_adjoint(C.byref(g), FAKE, None, 1, FAKE, None, FAKE, FAKE, None, FAKE, need.value - 1,
+                                  None) == nat.NLOS_ENOSPC
+    assert L.nlos_patches_adjoint(C.byref(g), FAKE, None, 3, FAKE, None, FAKE, FAKE, None, FAKE, need.value,
+                                  None) == nat.NLOS_EINVAL
+    assert L.nlos_patches_adjoint(C.byref(g), None, None, 1, FAKE, None, FAKE, FAKE, None, FAKE, need.value,
+                                  None) == nat.NLOS_EINVAL
