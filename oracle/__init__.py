@@ -86,6 +86,19 @@ def _bind(lib):
     lib.oracle_smooth_grad.restype = C.c_int32
     lib.oracle_adjoint_records.argtypes = [C.POINTER(Params), dp, C.c_int32, dp, C.c_void_p, C.c_int32, dp]
     lib.oracle_adjoint_records.restype = C.c_int32
+    u64p = C.POINTER(C.c_uint64)
+    lib.oracle_philox4x64.argtypes = [u64p, u64p, u64p]
+    lib.oracle_nx_exp.argtypes = [C.c_double]
+    lib.oracle_nx_exp.restype = C.c_double
+    lib.oracle_nx_log.argtypes = [C.c_double]
+    lib.oracle_nx_log.restype = C.c_double
+    lib.oracle_nx_logfact.argtypes = [C.c_double]
+    lib.oracle_nx_logfact.restype = C.c_double
+    lib.oracle_poisson_count.argtypes = [C.c_double, C.c_uint64, C.c_int64]
+    lib.oracle_poisson_count.restype = C.c_int64
+    lib.oracle_poisson_counts.argtypes = [dp, C.c_int64, C.c_uint64, C.c_void_p]
+    lib.oracle_noise_scale.argtypes = [C.c_void_p, C.c_int64, C.c_double, dp]
+    lib.oracle_poisson_noise.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_uint64, C.c_void_p]
     return lib
 
 
@@ -271,4 +284,45 @@ def adjoint_records(scene, G: np.ndarray, rec: np.ndarray | None = None, subset=
                                     None if sub is None else sub.ctypes.data, 0 if sub is None else n, _dptr(out))
     if rc != 0:
         raise ValueError("oracle_adjoint_records rejected its arguments")
+    return out
+
+
+NOISE_KEY1 = 0x4E4C4F53   # second key word of the noise generator
+
+
+def philox4x64(ctr, key, lib=None) -> np.ndarray:
+    """One Philox4x64-10 block (4 uint64) for counter ctr[4] and key key[2]."""
+    lib = lib or load()
+    c = np.ascontiguousarray(ctr, np.uint64)
+    k = np.ascontiguousarray(key, np.uint64)
+    o = np.zeros(4, np.uint64)
+    u64p = C.POINTER(C.c_uint64)
+    lib.oracle_philox4x64(c.ctypes.data_as(u64p), k.ctypes.data_as(u64p), o.ctypes.data_as(u64p))
+    return o
+
+
+def poisson_counts(lam, seed: int, lib=None) -> np.ndarray:
+    """Counts of the noise sampler for means lam (element i uses stream i)."""
+    lib = lib or load()
+    lm = np.ascontiguousarray(lam, np.float64).ravel()
+    k = np.zeros(lm.size, np.int64)
+    lib.oracle_poisson_counts(_dptr(lm), lm.size, C.c_uint64(seed), k.ctypes.data)
+    return k
+
+
+def noise_scale(tau: np.ndarray, nr_db: float, lib=None):
+    """(mean, population variance, sigma_n = Var / 10^(nr/10)) of an fp32 frame."""
+    lib = lib or load()
+    t = np.ascontiguousarray(tau, np.float32).ravel()
+    o = np.zeros(3, np.float64)
+    lib.oracle_noise_scale(t.ctypes.data, t.size, float(nr_db), _dptr(o))
+    return float(o[0]), float(o[1]), float(o[2])
+
+
+def poisson_noise(tau: np.ndarray, sigma_n: float, seed: int, lib=None) -> np.ndarray:
+    """Poisson(tau * sigma_n) / sigma_n elementwise, fp32, same shape."""
+    lib = lib or load()
+    t = np.ascontiguousarray(tau, np.float32)
+    out = np.zeros_like(t)
+    lib.oracle_poisson_noise(t.ctypes.data, t.size, float(sigma_n), C.c_uint64(seed), out.ctypes.data)
     return out

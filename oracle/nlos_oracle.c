@@ -644,3 +644,187 @@ int32_t oracle_smooth_grad(const oracle_params* prm, const oracle_grid* g, const
     free(rec); free(tau); free(gr); free(rx); free(lx);
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Poisson noise (Algorithm 1 step 2.4, after the blur of step 2.3):
+ *   T = Poisson(tau * sigma_n) / sigma_n,  sigma_n = Var(tau) / 10^(nr / 10),
+ * Var the population variance over the whole frame.  Random numbers come
+ * from the counter-based Philox4x64-10 generator (Salmon, Moraes, Dror and
+ * Shaw, SC 2011), so any element can be drawn independently: uniform t of
+ * element i is word t mod 4 of Philox(counter (i, t / 4, 0, 0), key
+ * (seed, 0x4e4c4f53)), mapped to [0, 1) by its top 53 bits.  Counts come from
+ * inversion by sequential search for lambda < 10 and from Hormann's
+ * transformed rejection with squeeze (PTRS, 1993) above.  exp, log and
+ * log k! are evaluated by the fixed recipes below from IEEE basic operations
+ * only, so that an implementation doing the same operations in the same
+ * order reaches the same integer decisions.
+ * ------------------------------------------------------------------------ */
+
+static void philox_mulhilo(uint64_t a, uint64_t b, uint64_t* hi, uint64_t* lo)
+{
+    const unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+    *hi = (uint64_t)(p >> 64);
+    *lo = (uint64_t)p;
+}
+
+/* Philox4x64 with 10 rounds: each round multiplies words 0 and 2 by the two
+ * round constants and mixes high halves, the other words and the key; the
+ * key is advanced by the two Weyl constants between rounds. */
+void oracle_philox4x64(const uint64_t ctr_in[4], const uint64_t key_in[2], uint64_t out[4])
+{
+    uint64_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint64_t k0 = key_in[0], k1 = key_in[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B97F4A7C15ull;
+            k1 += 0xBB67AE8584CAA73Bull;
+        }
+        uint64_t hi0, lo0, hi1, lo1;
+        philox_mulhilo(0xD2E7470EE14C6C93ull, c0, &hi0, &lo0);
+        philox_mulhilo(0xCA5A826395121157ull, c2, &hi1, &lo1);
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+static double noise_uniform(uint64_t seed, int64_t i, int t)
+{
+    const uint64_t ctr[4] = {(uint64_t)i, (uint64_t)(t / 4), 0, 0};
+    const uint64_t key[2] = {seed, 0x4e4c4f53ull};
+    uint64_t o[4];
+    oracle_philox4x64(ctr, key, o);
+    return (double)(o[t % 4] >> 11) * (1.0 / 9007199254740992.0);
+}
+
+#define NX_LN2_HI 6.93147180369123816490e-01
+#define NX_LN2_LO 1.90821492927058770002e-10
+#define NX_LOG2E 1.44269504088896338700e+00
+
+/* e^x: x = n ln2 + r, |r| <= ln2 / 2, e^r by its Taylor polynomial to r^13
+ * (Horner-free running term), scaled by 2^n; 0 below -708. */
+double oracle_nx_exp(double x)
+{
+    if (x < -708.0) return 0.0;
+    const double n = floor(x * NX_LOG2E + 0.5);
+    const double r = (x - n * NX_LN2_HI) - n * NX_LN2_LO;
+    double s = 1.0, t = 1.0;
+    for (int k = 1; k <= 13; ++k) {
+        t = t * r / (double)k;
+        s = s + t;
+    }
+    return ldexp(s, (int)n);
+}
+
+/* log x, x > 0: x = m 2^e with m in [1/sqrt2, sqrt2), log m = 2 atanh(s),
+ * s = (m - 1) / (m + 1), by its series to s^29. */
+double oracle_nx_log(double x)
+{
+    int e;
+    double m = frexp(x, &e);
+    if (m < 0.70710678118654752440) {
+        m = m * 2.0;
+        e = e - 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0), s2 = s * s;
+    double t = s, acc = 0.0;
+    for (int k = 1; k <= 29; k += 2) {
+        acc = acc + t / (double)k;
+        t = t * s2;
+    }
+    return 2.0 * acc + ((double)e * NX_LN2_HI + (double)e * NX_LN2_LO);
+}
+
+/* log k! for integer k >= 0: the product for k < 20, else Stirling's series
+ * k log k - k + log(2 pi k) / 2 + 1/(12k) - 1/(360k^3) + 1/(1260k^5) - 1/(1680k^7). */
+double oracle_nx_logfact(double k)
+{
+    if (k < 20.0) {
+        double f = 1.0;
+        for (double i = 2.0; i <= k; i = i + 1.0) f = f * i;
+        return oracle_nx_log(f);
+    }
+    const double ik = 1.0 / k, ik2 = ik * ik;
+    const double series = ik * (1.0 / 12.0 - ik2 * (1.0 / 360.0 - ik2 * (1.0 / 1260.0 - ik2 * (1.0 / 1680.0))));
+    return (k * oracle_nx_log(k) - k) + 0.5 * oracle_nx_log(2.0 * ORACLE_PI * k) + series;
+}
+
+/* One Poisson count of mean lam >= 0 from element i's uniforms. */
+int64_t oracle_poisson_count(double lam, uint64_t seed, int64_t i)
+{
+    if (!(lam > 0.0)) return 0;
+    if (lam < 10.0) {
+        /* inversion: smallest k with u <= F(k) */
+        const double u = noise_uniform(seed, i, 0);
+        double p = oracle_nx_exp(-lam), F = p;
+        int64_t k = 0;
+        while (u > F && k < 1000) {
+            k = k + 1;
+            p = p * lam / (double)k;
+            F = F + p;
+        }
+        return k;
+    }
+    /* transformed rejection with squeeze */
+    const double slam = sqrt(lam), loglam = oracle_nx_log(lam);
+    const double b = 0.931 + 2.53 * slam;
+    const double a = -0.059 + 0.02483 * b;
+    const double invalpha = 1.1239 + 1.1328 / (b - 3.4);
+    const double vr = 0.9277 - 3.6224 / (b - 2.0);
+    for (int it = 0; it < 100000; ++it) {
+        const double U = noise_uniform(seed, i, 2 * it) - 0.5;
+        const double V = noise_uniform(seed, i, 2 * it + 1);
+        const double us = 0.5 - fabs(U);
+        const double kd = floor((2.0 * a / us + b) * U + lam + 0.43);
+        if (us >= 0.07 && V <= vr) return (int64_t)kd;
+        if (kd < 0.0 || (us < 0.013 && V > us)) continue;
+        const double lhs = (oracle_nx_log(V) + oracle_nx_log(invalpha)) - oracle_nx_log(a / (us * us) + b);
+        const double rhs = (-lam + kd * loglam) - oracle_nx_logfact(kd);
+        if (lhs <= rhs) return (int64_t)kd;
+    }
+    return -1;
+}
+
+/* Counts for an array of means (distribution checks). */
+void oracle_poisson_counts(const double* lam, int64_t n, uint64_t seed, int64_t* k)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) k[i] = oracle_poisson_count(lam[i], seed, i);
+}
+
+/* mean, population variance and sigma_n = Var / 10^(nr / 10) of a frame. */
+void oracle_noise_scale(const float* tau, int64_t n, double nr_db, double* out)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += (double)tau[i];
+    const double mean = n > 0 ? s / (double)n : 0.0;
+    double v = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double d = (double)tau[i] - mean;
+        v += d * d;
+    }
+    const double var = n > 0 ? v / (double)n : 0.0;
+    out[0] = mean;
+    out[1] = var;
+    out[2] = var / pow(10.0, nr_db / 10.0);
+}
+
+/* T = Poisson(tau * sigma_n) / sigma_n elementwise (0 where sigma_n <= 0 or
+ * not finite; negative tau counts as 0), written as fp32. */
+void oracle_poisson_noise(const float* tau, int64_t n, double sigma_n, uint64_t seed, float* out)
+{
+    const int ok = sigma_n > 0.0 && isfinite(sigma_n);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        if (!ok) { out[i] = 0.0f; continue; }
+        const double t = (double)tau[i];
+        const double lam = t > 0.0 ? t * sigma_n : 0.0;
+        out[i] = (float)((double)oracle_poisson_count(lam, seed, i) / sigma_n);
+    }
+}

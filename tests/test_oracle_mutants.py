@@ -86,6 +86,46 @@ def test_smooth_mutant_is_caught(tmp_path, name, old, new):
     print(name, "caught by", failures)
 
 
+NOISE_MUTANTS = [
+    ("philox_multiplier", "0xD2E7470EE14C6C93ull", "0xD2E7470EE14C6C95ull"),
+    ("philox_weyl", "k1 += 0xBB67AE8584CAA73Bull;", "k1 += 0xBB67AE8584CAA73Dull;"),
+    ("uniform_word", "return (double)(o[t % 4] >> 11)", "return (double)(o[(t + 1) % 4] >> 11)"),
+    ("inversion_off_by_one", "while (u > F && k < 1000) {", "while (u >= F - 1e-3 && k < 1000) {"),
+    ("ptrs_shift", "* U + lam + 0.43);", "* U + lam + 0.93);"),
+    ("ptrs_squeeze_only", "if (lhs <= rhs) return (int64_t)kd;", "return (int64_t)kd;"),
+    ("exp_short_series", "for (int k = 1; k <= 13; ++k) {", "for (int k = 1; k <= 5; ++k) {"),
+    ("logfact_no_half_log", "+ 0.5 * oracle_nx_log(2.0 * ORACLE_PI * k)", "+ oracle_nx_log(2.0 * ORACLE_PI * k)"),
+    ("variance_sample", "const double var = n > 0 ? v / (double)n : 0.0;",
+     "const double var = n > 1 ? v / (double)(n - 1) : 0.0;"),
+    ("noise_db_scale", "out[2] = var / pow(10.0, nr_db / 10.0);", "out[2] = var / pow(10.0, nr_db / 20.0);"),
+]
+
+
+def _run_noise_pins(lib):
+    import pins_noise
+    failures = []
+    for pin in pins_noise.NOISE_PINS:
+        try:
+            pin(lib)
+        except Exception as e:  # noqa: BLE001 - any failure counts
+            failures.append((pin.__name__, type(e).__name__))
+    return failures
+
+
+@pytest.mark.parametrize("name,old,new", NOISE_MUTANTS, ids=[m[0] for m in NOISE_MUTANTS])
+def test_noise_mutant_is_caught(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation site for {name} not found"
+    path = str(tmp_path / "mut.c")
+    with open(path, "w") as f:
+        f.write(src.replace(old, new))
+    so = str(tmp_path / "libmut.so")
+    oracle.compile_library(path, so)
+    failures = _run_noise_pins(oracle.load(so))
+    assert failures, f"mutant {name} passed every noise pin"
+    print(name, "caught by", failures)
+
+
 def _run_pins(lib):
     failures = []
     for pin in pins.FAST_PINS:
