@@ -49,6 +49,7 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=256,
                     help="requests of the serving mix for the batched-vs-plain latency leg (0: skip)")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replayed step timing")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the smooth forward / adjoint leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs the operator on a single MI355X "
@@ -104,6 +105,7 @@ def main():
     graph = None
     if not args.no_graph:
         graph = graph_leg(step, stream, args.steps, pairs)
+    noise = noise_leg(out)
 
     kern_ms = np.array([a.elapsed_time(b) for a, b in evs])
     step_ms = np.array([step_ev[i].elapsed_time(step_ev[i + 1]) for i in range(args.steps)])
@@ -152,9 +154,29 @@ def main():
                      "kernel_ms": round(kern_avg, 5), "flops_per_pair": F},
         "cpu_baseline": cpu,
         "graph": graph,
+        "noise": noise,
         "serving": serving_leg(args.serving_requests) if args.serving_requests > 0 else None,
+        "adjoint": None if args.no_adjoint else adjoint_leg(),
     }
     print(json.dumps(line), flush=True)
+
+
+def noise_leg(tau, reps=20):
+    """Poisson noise of the step's output frame (Algorithm 1 step 2.4 after
+    the blur): frame variance -> sigma_n (nr = 2 dB) -> noisy frame."""
+    import torch
+    import paper_2506_03747_amd as nl
+    noisy = torch.empty_like(tau)
+    nl.add_poisson_noise(tau, 2.0, 1, out=noisy)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(reps):
+        nl.add_poisson_noise(tau, 2.0, i, out=noisy)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"elements": tau.numel(), "ms": round(ms, 4), "gelem_s": round(tau.numel() / (ms * 1e-3) / 1e9, 3)}
 
 
 def graph_leg(step, stream, steps, pairs):
@@ -178,6 +200,44 @@ def graph_leg(step, stream, steps, pairs):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     return {"ms_per_step": round(ms, 5), "gpairs_s": round(pairs / (ms * 1e-3) / 1e9, 3)}
+
+
+def adjoint_leg(reps=10):
+    """Differentiable path on the 128x128 scan x 128x128 patch workload
+    (T=1024 x 8 ps, FWHM 50 ps, smooth support ceil(6 sigma) = 16 bins):
+    smooth forward, record adjoint and map adjoint, HIP-event timed."""
+    import torch
+    import scenes
+    import paper_2506_03747_amd as nl
+    sc = scenes.cfg5()
+    d = torch.from_numpy(sc.depth).cuda()
+    a = torch.from_numpy(sc.albedo).cuda()
+    prm = nl.params_of(sc)
+    rec, n = nl.patches_from_depth(d, sc.patch_grid, a, None)
+    tau = nl.forward_smooth(prm, rec, n)
+    G = torch.randn(tau.shape, generator=torch.Generator(device="cuda").manual_seed(5), device="cuda")
+    gr = nl.adjoint(prm, rec, n, G)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    pairs = sc.n_scan * int(n.item())
+    t_s = timed(lambda: nl.forward_smooth(prm, rec, n, out=tau))
+    t_a = timed(lambda: nl.adjoint(prm, rec, n, G, out=gr))
+    t_m = timed(lambda: nl.patches_adjoint(sc.patch_grid, d, a, rec, n, gr))
+    return {"workload": "cfg5: confocal 128x128 scan, 128x128 patches (no mask), T=1024 x 8 ps, FWHM 50 ps",
+            "pairs": pairs, "smooth_ms": round(t_s, 4), "adjoint_ms": round(t_a, 4), "maps_ms": round(t_m, 4),
+            "smooth_gpairs_s": round(pairs / (t_s * 1e-3) / 1e9, 3),
+            "adjoint_gpairs_s": round(pairs / (t_a * 1e-3) / 1e9, 3)}
 
 
 def serving_leg(n_req):

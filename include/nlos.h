@@ -289,6 +289,35 @@ int nlos_patches_adjoint(const nlos_grid* g, const float* depth, const float* al
                          float* grad_depth, float* grad_albedo, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Poisson noise of a frame (Algorithm 1 step 2.4, applied after the blur of
+ * step 2.3):  T = Poisson(tau * sigma_n) / sigma_n with
+ * sigma_n = Var(tau) / 10^(nr / 10), Var the population variance of the whole
+ * frame (every histogram and bin).
+ */
+/* Workspace of nlos_noise_scale: fp64 moments of up to 1024 blocks. */
+int nlos_noise_scale_workspace_bytes(int64_t n, size_t* bytes);
+
+/* stats (device double[3], 8-byte aligned) <- { mean, Var, sigma_n } of the n
+ * floats of tau (device); fp64 throughout, merged in a fixed order
+ * (reproducible). */
+int nlos_noise_scale(const float* tau, int64_t n, double nr_db, double* stats, void* ws, size_t ws_bytes,
+                     void* stream);
+
+/*
+ * out[i] = Poisson(max(tau[i], 0) * s) / s for the n elements, s = *sigma_n
+ * (device double, e.g. stats + 2); out is all zeros when s <= 0 or not finite.
+ * out may be tau (in place).  Uniform t of element i is word t mod 4 of
+ * Philox4x64-10 (Salmon et al., SC 2011) at counter (i, t / 4, 0, 0) and key
+ * (seed, 0x4e4c4f53), mapped to [0, 1) by its top 53 bits.  Counts come from
+ * inversion by sequential search for lambda < 10 and from Hormann's
+ * transformed rejection with squeeze (PTRS, 1993) above; exp, log and log k!
+ * follow fixed recipes of IEEE basic operations, so the counts are a
+ * deterministic function of (tau[i], s, seed, i).
+ */
+int nlos_poisson_noise(const float* tau, int64_t n, const double* sigma_n, uint64_t seed, float* out,
+                       void* stream);
+
+/*
  * Test hook: the bin index of every (histogram, record) pair, decided by the
  * same device functions and the same fp32-then-fp64 rule as nlos_forward.
  *   bins    device int32 [H][n_patches], H = histograms of the output

@@ -26,7 +26,7 @@ from ._native import (NLOS_F_COSINES, NLOS_MAX_BINS, NLOS_MAX_PATCHES, NLOS_MAX_
 __all__ = ["Grid", "Params", "NlosError", "make_grid", "make_params", "params_of",
            "patches_from_depth", "forward", "debug_bins", "out_shape", "n_histograms",
            "Batcher", "patches_batched", "forward_batched", "forward_smooth", "adjoint", "patches_adjoint",
-           "SmoothTransient", "smooth_transient"]
+           "SmoothTransient", "smooth_transient", "noise_scale", "poisson_noise", "add_poisson_noise"]
 
 
 def make_grid(g) -> Grid:
@@ -367,3 +367,40 @@ def smooth_transient(depth: torch.Tensor, albedo: Optional[torch.Tensor], grid, 
                      mask: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Differentiable smooth forward of depth and albedo maps (confocal)."""
     return SmoothTransient.apply(depth, albedo, grid, params, mask)
+
+
+def noise_scale(tau: torch.Tensor, nr_db: float, stream=None) -> torch.Tensor:
+    """Device double[3] {mean, population variance, sigma_n = Var / 10^(nr/10)}
+    of a whole frame."""
+    _dev(tau, torch.float32, "tau")
+    n = tau.numel()
+    need = C.c_size_t(0)
+    check(lib().nlos_noise_scale_workspace_bytes(n, C.byref(need)), "nlos_noise_scale_workspace_bytes")
+    ws = _ws(need.value, tau.device)
+    stats = torch.empty(3, dtype=torch.float64, device=tau.device)
+    check(lib().nlos_noise_scale(_ptr(tau), n, float(nr_db), _ptr(stats), _ptr(ws), ws.numel(), _stream(stream)),
+          "nlos_noise_scale")
+    return stats
+
+
+def poisson_noise(tau: torch.Tensor, sigma_n: torch.Tensor, seed: int, out: Optional[torch.Tensor] = None,
+                  stream=None) -> torch.Tensor:
+    """Poisson(tau * s) / s elementwise, s = sigma_n[0] (device double)."""
+    _dev(tau, torch.float32, "tau")
+    _dev(sigma_n, torch.float64, "sigma_n")
+    if out is None:
+        out = torch.empty_like(tau)
+    _dev(out, torch.float32, "out")
+    if out.numel() != tau.numel():
+        raise ValueError("out has the wrong size")
+    check(lib().nlos_poisson_noise(_ptr(tau), tau.numel(), _ptr(sigma_n), C.c_uint64(int(seed) & (2**64 - 1)),
+                                   _ptr(out), _stream(stream)), "nlos_poisson_noise")
+    return out
+
+
+def add_poisson_noise(tau: torch.Tensor, nr_db: float, seed: int, out: Optional[torch.Tensor] = None,
+                      stream=None) -> torch.Tensor:
+    """Algorithm 1 step 2.4 on a (jittered) frame: sigma_n from the frame's
+    variance, then Poisson(tau sigma_n) / sigma_n; no host synchronisation."""
+    stats = noise_scale(tau, nr_db, stream)
+    return poisson_noise(tau, stats[2:], seed, out=out, stream=stream)

@@ -89,6 +89,10 @@ SIGNATURES = [
     ("nlos_patches_adjoint", C.c_int,
      [C.POINTER(Grid), C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
       C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("nlos_noise_scale_workspace_bytes", C.c_int, [C.c_int64, C.POINTER(C.c_size_t)]),
+    ("nlos_noise_scale", C.c_int,
+     [C.c_void_p, C.c_int64, C.c_double, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("nlos_poisson_noise", C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
     ("nlos_debug_bins", C.c_int,
      [C.POINTER(Params), C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
       C.c_void_p]),

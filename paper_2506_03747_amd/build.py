@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnlos.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["nlos_geometry.hip", "nlos_forward.hip", "nlos_smooth.hip", "nlos_abi.cpp"]
+SOURCES = ["nlos_geometry.hip", "nlos_forward.hip", "nlos_smooth.hip", "nlos_noise.hip", "nlos_abi.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

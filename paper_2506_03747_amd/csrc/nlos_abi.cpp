@@ -910,6 +910,41 @@ int nlos_patches_adjoint(const nlos_grid* g, const float* depth, const float* al
     return e == hipSuccess ? NLOS_OK : hip_fail(e);
 }
 
+int nlos_noise_scale_workspace_bytes(int64_t n, size_t* bytes)
+{
+    if (n < 0 || !bytes) return NLOS_EINVAL;
+    const int64_t nb = std::max<int64_t>(1, std::min<int64_t>(nlos::kNoiseMomentBlocks, (n + 255) / 256));
+    *bytes = (size_t)(3 * nb) * sizeof(double);
+    return NLOS_OK;
+}
+
+int nlos_noise_scale(const float* tau, int64_t n, double nr_db, double* stats, void* ws, size_t ws_bytes,
+                     void* stream)
+{
+    size_t need = 0;
+    if (nlos_noise_scale_workspace_bytes(n, &need) != NLOS_OK || !std::isfinite(nr_db)) return NLOS_EINVAL;
+    if ((n > 0 && (!tau || !aligned(tau, 4))) || !stats || !aligned(stats, 8)) return NLOS_EINVAL;
+    if (ws_bytes < need) return NLOS_ENOSPC;
+    if (!ws || !aligned(ws, 8)) return NLOS_EINVAL;
+    const int dev = device_check();
+    if (dev != NLOS_OK) return dev;
+    const int nb = (int)(need / (3 * sizeof(double)));
+    const hipError_t e =
+        nlos::launch_noise_scale(tau, n, nr_db, stats, static_cast<double*>(ws), nb, (hipStream_t)stream);
+    return e == hipSuccess ? NLOS_OK : hip_fail(e);
+}
+
+int nlos_poisson_noise(const float* tau, int64_t n, const double* sigma_n, uint64_t seed, float* out,
+                       void* stream)
+{
+    if (n < 0 || !sigma_n || !aligned(sigma_n, 8)) return NLOS_EINVAL;
+    if (n > 0 && (!tau || !out || !aligned(tau, 4) || !aligned(out, 4))) return NLOS_EINVAL;
+    const int dev = device_check();
+    if (dev != NLOS_OK) return dev;
+    const hipError_t e = nlos::launch_poisson(tau, n, sigma_n, seed, out, (hipStream_t)stream);
+    return e == hipSuccess ? NLOS_OK : hip_fail(e);
+}
+
 int nlos_debug_bins(const nlos_params* p, const float* patches, int32_t n_patches, const int32_t* n_active,
                     int32_t* bins, double* u_fast, double* u_exact, void* stream)
 {

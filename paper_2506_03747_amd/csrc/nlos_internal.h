@@ -179,6 +179,12 @@ hipError_t launch_adjoint_reduce(const SmoothArgs& a, float* grad_rec, hipStream
 hipError_t launch_grad_maps(const GradMapArgs& g, hipStream_t st);
 constexpr int kAdjStride = 5;   // doubles per record in the adjoint partials
 
+hipError_t launch_noise_scale(const float* tau, int64_t n, double nr_db, double* out, double* part, int nb,
+                              hipStream_t st);
+hipError_t launch_poisson(const float* tau, int64_t n, const double* sigma_n, uint64_t seed, float* out,
+                          hipStream_t st);
+constexpr int kNoiseMomentBlocks = 1024;
+
 // Batched launches (one launch each over all requests of the list).
 hipError_t launch_geometry_batch(const GeomList& g, int64_t n_blocks, hipStream_t st);
 hipError_t launch_stats_batch(const BatchList& b, int64_t n_blocks, hipStream_t st);

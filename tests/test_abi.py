@@ -26,7 +26,7 @@ def declared_functions():
 
 def test_exports_every_declared_symbol(nat):
     names = declared_functions()
-    assert len(names) == 18, names
+    assert len(names) == 21, names
     for n in names:
         assert hasattr(nat.lib(), n), n
     bound = {s[0] for s in nat.SIGNATURES}
@@ -245,3 +245,17 @@ def test_smooth_and_adjoint_checks(nat):
                                   None) == nat.NLOS_EINVAL
     assert L.nlos_patches_adjoint(C.byref(g), None, None, 1, FAKE, None, FAKE, FAKE, None, FAKE, need.value,
                                   None) == nat.NLOS_EINVAL
+
+
+def test_noise_checks(nat):
+    L = nat.lib()
+    need = C.c_size_t(0)
+    assert L.nlos_noise_scale_workspace_bytes(10**7, C.byref(need)) == 0
+    assert need.value == 3 * 8 * 1024
+    assert L.nlos_noise_scale_workspace_bytes(-1, C.byref(need)) == nat.NLOS_EINVAL
+    assert L.nlos_noise_scale(FAKE, 10**7, 2.0, FAKE, FAKE, need.value - 1, None) == nat.NLOS_ENOSPC
+    assert L.nlos_noise_scale(FAKE, 10**7, float("nan"), FAKE, FAKE, need.value, None) == nat.NLOS_EINVAL
+    assert L.nlos_noise_scale(FAKE, 10**7, 2.0, C.c_void_p(0x10004), FAKE, need.value, None) == nat.NLOS_EINVAL
+    assert L.nlos_poisson_noise(FAKE, 100, None, 1, FAKE, None) == nat.NLOS_EINVAL
+    assert L.nlos_poisson_noise(FAKE, -1, FAKE, 1, FAKE, None) == nat.NLOS_EINVAL
+    assert L.nlos_poisson_noise(None, 100, FAKE, 1, FAKE, None) == nat.NLOS_EINVAL
