@@ -50,6 +50,7 @@ def main():
                     help="requests of the serving mix for the batched-vs-plain latency leg (0: skip)")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replayed step timing")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the smooth forward / adjoint leg")
+    ap.add_argument("--no-lct", action="store_true", help="skip the FFT-route leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs the operator on a single MI355X "
@@ -157,6 +158,7 @@ def main():
         "noise": noise,
         "serving": serving_leg(args.serving_requests) if args.serving_requests > 0 else None,
         "adjoint": None if args.no_adjoint else adjoint_leg(),
+        "lct": None if args.no_lct else lct_leg(),
     }
     print(json.dumps(line), flush=True)
 
@@ -238,6 +240,47 @@ def adjoint_leg(reps=10):
             "pairs": pairs, "smooth_ms": round(t_s, 4), "adjoint_ms": round(t_a, 4), "maps_ms": round(t_m, 4),
             "smooth_gpairs_s": round(pairs / (t_s * 1e-3) / 1e9, 3),
             "adjoint_gpairs_s": round(pairs / (t_a * 1e-3) / 1e9, 3)}
+
+
+def lct_leg(reps=5):
+    """The paper's FFT (light-cone) route beside the direct operator on the
+    128x128 scan x 128x128 depth map workload without cosines (Eq. (1) as
+    printed), T=1024 x 8 ps: time of each and their correlation."""
+    import ctypes as C
+    import torch
+    import scenes
+    import paper_2506_03747_amd as nl
+    from paper_2506_03747_amd._native import check, lib
+    sc = scenes.cfg5()
+    sc.cosines = False
+    d = torch.from_numpy(sc.depth).cuda()
+    a = torch.from_numpy(sc.albedo).cuda()
+    prm = nl.params_of(sc)
+    out = nl.lct_forward(prm, d, a)
+    rec, n = nl.patches_from_depth(d, sc.patch_grid, a, None, cosines=False)
+    direct = nl.forward(prm, rec, n)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    nb = C.c_size_t(0)
+    check(lib().nlos_lct_workspace_bytes(C.byref(prm), C.byref(nb)), "nlos_lct_workspace_bytes")
+    big = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    t_lct = timed(lambda: nl.lct_forward(prm, d, a, out=out, workspace=big))
+    t_dir = timed(lambda: nl.forward(prm, rec, n, out=direct))
+    corr = float(torch.corrcoef(torch.stack([out.flatten().double(), direct.flatten().double()]))[0, 1])
+    return {"workload": "cfg5 without cosines: confocal 128x128 scan co-registered with the 128x128 depth map, "
+                        "T=1024 x 8 ps, FWHM 50 ps", "lct_ms": round(t_lct, 3), "direct_ms": round(t_dir, 4),
+            "corr_with_direct": round(corr, 4), "workspace_bytes": nb.value}
 
 
 def serving_leg(n_req):

@@ -318,6 +318,29 @@ int nlos_poisson_noise(const float* tau, int64_t n, const double* sigma_n, uint6
                        void* stream);
 
 /*
+ * The paper's FFT ("light-cone") forward route (Section 2, Eq. (3)-(5);
+ * Algorithm 1 steps 1.1-2.3) as a cross-check of the direct operator: a
+ * confocal N x N scan (relay.nx == relay.ny, half_x == half_y = w) whose
+ * depth map is the same N x N grid, no stand-off, flags 0 (Eq. (1) without
+ * cosines), T = M a power of two.  Steps: depth layer j = floor(D / dz),
+ * dz = c dt / 2; fold to u = J^2 (J = j + 1) with weight 1 / J and pairwise
+ * means down to M samples; 3-D convolution (fp64 FFTs on the zero-padded
+ * (2N, 2N, 2M) grid) with the cone that puts lateral offset n cells (x = n / N)
+ * at layer round((4 slope)^2 (x^2 + y^2) M), slope = w / (M c dt), layers past
+ * the window dropped; back to time bins by the mean over each bin's v-span
+ * [j^2, (j+1)^2) divided by (J dz)^3; Gaussian jitter.  Output float
+ * [N][N][M].  The first call for a size creates and keeps an FFT plan (the
+ * FFT library allocates its tables then); later calls allocate nothing.  A
+ * failure inside the FFT library gives NLOS_EHIP with nlos_last_hip_error()
+ * = -1.  The workspace (two complex fp64 volumes + FFT work) is about
+ * 32 * (2N)^2 * 2M bytes, 256-byte aligned.
+ */
+int nlos_lct_workspace_bytes(const nlos_params* p, size_t* bytes);
+
+int nlos_lct_forward(const nlos_params* p, const float* depth, const float* albedo, const uint8_t* mask,
+                     float* out, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Test hook: the bin index of every (histogram, record) pair, decided by the
  * same device functions and the same fp32-then-fp64 rule as nlos_forward.
  *   bins    device int32 [H][n_patches], H = histograms of the output

@@ -26,7 +26,8 @@ from ._native import (NLOS_F_COSINES, NLOS_MAX_BINS, NLOS_MAX_PATCHES, NLOS_MAX_
 __all__ = ["Grid", "Params", "NlosError", "make_grid", "make_params", "params_of",
            "patches_from_depth", "forward", "debug_bins", "out_shape", "n_histograms",
            "Batcher", "patches_batched", "forward_batched", "forward_smooth", "adjoint", "patches_adjoint",
-           "SmoothTransient", "smooth_transient", "noise_scale", "poisson_noise", "add_poisson_noise"]
+           "SmoothTransient", "smooth_transient", "noise_scale", "poisson_noise", "add_poisson_noise",
+           "lct_forward"]
 
 
 def make_grid(g) -> Grid:
@@ -404,3 +405,28 @@ def add_poisson_noise(tau: torch.Tensor, nr_db: float, seed: int, out: Optional[
     variance, then Poisson(tau sigma_n) / sigma_n; no host synchronisation."""
     stats = noise_scale(tau, nr_db, stream)
     return poisson_noise(tau, stats[2:], seed, out=out, stream=stream)
+
+
+def lct_forward(params: Params, depth: torch.Tensor, albedo: Optional[torch.Tensor] = None,
+                mask: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+                workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """The paper's FFT (light-cone) forward route, [N, N, M] fp32: confocal
+    N x N scan co-registered with the N x N depth map, no stand-off, no
+    cosines (params.flags = 0), M a power of two."""
+    _dev(depth, torch.float32, "depth")
+    _dev(albedo, torch.float32, "albedo")
+    _dev(mask, torch.uint8, "mask")
+    n = params.relay.nx
+    for t, name in ((depth, "depth"), (albedo, "albedo"), (mask, "mask")):
+        if t is not None and t.numel() != n * params.relay.ny:
+            raise ValueError(f"{name} must cover the scan grid")
+    if out is None:
+        out = torch.empty(out_shape(params), dtype=torch.float32, device=depth.device)
+    _dev(out, torch.float32, "out")
+    need = C.c_size_t(0)
+    check(lib().nlos_lct_workspace_bytes(C.byref(params), C.byref(need)), "nlos_lct_workspace_bytes")
+    if workspace is None or workspace.numel() < need.value:
+        workspace = torch.empty(need.value, dtype=torch.uint8, device=depth.device)
+    check(lib().nlos_lct_forward(C.byref(params), _ptr(depth), _ptr(albedo), _ptr(mask), _ptr(out), _ptr(workspace),
+                                 workspace.numel(), _stream(stream)), "nlos_lct_forward")
+    return out

@@ -93,6 +93,9 @@ SIGNATURES = [
     ("nlos_noise_scale", C.c_int,
      [C.c_void_p, C.c_int64, C.c_double, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     ("nlos_poisson_noise", C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
+    ("nlos_lct_workspace_bytes", C.c_int, [C.POINTER(Params), C.POINTER(C.c_size_t)]),
+    ("nlos_lct_forward", C.c_int,
+     [C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     ("nlos_debug_bins", C.c_int,
      [C.POINTER(Params), C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
       C.c_void_p]),

@@ -577,6 +577,44 @@ int adjoint_rows(int T)
 
 size_t adjoint_lds(int rows, int T) { return (((size_t)rows * T * 4 + 15) & ~(size_t)15) + (size_t)rows * 24; }
 
+// ---------------------------------------------------------------------------
+// FFT (light-cone) route.
+int lct_setup(const nlos_params* p, nlos::LctArgs* a, int64_t* n3)
+{
+    if (params_ok(p) != NLOS_OK || !is_confocal(p)) return NLOS_EINVAL;
+    const int N = p->relay.nx, M = p->n_bins;
+    if (p->relay.ny != N || p->relay.half_x != p->relay.half_y || p->standoff_m != 0.0 || p->flags != 0)
+        return NLOS_EINVAL;
+    if ((M & (M - 1)) != 0 || M > (1 << 16) || N > 4096) return NLOS_EINVAL;
+    const int64_t n = (int64_t)(2 * N) * (2 * N) * (2 * M);
+    if (n > ((int64_t)1 << 34)) return NLOS_EINVAL;
+    std::memset(a, 0, sizeof(*a));
+    const double dt = p->bin_ps * 1e-12;
+    const double slope = p->relay.half_x / ((double)M * kC * dt);
+    a->N = N;
+    a->M = M;
+    a->dz = kC * dt / 2.0;
+    a->cone = (4.0 * slope) * (4.0 * slope);
+    // jitter taps in fp64 (Section 2): sigma = FWHM / (2 sqrt(2 ln 2)) / dt bins, R = ceil(2 sigma)
+    if (p->fwhm_ps == 0.0) {
+        a->R = 0;
+        a->taps[0] = 1.0;
+    } else {
+        const double sigma = p->fwhm_ps / (2.0 * std::sqrt(2.0 * std::log(2.0))) / p->bin_ps;
+        const double rr = std::ceil(2.0 * sigma);
+        if (!(rr <= (double)nlos::kMaxRadius)) return NLOS_EINVAL;
+        a->R = (int)rr;
+        double sum = 0.0;
+        for (int j = -a->R; j <= a->R; ++j) {
+            a->taps[j + a->R] = std::exp(-(double)(j * j) / (2.0 * sigma * sigma));
+            sum += a->taps[j + a->R];
+        }
+        for (int i = 0; i <= 2 * a->R; ++i) a->taps[i] /= sum;
+    }
+    *n3 = n;
+    return NLOS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -943,6 +981,54 @@ int nlos_poisson_noise(const float* tau, int64_t n, const double* sigma_n, uint6
     if (dev != NLOS_OK) return dev;
     const hipError_t e = nlos::launch_poisson(tau, n, sigma_n, seed, out, (hipStream_t)stream);
     return e == hipSuccess ? NLOS_OK : hip_fail(e);
+}
+
+int nlos_lct_workspace_bytes(const nlos_params* p, size_t* bytes)
+{
+    nlos::LctArgs a;
+    int64_t n3 = 0;
+    if (!bytes) return NLOS_EINVAL;
+    int rc = lct_setup(p, &a, &n3);
+    if (rc != NLOS_OK) return rc;
+    const int dev = device_check();
+    if (dev != NLOS_OK) return dev;
+    size_t work = 0;
+    if (nlos::lct_fft_work_bytes(a.N, a.M, &work) != 0) {
+        g_last_hip = -1;
+        return NLOS_EHIP;
+    }
+    *bytes = 2 * (size_t)n3 * 16 + align_up(work, 256);
+    return NLOS_OK;
+}
+
+int nlos_lct_forward(const nlos_params* p, const float* depth, const float* albedo, const uint8_t* mask, float* out,
+                     void* ws, size_t ws_bytes, void* stream)
+{
+    nlos::LctArgs a;
+    int64_t n3 = 0;
+    int rc = lct_setup(p, &a, &n3);
+    if (rc != NLOS_OK) return rc;
+    if (!depth || !out || !aligned(depth, 4) || !aligned(out, 4) || (albedo && !aligned(albedo, 4))) return NLOS_EINVAL;
+    size_t need = 0;
+    rc = nlos_lct_workspace_bytes(p, &need);
+    if (rc != NLOS_OK) return rc;
+    if (ws_bytes < need) return NLOS_ENOSPC;
+    if (!ws || !aligned(ws, 256)) return NLOS_EINVAL;
+    a.depth = depth;
+    a.albedo = albedo;
+    a.mask = mask;
+    unsigned char* w = static_cast<unsigned char*>(ws);
+    double2* vol = reinterpret_cast<double2*>(w);
+    double2* psf = reinterpret_cast<double2*>(w + (size_t)n3 * 16);
+    void* work = w + 2 * (size_t)n3 * 16;
+    int fft = 0;
+    const hipError_t e = nlos::launch_lct(a, vol, psf, work, out, (hipStream_t)stream, &fft);
+    if (e != hipSuccess) return hip_fail(e);
+    if (fft != 0) {
+        g_last_hip = -1;
+        return NLOS_EHIP;
+    }
+    return NLOS_OK;
 }
 
 int nlos_debug_bins(const nlos_params* p, const float* patches, int32_t n_patches, const int32_t* n_active,

@@ -140,6 +140,18 @@ struct GradMapArgs {
     int32_t cosines;
 };
 
+// FFT (light-cone) route: N x N scan, M = T time bins (a power of two).
+struct LctArgs {
+    const float* depth;
+    const float* albedo;       // nullable -> 0.5
+    const uint8_t* mask;       // nullable
+    int32_t N, M;
+    double dz;                 // c dt / 2
+    double cone;               // (4 slope)^2, slope = w / (M c dt)
+    int32_t R;                 // jitter half-width
+    double taps[kMaxTaps];
+};
+
 // Debug/test hook arguments.
 struct DebugArgs {
     FwdArgs f;
@@ -184,6 +196,10 @@ hipError_t launch_noise_scale(const float* tau, int64_t n, double nr_db, double*
 hipError_t launch_poisson(const float* tau, int64_t n, const double* sigma_n, uint64_t seed, float* out,
                           hipStream_t st);
 constexpr int kNoiseMomentBlocks = 1024;
+
+int lct_fft_work_bytes(int N, int M, size_t* bytes);
+hipError_t launch_lct(const LctArgs& a, double2* vol, double2* psf, void* fft_work, float* out, hipStream_t st,
+                      int* fft_status);
 
 // Batched launches (one launch each over all requests of the list).
 hipError_t launch_geometry_batch(const GeomList& g, int64_t n_blocks, hipStream_t st);

@@ -26,7 +26,7 @@ def declared_functions():
 
 def test_exports_every_declared_symbol(nat):
     names = declared_functions()
-    assert len(names) == 21, names
+    assert len(names) == 23, names
     for n in names:
         assert hasattr(nat.lib(), n), n
     bound = {s[0] for s in nat.SIGNATURES}
@@ -259,3 +259,21 @@ def test_noise_checks(nat):
     assert L.nlos_poisson_noise(FAKE, 100, None, 1, FAKE, None) == nat.NLOS_EINVAL
     assert L.nlos_poisson_noise(FAKE, -1, FAKE, 1, FAKE, None) == nat.NLOS_EINVAL
     assert L.nlos_poisson_noise(None, 100, FAKE, 1, FAKE, None) == nat.NLOS_EINVAL
+
+
+def test_lct_checks(nat):
+    """Host-side checks of the FFT route (before any device is needed)."""
+    L = nat.lib()
+    need = C.c_size_t(0)
+    p = _params(nat, flags=0, n_bins=64)
+    bad = [_params(nat, n_bins=64),                      # cosines requested
+           _params(nat, flags=0, n_bins=60),             # not a power of two
+           _params(nat, flags=0, n_bins=64, standoff_m=0.5)]
+    nc = _params(nat, flags=0, n_bins=64)
+    nc.laser = nat.Grid(2, 2, 0.5, 0.5, 0.0, 0.0)
+    rect = _params(nat, flags=0, n_bins=64)
+    rect.relay.ny = 8
+    for q in bad + [nc, rect]:
+        assert L.nlos_lct_workspace_bytes(C.byref(q), C.byref(need)) == nat.NLOS_EINVAL
+        assert L.nlos_lct_forward(C.byref(q), FAKE, None, None, FAKE, FAKE, 1 << 30, None) == nat.NLOS_EINVAL
+    assert L.nlos_lct_forward(C.byref(p), None, None, None, FAKE, FAKE, 1 << 30, None) == nat.NLOS_EINVAL
