@@ -174,6 +174,22 @@ int nlos_forward(const nlos_params* p, const float* patches, int32_t n_patches,
                  const int32_t* n_active, float* out, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * The whole path in one call: nlos_patches_from_depth for the depth map on
+ * grid g (flags = p->flags) followed by nlos_forward over its records, with
+ * the record summaries built while the records are written (no separate
+ * pass).  Same results as the two calls.  patches [g.nx*g.ny][8] and
+ * n_active are written as by nlos_patches_from_depth; out as by
+ * nlos_forward.  ws: at least nlos_simulate_workspace_bytes, 256-byte
+ * aligned.  forward_mark: a hipEvent_t recorded on the stream right before
+ * the pair kernel (for timing it), or NULL.
+ */
+int nlos_simulate_workspace_bytes(const nlos_params* p, const nlos_grid* g, size_t* bytes);
+
+int nlos_simulate(const nlos_params* p, const nlos_grid* g, const float* depth, const float* albedo,
+                  const uint8_t* mask, float* patches, int32_t* n_active, float* out, void* ws, size_t ws_bytes,
+                  void* forward_mark, void* stream);
+
+/*
  * Batched calls: many independent scenes (uneven sizes, time windows, bin
  * widths, jitter) in one launch per kernel phase, as a serving loop issues
  * them (Algorithm 1 runs the forward model once per frame of a sequence).

@@ -24,7 +24,7 @@ from ._native import (NLOS_F_COSINES, NLOS_MAX_BINS, NLOS_MAX_PATCHES, NLOS_MAX_
                       strerror)
 
 __all__ = ["Grid", "Params", "NlosError", "make_grid", "make_params", "params_of",
-           "patches_from_depth", "forward", "debug_bins", "out_shape", "n_histograms",
+           "patches_from_depth", "forward", "simulate", "debug_bins", "out_shape", "n_histograms",
            "Batcher", "patches_batched", "forward_batched", "forward_smooth", "adjoint", "patches_adjoint",
            "SmoothTransient", "smooth_transient", "noise_scale", "poisson_noise", "add_poisson_noise",
            "lct_forward"]
@@ -132,6 +132,44 @@ def forward(params: Params, patches: torch.Tensor, n_active: Optional[torch.Tens
                              _ptr(ws), 0 if ws is None else ws.numel(), _stream(stream)),
           "nlos_forward")
     return out
+
+
+def simulate(params: Params, depth: torch.Tensor, grid, albedo: Optional[torch.Tensor] = None,
+             mask: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+             patches: Optional[torch.Tensor] = None, n_active: Optional[torch.Tensor] = None,
+             workspace: Optional[torch.Tensor] = None, forward_mark=None, stream=None):
+    """Depth map -> jittered histograms in one call (geometry, record
+    summaries and the forward operator).  Returns (out, patches, n_active).
+    ``forward_mark``: a torch.cuda.Event recorded right before the pair
+    kernel (timing hook), or None."""
+    g = make_grid(grid)
+    _dev(depth, torch.float32, "depth")
+    _dev(albedo, torch.float32, "albedo")
+    _dev(mask, torch.uint8, "mask")
+    npx = g.nx * g.ny
+    for t, name in ((depth, "depth"), (albedo, "albedo"), (mask, "mask")):
+        if t is not None and t.numel() != npx:
+            raise ValueError(f"{name} must have {g.nx}x{g.ny} elements")
+    dev = depth.device
+    if patches is None:
+        patches = torch.empty((npx, NLOS_RECORD_FLOATS), dtype=torch.float32, device=dev)
+    if n_active is None:
+        n_active = torch.empty(1, dtype=torch.int32, device=dev)
+    if out is None:
+        out = torch.empty(out_shape(params), dtype=torch.float32, device=dev)
+    _dev(out, torch.float32, "out")
+    if out.numel() != n_histograms(params) * params.n_bins:
+        raise ValueError("out has the wrong size")
+    need = C.c_size_t(0)
+    check(lib().nlos_simulate_workspace_bytes(C.byref(params), C.byref(g), C.byref(need)),
+          "nlos_simulate_workspace_bytes")
+    if workspace is None or workspace.numel() < need.value:
+        workspace = torch.empty(need.value, dtype=torch.uint8, device=dev)
+    mark = None if forward_mark is None else C.c_void_p(forward_mark.cuda_event)
+    check(lib().nlos_simulate(C.byref(params), C.byref(g), _ptr(depth), _ptr(albedo), _ptr(mask), _ptr(patches),
+                              _ptr(n_active), _ptr(out), _ptr(workspace), workspace.numel(), mark,
+                              _stream(stream)), "nlos_simulate")
+    return out, patches, n_active
 
 
 def debug_bins(params: Params, patches: torch.Tensor, n_active: Optional[torch.Tensor] = None,

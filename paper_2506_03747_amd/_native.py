@@ -70,6 +70,10 @@ SIGNATURES = [
     ("nlos_forward", C.c_int,
      [C.POINTER(Params), C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
       C.c_void_p]),
+    ("nlos_simulate_workspace_bytes", C.c_int, [C.POINTER(Params), C.POINTER(Grid), C.POINTER(C.c_size_t)]),
+    ("nlos_simulate", C.c_int,
+     [C.POINTER(Params), C.POINTER(Grid), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+      C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
     ("nlos_patches_batched_sizes", C.c_int,
      [C.POINTER(DepthRequest), C.c_int32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     ("nlos_patches_batched", C.c_int,

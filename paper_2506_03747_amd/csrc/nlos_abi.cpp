@@ -660,7 +660,7 @@ int nlos_patches_from_depth(const nlos_grid* g, const float* depth, const float*
     const int dev = device_check();
     if (dev != NLOS_OK) return dev;
     a.counts = reinterpret_cast<int32_t*>(ws);
-    a.offsets = a.counts + a.n_blocks;
+    a.offsets = a.n_blocks <= nlos::kScanFreeBlocks ? nullptr : a.counts + a.n_blocks;
     const hipError_t e = nlos::launch_geometry(a, (hipStream_t)stream);
     return e == hipSuccess ? NLOS_OK : hip_fail(e);
 }
@@ -688,9 +688,12 @@ int nlos_patches_batched(const nlos_depth_request* reqs, int32_t n, void* table,
     const int dev = device_check();
     if (dev != NLOS_OK) return dev;
     unsigned char* wsb = static_cast<unsigned char*>(ws);
+    bool need_scan = false;
     for (int i = 0; i < n; ++i) {
         b.args[i].counts = reinterpret_cast<int32_t*>(wsb + b.counts_off[i]);
-        b.args[i].offsets = b.args[i].counts + b.args[i].n_blocks;
+        const bool scan = b.args[i].n_blocks > nlos::kScanFreeBlocks;
+        b.args[i].offsets = scan ? b.args[i].counts + b.args[i].n_blocks : nullptr;
+        need_scan = need_scan || scan;
     }
     unsigned char* host = static_cast<unsigned char*>(table);
     if (!host) {
@@ -706,7 +709,7 @@ int nlos_patches_batched(const nlos_depth_request* reqs, int32_t n, void* table,
     gl.tab = reinterpret_cast<const nlos::GeomArgs*>(wsb + b.tab_off);
     gl.first = reinterpret_cast<const int64_t*>(wsb + b.first_off);
     gl.n = n;
-    e = nlos::launch_geometry_batch(gl, b.n_blocks, st);
+    e = nlos::launch_geometry_batch(gl, b.n_blocks, need_scan, st);
     return e == hipSuccess ? NLOS_OK : hip_fail(e);
 }
 
@@ -734,6 +737,61 @@ int nlos_forward(const nlos_params* p, const float* patches, int32_t n_patches, 
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = nlos::launch_stats(a, a.stats, st);
     if (e != hipSuccess) return hip_fail(e);
+    if (a.atomic_out) {
+        e = nlos::launch_fill(out, (size_t)a.out_len, st);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    e = nlos::launch_forward(a, plan, is_confocal(p), st);
+    return e == hipSuccess ? NLOS_OK : hip_fail(e);
+}
+
+int nlos_simulate_workspace_bytes(const nlos_params* p, const nlos_grid* g, size_t* bytes)
+{
+    if (!bytes || !grid_ok(g) || (int64_t)g->nx * g->ny > NLOS_MAX_PATCHES) return NLOS_EINVAL;
+    size_t geo = 0, fwd = 0;
+    int rc = nlos_patches_workspace_bytes(g, &geo);
+    if (rc != NLOS_OK) return rc;
+    rc = nlos_forward_workspace_bytes(p, g->nx * g->ny, &fwd);
+    if (rc != NLOS_OK) return rc;
+    *bytes = align_up(geo, 256) + fwd;
+    return NLOS_OK;
+}
+
+int nlos_simulate(const nlos_params* p, const nlos_grid* g, const float* depth, const float* albedo,
+                  const uint8_t* mask, float* patches, int32_t* n_active, float* out, void* ws, size_t ws_bytes,
+                  void* forward_mark, void* stream)
+{
+    nlos::GeomArgs ga;
+    int rc = geom_args(g, depth, albedo, mask, p ? p->flags : 0u, patches, n_active, &ga);
+    if (rc != NLOS_OK) return rc;
+    const int32_t n_patches = g->nx * g->ny;
+    nlos::FwdArgs a;
+    nlos::Plan plan;
+    size_t need_fwd = 0;
+    rc = setup_forward(p, patches, n_patches, n_active, out, kTargetBlocks, &a, &plan, &need_fwd);
+    if (rc != NLOS_OK) return rc;
+    size_t need = 0;
+    rc = nlos_simulate_workspace_bytes(p, g, &need);
+    if (rc != NLOS_OK) return rc;
+    if (ws_bytes < need) return NLOS_ENOSPC;
+    if (!ws || !aligned(ws, 256)) return NLOS_EINVAL;
+    const int dev = device_check();
+    if (dev != NLOS_OK) return dev;
+    size_t geo = 0;
+    nlos_patches_workspace_bytes(g, &geo);
+    unsigned char* w = static_cast<unsigned char*>(ws);
+    ga.counts = reinterpret_cast<int32_t*>(w);
+    ga.offsets = ga.n_blocks <= nlos::kScanFreeBlocks ? nullptr : ga.counts + ga.n_blocks;
+    a.stats = reinterpret_cast<nlos::ChunkStat*>(w + align_up(geo, 256));
+    ga.stats = a.stats;
+    ga.n_stats = a.n_stats;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = nlos::launch_geometry(ga, st);
+    if (e != hipSuccess) return hip_fail(e);
+    if (forward_mark) {
+        e = hipEventRecord((hipEvent_t)forward_mark, st);
+        if (e != hipSuccess) return hip_fail(e);
+    }
     if (a.atomic_out) {
         e = nlos::launch_fill(out, (size_t)a.out_len, st);
         if (e != hipSuccess) return hip_fail(e);

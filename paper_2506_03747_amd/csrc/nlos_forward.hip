@@ -257,12 +257,12 @@ __device__ __forceinline__ void chunk_stats_body(const FwdArgs& a, ChunkStat* st
         for (int w = 0; w < kStatBlock / 64; ++w)
             for (int k = 0; k < 6; ++k) r[k] = (k == 5) ? fmaxf(r[k], red[k][w]) : fminf(r[k], red[k][w]);
         ChunkStat c;
-        c.x0 = r[0];
-        c.x1 = -r[1];
-        c.y0 = r[2];
-        c.y1 = -r[3];
-        c.z0 = r[4];
-        c.amax = r[5];
+        c.x0 = ord_f(r[0]);
+        c.x1 = ord_f(-r[1]);
+        c.y0 = ord_f(r[2]);
+        c.y1 = ord_f(-r[3]);
+        c.z0 = ord_f(r[4]);
+        c.amax = ord_f(r[5]);
         c.count = max(0, min(kStatBlock, n_act - blk * kStatBlock));
         c.pad = 0;
         st[blk] = c;
@@ -325,16 +325,7 @@ template <bool CONF, int TL, int TX, int TY>
 __device__ float unit_weight_bound(const FwdArgs& a, int u, int i)
 {
     const UnitRect R = unit_rect<CONF, TL, TX, TY>(a, u);
-    const v4f c0 = gmem(reinterpret_cast<const v4f*>(a.stats))[2 * (size_t)i];
-    const v4f c1 = gmem(reinterpret_cast<const v4f*>(a.stats))[2 * (size_t)i + 1];
-    ChunkStat c;
-    c.x0 = c0.x;
-    c.x1 = c0.y;
-    c.y0 = c0.z;
-    c.y1 = c0.w;
-    c.z0 = c1.x;
-    c.amax = c1.y;
-    c.count = __float_as_int(c1.z);
+    const StatF c = load_stat(a.stats, i);
     if (c.count <= 0) return 0.f;
     const float z2 = c.z0 * c.z0;
     const float rd2 = rect_rect_d2(R.dx0, R.dx1, R.dy0, R.dy1, c.x0, c.x1, c.y0, c.y1) + z2;

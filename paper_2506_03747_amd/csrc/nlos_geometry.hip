@@ -51,6 +51,18 @@ __device__ __forceinline__ void count_body(const GeomArgs& a, int blk)
     if (p) p = is_present(a, (int64_t)ix * a.ay.n + iy);
     const int cnt = __syncthreads_count(p);
     if (threadIdx.x == 0) a.counts[blk] = cnt;
+    // record summaries (when built here): start from the identity of the merge
+    if (a.stats) {
+        for (int64_t i = (int64_t)blk * kGeomBlock + threadIdx.x; i < a.n_stats;
+             i += (int64_t)a.n_blocks * kGeomBlock) {
+            ChunkStat c;
+            c.x0 = c.y0 = c.z0 = INT32_MAX;
+            c.x1 = c.y1 = c.amax = INT32_MIN;
+            c.count = 0;
+            c.pad = 0;
+            a.stats[i] = c;
+        }
+    }
 }
 
 __global__ void __launch_bounds__(kGeomBlock) k_geom_count(const GeomArgs a) { count_body(a, (int)blockIdx.x); }
@@ -93,9 +105,31 @@ __device__ __forceinline__ float deriv(const float* d, int n, int i, int64_t str
     return (d[stride] - d[-stride]) / (2.f * h);
 }
 
+__device__ __forceinline__ int wave_min_i(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max_i(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Records of one enumeration block at base + (rank among the present pixels
+// before it).  base is the exclusive prefix of the block counts: read from
+// `offsets`, or (offsets null) summed here from the counts.  With `stats`,
+// the records' summaries are merged per wave (a wave's records touch at most
+// two summaries), per block in LDS, then into the summaries with integer
+// min / max / add atomics on their order-preserving images.
 __device__ __forceinline__ void scatter_body(const GeomArgs& a, int blk)
 {
     __shared__ int wave_cnt[kGeomBlock / 64];
+    __shared__ int red[kGeomBlock / 64];
+    __shared__ int sst[kStatSlots][7];   // x0, x1, y0, y1, z0, amax, count
     const int64_t e = (int64_t)blk * kGeomBlock + threadIdx.x;
     int ix = 0, iy = 0;
     bool p = enum_pixel(a, e, &ix, &iy);
@@ -105,21 +139,86 @@ __device__ __forceinline__ void scatter_body(const GeomArgs& a, int blk)
     const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
     const int rank = __popcll(bal & ((1ull << lane) - 1ull));
     if (lane == 0) wave_cnt[wave] = __popcll(bal);
+    if (threadIdx.x < kStatSlots * 7) {
+        const int f = threadIdx.x % 7;
+        sst[threadIdx.x / 7][f] = (f == 6) ? 0 : ((f == 0 || f == 2 || f == 4) ? INT32_MAX : INT32_MIN);
+    }
+    int base;
+    if (a.offsets) {
+        base = a.offsets[blk];
+    } else {
+        int sum = 0;
+        for (int i = threadIdx.x; i < blk; i += kGeomBlock) sum += a.counts[i];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        if (lane == 0) red[wave] = sum;
+        __syncthreads();
+        base = 0;
+        for (int w = 0; w < kGeomBlock / 64; ++w) base += red[w];
+    }
     __syncthreads();
-    if (!p) return;
-    int off = a.offsets[blk];
+    int off = base + rank;
     for (int w = 0; w < wave; ++w) off += wave_cnt[w];
-    off += rank;
+    if (!a.offsets && blk == a.n_blocks - 1 && threadIdx.x == 0) {
+        int tot = base;
+        for (int w = 0; w < kGeomBlock / 64; ++w) tot += wave_cnt[w];
+        *a.n_active = tot;
+    }
 
-    const float* D = a.depth + idx;
-    const float z = D[0];
-    const float rho = a.albedo ? a.albedo[idx] : 0.5f;
-    const float gx = deriv(D, a.ax.n, ix, a.ay.n, a.hx);
-    const float gy = deriv(D, a.ay.n, iy, 1, a.hy);
-    const float len = sqrtf(1.f + gx * gx + gy * gy);
-    const float area = a.hx * a.hy * (a.cosines ? len : 1.f);
-    a.patches[2 * (int64_t)off] = make_float4(canon(a.ax, ix), canon(a.ay, iy), z, rho * area);
-    a.patches[2 * (int64_t)off + 1] = make_float4(gx / len, gy / len, -1.f / len, __int_as_float((int)idx));
+    float4 A = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (p) {
+        const float* D = a.depth + idx;
+        const float z = D[0];
+        const float rho = a.albedo ? a.albedo[idx] : 0.5f;
+        const float gx = deriv(D, a.ax.n, ix, a.ay.n, a.hx);
+        const float gy = deriv(D, a.ay.n, iy, 1, a.hy);
+        const float len = sqrtf(1.f + gx * gx + gy * gy);
+        const float area = a.hx * a.hy * (a.cosines ? len : 1.f);
+        A = make_float4(canon(a.ax, ix), canon(a.ay, iy), z, rho * area);
+        a.patches[2 * (int64_t)off] = A;
+        a.patches[2 * (int64_t)off + 1] = make_float4(gx / len, gy / len, -1.f / len, __int_as_float((int)idx));
+    }
+    if (!a.stats) return;   // uniform across the block
+
+    const int first = base / kStatBlock;
+    const int slot = p ? off / kStatBlock - first : INT32_MAX;
+    const int s_lo = wave_min_i(slot);
+    if (s_lo != INT32_MAX) {
+#pragma unroll
+        for (int seg = 0; seg < 2; ++seg) {
+            const bool mine = p && slot == s_lo + seg;
+            const unsigned long long mb = __ballot(mine);
+            if (mb == 0ull) continue;
+            const int x0 = wave_min_i(mine ? ord_f(A.x) : INT32_MAX);
+            const int x1 = wave_max_i(mine ? ord_f(A.x) : INT32_MIN);
+            const int y0 = wave_min_i(mine ? ord_f(A.y) : INT32_MAX);
+            const int y1 = wave_max_i(mine ? ord_f(A.y) : INT32_MIN);
+            const int z0 = wave_min_i(mine ? ord_f(A.z) : INT32_MAX);
+            const int am = wave_max_i(mine ? ord_f(A.w) : INT32_MIN);
+            if (lane == 0) {
+                int* t = sst[s_lo + seg];
+                atomicMin(&t[0], x0);
+                atomicMax(&t[1], x1);
+                atomicMin(&t[2], y0);
+                atomicMax(&t[3], y1);
+                atomicMin(&t[4], z0);
+                atomicMax(&t[5], am);
+                atomicAdd(&t[6], __popcll(mb));
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kStatSlots && sst[threadIdx.x][6] > 0) {
+        const int* t = sst[threadIdx.x];
+        ChunkStat* c = a.stats + first + threadIdx.x;
+        atomicMin(&c->x0, t[0]);
+        atomicMax(&c->x1, t[1]);
+        atomicMin(&c->y0, t[2]);
+        atomicMax(&c->y1, t[3]);
+        atomicMin(&c->z0, t[4]);
+        atomicMax(&c->amax, t[5]);
+        atomicAdd(&c->count, t[6]);
+    }
 }
 
 __global__ void __launch_bounds__(kGeomBlock) k_geom_scatter(const GeomArgs a) { scatter_body(a, (int)blockIdx.x); }
@@ -142,7 +241,10 @@ __global__ void __launch_bounds__(kGeomBlock) k_geom_count_batch(const GeomList 
     count_body(g.tab[i], (int)((int64_t)blockIdx.x - g.first[i]));
 }
 
-__global__ void __launch_bounds__(1024) k_geom_scan_batch(const GeomList g) { scan_body(g.tab[blockIdx.x]); }
+__global__ void __launch_bounds__(1024) k_geom_scan_batch(const GeomList g)
+{
+    if (g.tab[blockIdx.x].offsets) scan_body(g.tab[blockIdx.x]);
+}
 
 __global__ void __launch_bounds__(kGeomBlock) k_geom_scatter_batch(const GeomList g)
 {
@@ -150,29 +252,35 @@ __global__ void __launch_bounds__(kGeomBlock) k_geom_scatter_batch(const GeomLis
     scatter_body(g.tab[i], (int)((int64_t)blockIdx.x - g.first[i]));
 }
 
+// Two launches (count, scatter) when the scatter can sum the counts itself
+// (a.offsets null), three (count, scan, scatter) otherwise.
 hipError_t launch_geometry(const GeomArgs& a, hipStream_t st)
 {
     if (a.n_blocks <= 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_geom_count, dim3(a.n_blocks), dim3(kGeomBlock), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_geom_scan, dim3(1), dim3(1024), 0, st, a);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (a.offsets) {
+        hipLaunchKernelGGL(k_geom_scan, dim3(1), dim3(1024), 0, st, a);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_geom_scatter, dim3(a.n_blocks), dim3(kGeomBlock), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_geometry_batch(const GeomList& g, int64_t n_blocks, hipStream_t st)
+hipError_t launch_geometry_batch(const GeomList& g, int64_t n_blocks, bool need_scan, hipStream_t st)
 {
     if (g.n <= 0 || n_blocks <= 0) return hipSuccess;
     if (n_blocks > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_geom_count_batch, dim3((unsigned)n_blocks), dim3(kGeomBlock), 0, st, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_geom_scan_batch, dim3((unsigned)g.n), dim3(1024), 0, st, g);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (need_scan) {
+        hipLaunchKernelGGL(k_geom_scan_batch, dim3((unsigned)g.n), dim3(1024), 0, st, g);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_geom_scatter_batch, dim3((unsigned)n_blocks), dim3(kGeomBlock), 0, st, g);
     return hipGetLastError();
 }

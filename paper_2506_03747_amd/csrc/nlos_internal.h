@@ -21,6 +21,8 @@ struct Axis {
     int32_t n;
 };
 
+struct ChunkStat;
+
 struct GeomArgs {
     const float* depth;
     const float* albedo;   // nullable -> 0.5
@@ -28,7 +30,10 @@ struct GeomArgs {
     float4* patches;       // [n][2] float4 records
     int32_t* n_active;
     int32_t* counts;       // workspace: per enumeration block
-    int32_t* offsets;      // workspace: exclusive prefix of counts
+    int32_t* offsets;      // workspace: exclusive prefix of counts; null: each
+                           // scatter block sums the counts before it
+    ChunkStat* stats;      // nullable: record summaries built while scattering
+    int32_t n_stats;
     Axis ax, ay;
     float hx, hy;          // spacings
     int32_t bx, by;        // ceil(n / 16) per axis
@@ -39,14 +44,47 @@ struct GeomArgs {
 constexpr int kGeomBlock = 1024;
 
 // Summary of one block of kStatBlock consecutive patch records: lateral
-// bounding box, smallest depth, largest a, record count.  Used to estimate
-// the work of each unit of histograms and to bound the pair weights.
+// bounding box, smallest depth, largest a, record count.  Used to bound the
+// pair weights.  The six float fields are stored as order-preserving int32
+// images (ord_f), so summaries can also be merged with integer min / max
+// atomics while the records are written.
 struct ChunkStat {
-    float x0, x1, y0, y1, z0, amax;
+    int32_t x0, x1, y0, y1, z0, amax;
     int32_t count, pad;
 };
-static_assert(sizeof(ChunkStat) == 32, "summaries are read as two float4");
+static_assert(sizeof(ChunkStat) == 32, "summaries are read as two int4");
 constexpr int kStatBlock = 256;
+constexpr int kStatSlots = kGeomBlock / kStatBlock + 1;   // summaries one geometry block can touch
+
+struct StatF {
+    float x0, x1, y0, y1, z0, amax;
+    int32_t count;
+};
+
+// f -> int32 with the same order (negative floats: magnitude bits flipped).
+__device__ __forceinline__ int32_t ord_f(float f)
+{
+    const int32_t b = __float_as_int(f);
+    return b >= 0 ? b : b ^ 0x7FFFFFFF;
+}
+
+__device__ __forceinline__ float unord_f(int32_t k) { return __int_as_float(k >= 0 ? k : k ^ 0x7FFFFFFF); }
+
+__device__ __forceinline__ StatF load_stat(const ChunkStat* st, int i)
+{
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const __attribute__((address_space(1))) v4i* g = (const __attribute__((address_space(1))) v4i*)st;
+    const v4i c0 = g[2 * (size_t)i], c1 = g[2 * (size_t)i + 1];
+    StatF r;
+    r.x0 = unord_f(c0.x);
+    r.x1 = unord_f(c0.y);
+    r.y0 = unord_f(c0.z);
+    r.y1 = unord_f(c0.w);
+    r.z0 = unord_f(c1.x);
+    r.amax = unord_f(c1.y);
+    r.count = c1.z;
+    return r;
+}
 
 // Arguments of the pair kernels (confocal and non-confocal).
 struct FwdArgs {
@@ -180,6 +218,7 @@ size_t lds_bytes_for(int slots, int stride, int q_cap);
 bool tile_supported(bool confocal, int tx, int ty, int tl);
 
 hipError_t launch_geometry(const GeomArgs& a, hipStream_t st);
+constexpr int kScanFreeBlocks = 1024;   // up to this many blocks, the scatter sums the counts itself
 hipError_t launch_forward(const FwdArgs& a, const Plan& plan, bool confocal, hipStream_t st);
 hipError_t launch_stats(const FwdArgs& a, ChunkStat* stats, hipStream_t st);
 hipError_t launch_fill(float* out, size_t n, hipStream_t st);
@@ -202,7 +241,7 @@ hipError_t launch_lct(const LctArgs& a, double2* vol, double2* psf, void* fft_wo
                       int* fft_status);
 
 // Batched launches (one launch each over all requests of the list).
-hipError_t launch_geometry_batch(const GeomList& g, int64_t n_blocks, hipStream_t st);
+hipError_t launch_geometry_batch(const GeomList& g, int64_t n_blocks, bool need_scan, hipStream_t st);
 hipError_t launch_stats_batch(const BatchList& b, int64_t n_blocks, hipStream_t st);
 constexpr int kFillBlocksPerRequest = 64;
 hipError_t launch_fill_batch(const BatchList& b, hipStream_t st);

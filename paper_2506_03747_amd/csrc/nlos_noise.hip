@@ -4,8 +4,9 @@
 // Var the population variance of the whole frame.
 //
 // k_noise_moments / k_noise_scale   frame mean and variance: per-thread
-//     Welford updates, merged pairwise (Chan et al.) within a block and then
-//     across blocks in block order, all fp64, so the result is reproducible.
+//     Welford updates, merged pairwise (Chan et al.) in fixed trees within
+//     each block and then across the blocks, all fp64, so the result is
+//     reproducible.
 // k_poisson   one element per thread (grid-stride).  Uniform t of element i
 //     is word t mod 4 of Philox4x64-10 (Salmon, Moraes, Dror and Shaw, SC
 //     2011) at counter (i, t / 4, 0, 0), key (seed, 0x4e4c4f53), scaled from
@@ -82,17 +83,21 @@ __global__ void __launch_bounds__(kNoiseBlock) k_noise_moments(const float* tau,
     }
 }
 
-// One workgroup: merge the block moments in block order -> mean, population
+// One workgroup: thread t merges blocks t, t + 256, ... in order, then the
+// per-thread moments are merged pairwise in a fixed tree -> mean, population
 // variance, sigma_n.
 __global__ void __launch_bounds__(kNoiseBlock) k_noise_scale(const double* part, int nb, double nr_db, double* out)
 {
-    if (threadIdx.x != 0) return;
     Moments m{0.0, 0.0, 0.0};
-    for (int b = 0; b < nb; ++b) m = merge(m, Moments{part[3 * b], part[3 * b + 1], part[3 * b + 2]});
-    const double var = m.n > 0.0 ? m.m2 / m.n : 0.0;
-    out[0] = m.mean;
-    out[1] = var;
-    out[2] = var / pow(10.0, nr_db / 10.0);
+    for (int b = threadIdx.x; b < nb; b += kNoiseBlock)
+        m = merge(m, Moments{part[3 * b], part[3 * b + 1], part[3 * b + 2]});
+    m = block_merge(m);
+    if (threadIdx.x == 0) {
+        const double var = m.n > 0.0 ? m.m2 / m.n : 0.0;
+        out[0] = m.mean;
+        out[1] = var;
+        out[2] = var / pow(10.0, nr_db / 10.0);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth(const SmoothArgs a)
         const float x0 = fminf(wx[0], wx[TX - 1]), x1 = fmaxf(wx[0], wx[TX - 1]);
         const float y0 = fminf(wy[0], wy[TY - 1]), y1 = fmaxf(wy[0], wy[TY - 1]);
         for (int i = threadIdx.x; i < a.n_stats; i += blockDim.x) {
-            const ChunkStat c = a.stats[i];
+            const StatF c = load_stat(a.stats, i);
             if (c.count <= 0) continue;
             const float ddx = fmaxf(fmaxf(x0 - c.x1, c.x0 - x1), 0.f);
             const float ddy = fmaxf(fmaxf(y0 - c.y1, c.y0 - y1), 0.f);

@@ -26,7 +26,7 @@ def declared_functions():
 
 def test_exports_every_declared_symbol(nat):
     names = declared_functions()
-    assert len(names) == 23, names
+    assert len(names) == 25, names
     for n in names:
         assert hasattr(nat.lib(), n), n
     bound = {s[0] for s in nat.SIGNATURES}
@@ -277,3 +277,22 @@ def test_lct_checks(nat):
         assert L.nlos_lct_workspace_bytes(C.byref(q), C.byref(need)) == nat.NLOS_EINVAL
         assert L.nlos_lct_forward(C.byref(q), FAKE, None, None, FAKE, FAKE, 1 << 30, None) == nat.NLOS_EINVAL
     assert L.nlos_lct_forward(C.byref(p), None, None, None, FAKE, FAKE, 1 << 30, None) == nat.NLOS_EINVAL
+
+
+def test_simulate_checks(nat):
+    L = nat.lib()
+    p = _params(nat)
+    g = nat.Grid(64, 64, 0.5, 0.5, 0.0, 0.0)
+    need, geo, fwd = C.c_size_t(0), C.c_size_t(0), C.c_size_t(0)
+    assert L.nlos_simulate_workspace_bytes(C.byref(p), C.byref(g), C.byref(need)) == 0
+    L.nlos_patches_workspace_bytes(C.byref(g), C.byref(geo))
+    L.nlos_forward_workspace_bytes(C.byref(p), 64 * 64, C.byref(fwd))
+    assert need.value >= geo.value + fwd.value
+    args = (FAKE, None, None, FAKE, FAKE, FAKE)
+    assert L.nlos_simulate(C.byref(p), C.byref(g), *args, FAKE, need.value - 1, None, None) == nat.NLOS_ENOSPC
+    assert L.nlos_simulate(C.byref(p), C.byref(g), *args, C.c_void_p(0x10010), need.value, None,
+                           None) == nat.NLOS_EINVAL
+    assert L.nlos_simulate(C.byref(p), C.byref(g), None, None, None, FAKE, FAKE, FAKE, FAKE, need.value, None,
+                           None) == nat.NLOS_EINVAL
+    bad = _params(nat, bin_ps=0.0)
+    assert L.nlos_simulate(C.byref(bad), C.byref(g), *args, FAKE, 1 << 30, None, None) == nat.NLOS_EINVAL

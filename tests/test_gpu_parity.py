@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import scenes
-from gpu_helpers import (assert_parity, gpu_forward, gpu_patches, guard_delta, log,
+from gpu_helpers import (assert_parity, gpu_forward, gpu_patches, guard_delta, log, to_gpu,
                          oracle_bins_for_records)
 
 pytestmark = pytest.mark.gpu
@@ -292,3 +292,70 @@ def test_repeatable_within_tolerance():
     a, _, _ = gpu_forward(sc)
     b, _, _ = gpu_forward(sc)
     assert_parity(a.cpu().numpy(), b.cpu().numpy().astype(np.float64), tol=1e-6, what="repeat")
+
+
+@pytest.mark.parametrize("make", [scenes.cfg1, scenes.cfg2, scenes.cfg3,
+                                  lambda: scenes.tiny(seed=510, scan=(2, 2), patches=(160, 160), n_bins=256,
+                                                      bin_ps=20.0, fwhm_ps=60.0, masked=False),
+                                  lambda: scenes.tiny(seed=511, scan=(2, 3), patches=(24, 24), n_bins=50000,
+                                                      bin_ps=2.0, fwhm_ps=40.0, zlo=0.5, zhi=4.0, half=2.0)],
+                         ids=["cfg1", "cfg2", "cfg3", "split", "windows"])
+def test_simulate_equals_two_calls(make):
+    """One call (geometry + summaries merged while scattering + forward)
+    gives the records, count and histograms of the two calls (bit for bit:
+    the same summaries give the same fixed-point scale)."""
+    import torch
+    import paper_2506_03747_amd as nl
+    sc = make()
+    log(f"simulate {sc.name}")
+    depth, albedo, mask = to_gpu(sc)
+    prm = nl.params_of(sc)
+    out, rec, n = nl.simulate(prm, depth, sc.patch_grid, albedo, mask)
+    rec2, n2 = nl.patches_from_depth(depth, sc.patch_grid, albedo, mask, cosines=sc.cosines)
+    out2 = nl.forward(prm, rec2, n2)
+    torch.cuda.synchronize()
+    k = int(n.item())
+    assert k == int(n2.item())
+    np.testing.assert_array_equal(rec[:k].cpu().numpy().view(np.uint32), rec2[:k].cpu().numpy().view(np.uint32))
+    # identical summaries -> identical fixed-point scale -> identical bins;
+    # only workgroups that split the patches add partials in a varying order
+    assert_parity(out.cpu().numpy(), out2.cpu().numpy().astype(np.float64), tol=1e-6, what="simulate")
+    if sc.name == "cfg2":
+        np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), out2.cpu().numpy().view(np.uint32))
+
+
+def test_simulate_empty_scene():
+    import torch
+    import paper_2506_03747_amd as nl
+    sc = scenes.tiny(seed=512, scan=(4, 4), patches=(8, 8))
+    sc.mask = np.zeros_like(sc.mask)
+    depth, albedo, mask = to_gpu(sc)
+    out, _, n = nl.simulate(nl.params_of(sc), depth, sc.patch_grid, albedo, mask)
+    torch.cuda.synchronize()
+    assert int(n.item()) == 0 and not out.cpu().numpy().any()
+
+
+def test_large_map_uses_scan_path():
+    """A depth map of more than 1024 enumeration blocks (1056 x 1024 pixels):
+    block offsets come from the scan kernel; every present pixel appears
+    exactly once and the one-call path agrees with the two calls."""
+    import torch
+    import paper_2506_03747_amd as nl
+    rng = np.random.default_rng(77)
+    nx, ny = 1056, 1024
+    depth = rng.uniform(0.3, 0.6, (nx, ny)).astype(np.float32)
+    mask = (rng.uniform(size=(nx, ny)) < 0.3).astype(np.uint8)
+    grid = scenes.grid(nx, ny, 0.5)
+    d, m = torch.from_numpy(depth).cuda(), torch.from_numpy(mask).cuda()
+    rec, n = nl.patches_from_depth(d, grid, None, m)
+    torch.cuda.synchronize()
+    k = int(n.item())
+    assert k == int(mask.sum())
+    idx = np.sort(rec[:k].cpu().numpy()[:, 7].view(np.int32))
+    np.testing.assert_array_equal(idx, np.nonzero(mask.ravel())[0])
+    prm = nl.make_params(scenes.grid(2, 2, 0.5), 64, 50.0, 120.0)
+    out, rec1, n1 = nl.simulate(prm, d, grid, None, m)
+    out2 = nl.forward(prm, rec, n)
+    torch.cuda.synchronize()
+    assert int(n1.item()) == k
+    assert_parity(out.cpu().numpy(), out2.cpu().numpy().astype(np.float64), tol=1e-6, what="large map")
