@@ -28,6 +28,25 @@ FLOPS_CONFOCAL = 29      # nominal flops per confocal pair (formula written with
 FLOPS_NONCONFOCAL = 48   # per non-confocal (laser, detector, patch) triple
 FP32_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
 
+# HBM bytes per launch of the cfg2 pair kernel from rocprofv3 counters
+# (FETCH_SIZE 4310 KiB x 2.0 + WRITE_SIZE 16384 KiB x 1.0; the factors are
+# what the same counters read for a 256 MiB device copy, see
+# profiles/k_forward_cfg2_hbm_counters.md), valid only for the kernel sources
+# they were taken on (hash below); any other source reports null.
+TRAFFIC_BYTES = (4310.1 * 2.0 + 16384.0 * 1.0) * 1024
+TRAFFIC_SOURCES = ("paper_2506_03747_amd/csrc/nlos_forward.hip", "paper_2506_03747_amd/csrc/nlos_device.h",
+                   "paper_2506_03747_amd/csrc/nlos_internal.h")
+TRAFFIC_HASH = "7c382498e178c239"
+
+
+def traffic_for_sources():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return TRAFFIC_BYTES if h.hexdigest()[:16] == TRAFFIC_HASH else None
+
 WORKLOADS = {
     "cfg2": "confocal 64x64 scan on 2x2 m wall, 256x256 patch depth map in [0.4,1.2] m with blob mask, "
             "albedo U[0,1], T=1024 x 8 ps, FWHM 50 ps, no stand-off",
@@ -51,6 +70,9 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replayed step timing")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the smooth forward / adjoint leg")
     ap.add_argument("--no-lct", action="store_true", help="skip the FFT-route leg")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
+                    help="also run a plain device copy of this size (3 times), the known-size reference for "
+                         "the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs the operator on a single MI355X "
@@ -99,6 +121,15 @@ def main():
             check(rc, "nlos_simulate")
         if ev is not None:
             ev[1].record(cur)
+
+    if args.copy_calibration > 0:
+        n_b = args.copy_calibration << 20
+        src = torch.ones(n_b // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         step()
@@ -180,7 +211,7 @@ def main():
                        "p99": round(float(np.percentile(step_ms, 99)), 5)},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                     "traffic": None, "kernel": "k_forward",
+                     "traffic": traffic_for_sources() if args.workload == "cfg2" else None, "kernel": "k_forward",
                      "kernel_ms": round(kern_avg, 5), "flops_per_pair": F},
         "cpu_baseline": cpu,
         "graph": graph,
