@@ -357,6 +357,39 @@ int nlos_lct_forward(const nlos_params* p, const float* depth, const float* albe
                      float* out, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Launch planning.  The forward groups histograms in units (confocal: TX x TY
+ * scan points; non-confocal: TL laser points x TX x TY detectors; supported:
+ * confocal 4x4, 4x2, 2x2, 2x1, 1x1; non-confocal TL,TX,TY = 2,2,2 / 2,1,2 /
+ * 1,1,2 / 1,1,1).  A tuning table, measured by the autotuner, names the unit
+ * per class of problems; the first matching entry whose unit fits in LDS is
+ * used, otherwise the built-in rule (largest unit that fits and still gives
+ * one workgroup per CU).  The table is the library's only shared state: it is
+ * copied, read under a lock, and replaced as a whole.
+ */
+typedef struct nlos_tuning_entry {
+    int32_t confocal;        /* 1: confocal, 0: non-confocal */
+    int32_t t_min, t_max;    /* n_bins range, inclusive */
+    int64_t h_min, h_max;    /* histogram count range (S or L*S), inclusive */
+    int32_t tl, tx, ty;      /* unit */
+} nlos_tuning_entry;
+
+typedef struct nlos_plan_info {
+    int32_t tl, tx, ty;      /* unit */
+    int32_t pair;            /* 1: two units per workgroup over the whole window */
+    int32_t n_split;         /* patch ranges per unit pair */
+    int32_t n_windows;       /* time windows (1 unless a histogram exceeds LDS) */
+    int64_t workgroups;
+    int64_t lds_bytes;
+} nlos_plan_info;
+
+/* Replace the tuning table (n = 0 clears it).  Entries naming an unsupported
+ * unit or an empty range are rejected (the table is then left unchanged). */
+int nlos_set_tuning(const nlos_tuning_entry* entries, int32_t n);
+
+/* The plan nlos_forward would use for these parameters (host only). */
+int nlos_get_plan(const nlos_params* p, int32_t n_patches, nlos_plan_info* info);
+
+/*
  * Test hook: the bin index of every (histogram, record) pair, decided by the
  * same device functions and the same fp32-then-fp64 rule as nlos_forward.
  *   bins    device int32 [H][n_patches], H = histograms of the output

@@ -15,19 +15,22 @@ on the wall plane z = 0); maps are [nx, ny] (x major).
 from __future__ import annotations
 
 import ctypes as C
+import json
+import os
 from typing import Optional
 
 import torch
 
+from ._native import TUNING_PATH  # noqa: F401
 from ._native import (NLOS_F_COSINES, NLOS_MAX_BINS, NLOS_MAX_PATCHES, NLOS_MAX_RADIUS,  # noqa: F401
-                      NLOS_RECORD_FLOATS, DepthRequest, Grid, NlosError, Params, Request, check, lib,
-                      strerror)
+                      NLOS_RECORD_FLOATS, DepthRequest, Grid, NlosError, Params, PlanInfo, Request, TuningEntry,
+                      check, lib, strerror)
 
 __all__ = ["Grid", "Params", "NlosError", "make_grid", "make_params", "params_of",
            "patches_from_depth", "forward", "simulate", "debug_bins", "out_shape", "n_histograms",
            "Batcher", "patches_batched", "forward_batched", "forward_smooth", "adjoint", "patches_adjoint",
            "SmoothTransient", "smooth_transient", "noise_scale", "poisson_noise", "add_poisson_noise",
-           "lct_forward"]
+           "lct_forward", "set_tuning", "get_plan", "load_tuning", "reset_tuning", "TUNING_PATH"]
 
 
 def make_grid(g) -> Grid:
@@ -468,3 +471,38 @@ def lct_forward(params: Params, depth: torch.Tensor, albedo: Optional[torch.Tens
     check(lib().nlos_lct_forward(C.byref(params), _ptr(depth), _ptr(albedo), _ptr(mask), _ptr(out), _ptr(workspace),
                                  workspace.numel(), _stream(stream)), "nlos_lct_forward")
     return out
+
+
+def set_tuning(entries) -> None:
+    """Install a tuning table: a list of dicts with confocal, t_min, t_max,
+    h_min, h_max, tl, tx, ty (an empty list clears it)."""
+    n = len(entries)
+    arr = (TuningEntry * max(n, 1))()
+    for i, e in enumerate(entries):
+        arr[i] = TuningEntry(int(e["confocal"]), int(e["t_min"]), int(e["t_max"]), int(e["h_min"]),
+                             int(e["h_max"]), int(e["tl"]), int(e["tx"]), int(e["ty"]))
+    check(lib().nlos_set_tuning(arr, n), "nlos_set_tuning")
+
+
+def get_plan(params: Params, n_patches: int) -> dict:
+    """The launch plan nlos_forward would use (unit, pairing, split, windows)."""
+    info = PlanInfo()
+    check(lib().nlos_get_plan(C.byref(params), int(n_patches), C.byref(info)), "nlos_get_plan")
+    return {k: getattr(info, k) for k, _ in PlanInfo._fields_}
+
+
+def load_tuning(path: str = TUNING_PATH) -> bool:
+    """Install the table written by the autotuner, if there is one."""
+    if not os.path.exists(path):
+        return False
+    with open(path) as f:
+        set_tuning(json.load(f)["entries"])
+    return True
+
+
+def reset_tuning() -> None:
+    """Back to the table installed at load: tuning.json if present (and
+    NLOS_NO_TUNING unset), else none."""
+    set_tuning([])
+    if not os.environ.get("NLOS_NO_TUNING"):
+        load_tuning()

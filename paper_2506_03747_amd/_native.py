@@ -46,6 +46,17 @@ class Request(C.Structure):
                 ("n_active", C.c_void_p), ("out", C.c_void_p)]
 
 
+class TuningEntry(C.Structure):
+    _fields_ = [("confocal", C.c_int32), ("t_min", C.c_int32), ("t_max", C.c_int32), ("h_min", C.c_int64),
+                ("h_max", C.c_int64), ("tl", C.c_int32), ("tx", C.c_int32), ("ty", C.c_int32)]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("tl", C.c_int32), ("tx", C.c_int32), ("ty", C.c_int32), ("pair", C.c_int32),
+                ("n_split", C.c_int32), ("n_windows", C.c_int32), ("workgroups", C.c_int64),
+                ("lds_bytes", C.c_int64)]
+
+
 class NlosError(RuntimeError):
     def __init__(self, code: int, where: str, hip: int = 0):
         self.code = code
@@ -100,6 +111,8 @@ SIGNATURES = [
     ("nlos_lct_workspace_bytes", C.c_int, [C.POINTER(Params), C.POINTER(C.c_size_t)]),
     ("nlos_lct_forward", C.c_int,
      [C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("nlos_set_tuning", C.c_int, [C.POINTER(TuningEntry), C.c_int32]),
+    ("nlos_get_plan", C.c_int, [C.POINTER(Params), C.c_int32, C.POINTER(PlanInfo)]),
     ("nlos_debug_bins", C.c_int,
      [C.POINTER(Params), C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
       C.c_void_p]),
@@ -118,8 +131,29 @@ def lib():
             fn = getattr(h, name)
             fn.restype = res
             fn.argtypes = args
+        _install_tuning(h)
         _lib = h
     return _lib
+
+
+TUNING_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+
+
+def _install_tuning(h) -> None:
+    """Install the autotuner's table (tuning.json beside the library) unless
+    NLOS_NO_TUNING is set; without a table the library's built-in rule plans."""
+    if os.environ.get("NLOS_NO_TUNING") or not os.path.exists(TUNING_PATH):
+        return
+    import json
+    with open(TUNING_PATH) as f:
+        ents = json.load(f)["entries"]
+    arr = (TuningEntry * max(len(ents), 1))()
+    for i, e in enumerate(ents):
+        arr[i] = TuningEntry(int(e["confocal"]), int(e["t_min"]), int(e["t_max"]), int(e["h_min"]),
+                             int(e["h_max"]), int(e["tl"]), int(e["tx"]), int(e["ty"]))
+    rc = h.nlos_set_tuning(arr, len(ents))
+    if rc != NLOS_OK:
+        raise RuntimeError(f"{TUNING_PATH}: rejected by nlos_set_tuning ({h.nlos_strerror(rc).decode()})")
 
 
 def strerror(code: int) -> str:

@@ -161,6 +161,25 @@ int64_t stats_count(int32_t n_patches) { return ((int64_t)n_patches + nlos::kSta
 // over a window of bins (time windows).  Patches are split over workgroups
 // when there are fewer workgroups than CUs.  Units are ordered by estimated
 // work inside the kernel when their count keeps that cheap.
+// Tuning table (nlos_set_tuning): the unit shape to use per (geometry,
+// window length, histogram count) class, found by measurement.  Read under a
+// lock by every plan; replaced as a whole.
+std::mutex g_tune_mu;
+std::vector<nlos_tuning_entry> g_tune;
+
+bool tuned_unit(bool conf, int32_t T, int64_t H, Cand* c)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& e : g_tune) {
+        if ((e.confocal != 0) != conf || T < e.t_min || T > e.t_max || H < e.h_min || H > e.h_max) continue;
+        c->tl = e.tl;
+        c->tx = e.tx;
+        c->ty = e.ty;
+        return true;
+    }
+    return false;
+}
+
 int make_plan(const nlos_params* p, int32_t n_patches, int R, int64_t target, nlos::Plan* plan)
 {
     const bool conf = is_confocal(p);
@@ -168,6 +187,18 @@ int make_plan(const nlos_params* p, int32_t n_patches, int R, int64_t target, nl
     static const Cand nc_c[] = {{2, 2, 2}, {2, 1, 2}, {1, 1, 2}, {1, 1, 1}};
     const Cand* cands = conf ? conf_c : nc_c;
     const int nc = conf ? 5 : 4;
+    // a tuned shape comes first among the candidates (it is used when its
+    // histograms fit in LDS; the usual rule decides otherwise)
+    Cand tuned_list[6];
+    Cand tuned;
+    if (tuned_unit(conf, p->n_bins, n_hist(p), &tuned)) {
+        int k = 0;
+        tuned_list[k++] = tuned;
+        for (int i = 0; i < nc; ++i)
+            if (cands[i].tl != tuned.tl || cands[i].tx != tuned.tx || cands[i].ty != tuned.ty) tuned_list[k++] = cands[i];
+        cands = tuned_list;
+    }
+    const bool forced = cands == tuned_list;
     const int T = p->n_bins;
     const int64_t L = conf ? 1 : (int64_t)p->laser.nx * p->laser.ny;
     int q_cap = kQueueDefault;
@@ -187,7 +218,7 @@ int make_plan(const nlos_params* p, int32_t n_patches, int R, int64_t target, nl
         const int slots = 2 * cands[i].tl * cands[i].tx * cands[i].ty;
         if (nlos::lds_bytes_for(slots, stride_of(T), q_cap) > kLdsMax) continue;
         if (largest < 0) largest = i;
-        if ((units_of(cands[i]) + 1) / 2 >= target) {
+        if ((forced && i == 0) || (units_of(cands[i]) + 1) / 2 >= target) {
             chosen = i;
             break;
         }
@@ -1086,6 +1117,40 @@ int nlos_lct_forward(const nlos_params* p, const float* depth, const float* albe
         g_last_hip = -1;
         return NLOS_EHIP;
     }
+    return NLOS_OK;
+}
+
+int nlos_set_tuning(const nlos_tuning_entry* entries, int32_t n)
+{
+    if (n < 0 || (n > 0 && !entries) || n > 4096) return NLOS_EINVAL;
+    for (int32_t i = 0; i < n; ++i) {
+        const nlos_tuning_entry& e = entries[i];
+        if (e.t_min > e.t_max || e.h_min > e.h_max || !nlos::tile_supported(e.confocal != 0, e.tx, e.ty, e.tl))
+            return NLOS_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.assign(entries, entries + n);
+    return NLOS_OK;
+}
+
+int nlos_get_plan(const nlos_params* p, int32_t n_patches, nlos_plan_info* info)
+{
+    if (params_ok(p) != NLOS_OK || !info || n_patches < 0 || n_patches > NLOS_MAX_PATCHES) return NLOS_EINVAL;
+    float taps[nlos::kMaxTaps];
+    int32_t R = 0;
+    int rc = jitter_taps(p->fwhm_ps, p->bin_ps, taps, &R);
+    if (rc != NLOS_OK) return rc;
+    nlos::Plan plan;
+    rc = make_plan(p, n_patches, R, kTargetBlocks, &plan);
+    if (rc != NLOS_OK) return rc;
+    info->tl = plan.tl;
+    info->tx = plan.tx;
+    info->ty = plan.ty;
+    info->pair = plan.pair;
+    info->n_split = plan.n_split;
+    info->n_windows = plan.n_tw;
+    info->workgroups = plan.n_blocks;
+    info->lds_bytes = (int64_t)plan.lds_bytes;
     return NLOS_OK;
 }
 

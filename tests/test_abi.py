@@ -26,7 +26,7 @@ def declared_functions():
 
 def test_exports_every_declared_symbol(nat):
     names = declared_functions()
-    assert len(names) == 25, names
+    assert len(names) == 27, names
     for n in names:
         assert hasattr(nat.lib(), n), n
     bound = {s[0] for s in nat.SIGNATURES}
@@ -296,3 +296,69 @@ def test_simulate_checks(nat):
                            None) == nat.NLOS_EINVAL
     bad = _params(nat, bin_ps=0.0)
     assert L.nlos_simulate(C.byref(bad), C.byref(g), *args, FAKE, 1 << 30, None, None) == nat.NLOS_EINVAL
+
+
+def test_tuning_table_and_plan(nat):
+    """The tuning table steers the plan; bad entries are rejected."""
+    L = nat.lib()
+    p = _params(nat, n_bins=1024)
+    p.relay.nx = p.relay.ny = 64
+    info = nat.PlanInfo()
+    assert L.nlos_set_tuning(None, 0) == 0  # the built-in rule
+    assert L.nlos_get_plan(C.byref(p), 30000, C.byref(info)) == 0
+    default = (info.tl, info.tx, info.ty)
+    E = nat.TuningEntry
+    for unit in ((1, 2, 2), (1, 4, 4), (1, 2, 1)):
+        tab = (E * 1)(E(1, 512, 2048, 1, 1 << 20, *unit))
+        assert L.nlos_set_tuning(tab, 1) == 0
+        assert L.nlos_get_plan(C.byref(p), 30000, C.byref(info)) == 0
+        if unit == (1, 4, 4):
+            # 2 x 16 histograms of 1024 u64 bins do not fit in LDS: the rule decides
+            assert (info.tl, info.tx, info.ty) == default
+        else:
+            assert (info.tl, info.tx, info.ty) == unit
+    other = (E * 1)(E(1, 1, 100, 1, 1 << 20, 1, 2, 1))      # class that does not match
+    assert L.nlos_set_tuning(other, 1) == 0
+    L.nlos_get_plan(C.byref(p), 30000, C.byref(info))
+    assert (info.tl, info.tx, info.ty) == default
+    bad = (E * 1)(E(1, 1, 100, 1, 10, 1, 3, 3))              # unsupported unit
+    assert L.nlos_set_tuning(bad, 1) == nat.NLOS_EINVAL
+    bad2 = (E * 1)(E(0, 200, 100, 1, 10, 2, 2, 2))           # empty range
+    assert L.nlos_set_tuning(bad2, 1) == nat.NLOS_EINVAL
+    assert L.nlos_set_tuning(None, 0) == 0
+    L.nlos_get_plan(C.byref(p), 30000, C.byref(info))
+    assert (info.tl, info.tx, info.ty) == default
+    nat._install_tuning(L)                  # the table the package installed at load
+
+
+def test_tuning_file_is_installed(tmp_path, monkeypatch):
+    """tuning.json beside the library is installed when the library loads."""
+    import json
+    from paper_2506_03747_amd import _native
+    tab = tmp_path / "tuning.json"
+    tab.write_text(json.dumps({"entries": [dict(confocal=1, t_min=512, t_max=2048, h_min=1, h_max=1 << 20,
+                                                tl=1, tx=2, ty=1)]}))
+    monkeypatch.setattr(_native, "TUNING_PATH", str(tab))
+    monkeypatch.setattr(_native, "_lib", None)
+    L = _native.lib()
+    try:
+        p = _params(_native, n_bins=1024)
+        p.relay.nx = p.relay.ny = 64
+        info = _native.PlanInfo()
+        assert L.nlos_get_plan(C.byref(p), 30000, C.byref(info)) == 0
+        assert (info.tl, info.tx, info.ty) == (1, 2, 1)
+    finally:
+        L.nlos_set_tuning(None, 0)
+        _native._install_tuning(L)
+    tab.write_text(json.dumps({"entries": [dict(confocal=1, t_min=512, t_max=2048, h_min=1, h_max=9,
+                                                tl=1, tx=3, ty=3)]}))
+    monkeypatch.setattr(_native, "_lib", None)
+    with pytest.raises(RuntimeError, match="rejected"):
+        _native.lib()
+    monkeypatch.setattr(_native, "_lib", None)
+    monkeypatch.setenv("NLOS_NO_TUNING", "1")
+    _native.lib()
+    monkeypatch.delenv("NLOS_NO_TUNING")
+    monkeypatch.undo()
+    _native.lib().nlos_set_tuning(None, 0)
+    _native._install_tuning(_native.lib())
