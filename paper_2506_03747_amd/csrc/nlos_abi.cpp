@@ -203,12 +203,13 @@ int make_plan(const nlos_params* p, int32_t n_patches, int R, int64_t target, nl
     const int64_t L = conf ? 1 : (int64_t)p->laser.nx * p->laser.ny;
     int q_cap = kQueueDefault;
 
-    // u64 bins per histogram row (at least tl),
-    // and reused by the flush as float rows padded with PAD = RM + 8 zeros on
-    // both sides (RM = R rounded up to 4, 8, 16), so 2 * stride >= tl + 2 PAD
+    // u64 bins per histogram row (at least tl + 1: bin tl is a spare that
+    // takes the pairs just past the window), even, and reused by the flush as
+    // float rows padded with PAD = RM + 8 zeros on both sides (RM = R rounded
+    // up to 4, 8, 16), so 2 * stride >= tl + 2 PAD
     const int RM = R <= 4 ? 4 : (R <= 8 ? 8 : (R <= 16 ? 16 : R));
     const int PAD = RM + 8;
-    auto stride_of = [PAD](int tl) { return std::max((tl + 1) & ~1, ((tl + 2 * PAD + 1) / 2 + 1) & ~1); };
+    auto stride_of = [PAD](int tl) { return std::max((tl + 2) & ~1, ((tl + 2 * PAD + 1) / 2 + 1) & ~1); };
     auto units_of = [&](const Cand& c) {
         return ((L + c.tl - 1) / c.tl) * (int64_t)((p->relay.nx + c.tx - 1) / c.tx) *
                (int64_t)((p->relay.ny + c.ty - 1) / c.ty);
@@ -250,7 +251,7 @@ int make_plan(const nlos_params* p, int32_t n_patches, int R, int64_t target, nl
     plan->stride = stride_of(tl_len);
     plan->q_cap = q_cap;
     plan->lds_bytes = nlos::lds_bytes_for(slots, plan->stride, q_cap);
-    if (plan->lds_bytes > kLdsMax || plan->stride < tl_len) return NLOS_EINVAL;
+    if (plan->lds_bytes > kLdsMax || plan->stride <= tl_len) return NLOS_EINVAL;
     const int64_t units = units_of(c);
     const int64_t groups = pair ? (units + 1) / 2 : units;
     // torus-shift pairing needs an even side in the unit plane (x or y)

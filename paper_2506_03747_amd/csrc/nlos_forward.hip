@@ -45,22 +45,23 @@ namespace nlos {
 
 typedef unsigned long long u64;
 
+constexpr int kQueueWaves = kBlock / 64;   // the guard queue has one segment per wavefront
+
 size_t lds_bytes_for(int slots, int stride, int q_cap)
 {
     size_t b = (size_t)slots * (size_t)stride * 8;   // u64 histograms
-    b += (size_t)q_cap * 8;                            // queue: index + increment
+    b += (size_t)q_cap * 8;                            // queue: (record, slot) + increment
     b += (size_t)slots * 8;                            // fp64 path offset per slot
     b += (size_t)slots * 8;                            // output row per slot
     b += (size_t)slots * 4 * 8;                        // fp32 tables
-    b += 16 + 64 * 4;                                  // counter, reduction scratch (64 floats)
+    b += kQueueWaves * 4 + 64 * 4;                     // queue fill per wave, reduction scratch
     return (b + 255) & ~(size_t)255;
 }
 
 // LDS layout (8-byte aligned: histograms, queue and fp64 table come first).
 struct Lds {
     u64* hist;
-    uint32_t* qidx;
-    uint32_t* qinc;
+    uint2* q;       // guard queue: kQueueWaves segments of (record << 8 | slot, increment)
     double* so;     // [slots] fp64 path offset o (both device legs)
     long long* row; // [slots] output histogram index, -1: not written
     float* wlx;     // [slots] laser point (confocal: = detector point)
@@ -71,7 +72,7 @@ struct Lds {
     float* oid;     // [slots] fp32(o_d * inv)           (confocal: unused)
     float* gg;      // [slots] g_l * g_d
     float* pad;
-    uint32_t* qcount;
+    uint32_t* qcount;   // [kQueueWaves] entries in each segment
     float* red;     // [64] per-wave reduction scratch
 };
 
@@ -79,9 +80,8 @@ __device__ __forceinline__ Lds lds_layout(unsigned char* base, int slots, int st
 {
     Lds L;
     L.hist = (u64*)base;
-    L.qidx = (uint32_t*)(L.hist + (size_t)slots * stride);
-    L.qinc = L.qidx + q_cap;
-    L.so = (double*)(L.qinc + q_cap);
+    L.q = (uint2*)(L.hist + (size_t)slots * stride);
+    L.so = (double*)(L.q + q_cap);
     L.row = (long long*)(L.so + slots);
     L.wlx = (float*)(L.row + slots);
     L.wly = L.wlx + slots;
@@ -92,7 +92,7 @@ __device__ __forceinline__ Lds lds_layout(unsigned char* base, int slots, int st
     L.gg = L.oid + slots;
     L.pad = L.gg + slots;
     L.qcount = (uint32_t*)(L.pad + slots);
-    L.red = (float*)(L.qcount + 4);
+    L.red = (float*)(L.qcount + kQueueWaves);
     return L;
 }
 
@@ -172,57 +172,92 @@ __device__ __forceinline__ int active_count(const FwdArgs& a)
     return n;
 }
 
-// Queue overflow: re-bin the pair in fp64 right away (out of line: it is
-// rare, and keeping it out of the unrolled pair loop keeps its fp64 work off
-// the common path).
-__device__ __attribute__((noinline)) void guard_overflow(u64* hist_row, const float4* patches, int p,
+__device__ __forceinline__ void lds_sub(u64* p, uint32_t dec)
+{
+    __hip_atomic_fetch_add(p, 0ull - (u64)dec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Guard correction: the pair was added at its fp32 bin kf (0 <= kf <= Tl);
+// move it to the fp64 bin when they differ (the row sums are exact modulo
+// 2^64, and every final bin is a sum of non-negative increments).
+__device__ __forceinline__ void guard_fix(u64* hist_row, int kf, int ke, int Tl, uint32_t inc)
+{
+    if (ke == kf) return;
+    lds_sub(hist_row + kf, inc);
+    if ((unsigned)ke < (unsigned)Tl) lds_add(hist_row + ke, inc);
+}
+
+// Queue overflow: correct the pair right away (out of line: it is rare, and
+// keeping it out of the unrolled pair loop keeps its fp64 work off the
+// common path).
+__device__ __attribute__((noinline)) void guard_overflow(u64* hist_row, const float4* patches, int p, int kf,
                                                          float wlx, float wly, float wdx, float wdy,
                                                          double o, double inv, int hb, int Tl, uint32_t inc)
 {
     const float4 A = load4(patches, 2 * (size_t)p);
-    const int kl = exact_bin(A.x, A.y, A.z, wlx, wly, wdx, wdy, o, inv) - hb;
-    if ((unsigned)kl < (unsigned)Tl) lds_add(hist_row + kl, inc);
+    guard_fix(hist_row, kf, exact_bin(A.x, A.y, A.z, wlx, wly, wdx, wdy, o, inv) - hb, Tl, inc);
 }
 
-// Push a guard pair to the LDS queue (re-binned in fp64 before the flush).
-__device__ __forceinline__ void guard_push(const Lds& L, const FwdArgs& a, int p, int j, uint32_t inc, int hb,
-                                           int Tl)
+// Guard pairs: every pair whose fp32 bin lies in 0 .. Tl is added there; the
+// pairs whose fp32 arrival lies within the guard band of a bin edge (lane
+// mask `m`, uniform, every lane of the wavefront present) are also queued and
+// moved to their fp64 bin after the pair loop.  Each wavefront appends to its
+// own queue segment (qw entries) and keeps the fill `qn`, uniform, in a
+// register, so a push waits for nothing.  A full segment corrects in place.
+__device__ __forceinline__ void guard_push(const Lds& L, const FwdArgs& a, uint64_t m, int p, int j, int kf,
+                                           uint32_t inc, int hb, int Tl, int wave, int qw, int& qn)
 {
-    const uint32_t slot = __hip_atomic_fetch_add(L.qcount, 1u, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (slot < (uint32_t)a.q_cap) {
-        L.qidx[slot] = ((uint32_t)p << 8) | (uint32_t)j;
-        L.qinc[slot] = inc;
-    } else {
-        guard_overflow(L.hist + (size_t)j * a.stride, a.patches, p, L.wlx[j], L.wly[j], L.wdx[j], L.wdy[j],
+    if (m == 0ull) return;
+    const bool want = (m >> (threadIdx.x & 63)) & 1ull;
+    const int n = __popcll(m);
+    if (qn + n <= qw) {
+        if (want) {
+            const int r = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            L.q[wave * qw + qn + r] = make_uint2(((uint32_t)p << 8) | (uint32_t)j, inc);
+        }
+        qn += n;
+    } else if (want) {
+        guard_overflow(L.hist + (size_t)j * a.stride, a.patches, p, kf, L.wlx[j], L.wly[j], L.wdx[j], L.wdy[j],
                        L.so[j], a.inv, hb, Tl, inc);
     }
 }
 
-// Drain the guard queue: exact fp64 bin for every queued pair.
-__device__ __forceinline__ void guard_drain(const Lds& L, const FwdArgs& a, int hb, int Tl)
+// fp32 arrival (in bins, + delta) of record (A, B) at slot j, by the same
+// operations as the pair loop.
+template <bool CONF>
+__device__ __forceinline__ float fast_arrival(const FwdArgs& a, const Lds& L, float4 A, float4 B, int j)
 {
-    const uint32_t nq = min(*L.qcount, (uint32_t)a.q_cap);
-    for (uint32_t i = threadIdx.x; i < nq; i += blockDim.x) {
-        const uint32_t e = L.qidx[i];
-        const int p = (int)(e >> 8), j = (int)(e & 255u);
+    const PatchC pc = patch_consts(A, B, a.cosines != 0);
+    float cx2, axv, cy2, byv;
+    col_terms(pc, L.wdx[j], &cx2, &axv);
+    row_terms(pc, L.wdy[j], &cy2, &byv);
+    const Leg ld = leg_eval(cx2, cy2, axv, byv, false);
+    if (CONF) return fmaf(ld.rr, a.inv2_f, L.oil[j]);
+    col_terms(pc, L.wlx[j], &cx2, &axv);
+    row_terms(pc, L.wly[j], &cy2, &byv);
+    const Leg ll = leg_eval(cx2, cy2, axv, byv, false);
+    return fmaf(ll.rr, a.inv_f, L.oil[j]) + fmaf(ld.rr, a.inv_f, L.oid[j]);
+}
+
+// After the pair loop (segment fills published in L.qcount, barrier passed).
+template <bool CONF>
+__device__ __forceinline__ void guard_drain(const Lds& L, const FwdArgs& a, int hb, int Tl, int qw)
+{
+    for (int i = threadIdx.x; i < kQueueWaves * qw; i += blockDim.x) {
+        if (i % qw >= (int)L.qcount[i / qw]) continue;
+        const uint2 e = L.q[i];
+        const int p = (int)(e.x >> 8), j = (int)(e.x & 255u);
         const float4 A = load4(a.patches, 2 * (size_t)p);
-        const int kl = exact_bin(A.x, A.y, A.z, L.wlx[j], L.wly[j], L.wdx[j], L.wdy[j], L.so[j], a.inv) - hb;
-        if ((unsigned)kl < (unsigned)Tl) lds_add(L.hist + (size_t)j * a.stride + kl, L.qinc[i]);
+        const float4 B = load4(a.patches, 2 * (size_t)p + 1);
+        const int kf = decide(fast_arrival<CONF>(a, L, A, B, j), a.two_delta).k - hb;
+        const int ke = exact_bin(A.x, A.y, A.z, L.wlx[j], L.wly[j], L.wdx[j], L.wdy[j], L.so[j], a.inv) - hb;
+        guard_fix(L.hist + (size_t)j * a.stride, kf, ke, Tl, e.y);
     }
 }
 
 // Load patch p of [pb, pe) or, past the range, a stand-in patch whose arrival
 // lies at least 64 bins past the window (never binned, never queued, culled).
-__device__ __forceinline__ void load_patch(const FwdArgs& a, int p, int pe, float4* A, float4* B)
-{
-    *A = make_float4(a.dummy_x, 0.f, 1.f, 0.f);
-    *B = make_float4(0.f, 0.f, -1.f, 0.f);
-    if (p < pe) {
-        *A = load4(a.patches, 2 * (size_t)p);
-        *B = load4(a.patches, 2 * (size_t)p + 1);
-    }
-}
 
 // ---------------------------------------------------------------------------
 // Record summaries: one workgroup per kStatBlock consecutive records.
@@ -429,7 +464,7 @@ __device__ __forceinline__ void flush(const FwdArgs& a, const Lds& L, float s, i
     const int P = Tl + 2 * PAD;
     const float inv_s = 1.0f / s;
     float* F = reinterpret_cast<float*>(L.hist);
-    float* gp = reinterpret_cast<float*>(L.qidx);   // padded taps [2 RM + 1]
+    float* gp = reinterpret_cast<float*>(L.q);      // padded taps [2 RM + 1]
     const int sj = (int)blockDim.x / Tl, st = (int)blockDim.x % Tl;
     float v[kMaxPer];
     {
@@ -539,7 +574,6 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
     for (int k = 0; k < NU; ++k) uvalid[k] = unit[k] >= 0;
 
     for (int i = threadIdx.x; i < NS * a.stride; i += blockDim.x) L.hist[i] = 0ull;
-    if (threadIdx.x == 0) *L.qcount = 0u;
     if (threadIdx.x < NS) {
         const int j = threadIdx.x;
         const int k = j / NH, jl = j % NH;
@@ -642,10 +676,17 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
         cut_r2[k] = rc * rc * 1.00001f;
     }
 
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    const int qw = a.q_cap / kQueueWaves;
+    int qn = 0;
     for (int base = pb; base < pe; base += blockDim.x) {
+        // lanes past the range read the last record, moved to dummy_x: every
+        // arrival of that position lies past the window
         const int p = base + (int)threadIdx.x;
-        float4 A, B;
-        load_patch(a, p, pe, &A, &B);
+        const int pl = min(p, pe - 1);
+        float4 A = load4(a.patches, 2 * (size_t)pl);
+        const float4 B = load4(a.patches, 2 * (size_t)pl + 1);
+        if (p >= pe) A.x = a.dummy_x;
         const PatchC pc = patch_consts(A, B, COS);
 #pragma unroll
         for (int k = 0; k < NU; ++k) {
@@ -653,7 +694,6 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
             {
                 bool out;
                 if (CONF) {
-                    // 2 r inv + omin >= cut  <=>  r^2 >= ((cut - omin) / (2 inv))^2
                     out = rect_r2_min(pc.px, pc.py, pc.pz2, x0[k], x1[k], y0[k], y1[k]) >= cut_r2[k];
                 } else {
                     const float rd = __builtin_amdgcn_sqrtf(rect_r2_min(pc.px, pc.py, pc.pz2, x0[k], x1[k], y0[k], y1[k]));
@@ -687,11 +727,12 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
                         const Decision d = decide(w, two_delta);
                         const uint32_t inc = (uint32_t)fmaf(COS ? lg.q * lg.q : lg.ri4, aps, 0.5f);
                         const int kl = d.k - hb;
-                        if (d.sure) {
-                            if ((unsigned)kl < (unsigned)Tl) lds_add(L.hist + j * a.stride + kl, inc);
-                        } else if ((unsigned)kl <= (unsigned)Tl) {
-                            guard_push(L, a, p, j, inc, hb, Tl);
-                        }
+                        // bins 0 .. Tl exist (Tl: a spare past the window, never
+                        // flushed); lane masks are taken before the divergent add
+                        const uint64_t m_unsure = __builtin_amdgcn_ballot_w64((unsigned)kl <= (unsigned)Tl) &
+                                                  ~__builtin_amdgcn_ballot_w64(d.sure);
+                        if ((unsigned)kl <= (unsigned)Tl) lds_add(L.hist + j * a.stride + kl, inc);
+                        guard_push(L, a, m_unsure, p, j, kl, inc, hb, Tl, wave, qw, qn);
                     }
                 }
             } else {
@@ -725,19 +766,19 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
                             const Decision d = decide(w, two_delta);
                             const uint32_t inc = (uint32_t)fmaf(fl[l], fd, 0.5f);
                             const int kl = d.k - hb;
-                            if (d.sure) {
-                                if ((unsigned)kl < (unsigned)Tl) lds_add(L.hist + j * a.stride + kl, inc);
-                            } else if ((unsigned)kl <= (unsigned)Tl) {
-                                guard_push(L, a, p, j, inc, hb, Tl);
-                            }
+                            const uint64_t m_unsure = __builtin_amdgcn_ballot_w64((unsigned)kl <= (unsigned)Tl) &
+                                                      ~__builtin_amdgcn_ballot_w64(d.sure);
+                            if ((unsigned)kl <= (unsigned)Tl) lds_add(L.hist + j * a.stride + kl, inc);
+                            guard_push(L, a, m_unsure, p, j, kl, inc, hb, Tl, wave, qw, qn);
                         }
                     }
                 }
             }
         }
     }
+    if (lane == 0) L.qcount[wave] = (uint32_t)qn;
     __syncthreads();
-    guard_drain(L, a, hb, Tl);
+    guard_drain<CONF>(L, a, hb, Tl, qw);
     __syncthreads();
     flush<NS>(a, L, s, hb, Tl, t0w, t1w);
 }
