@@ -5,7 +5,10 @@
 Every source is compiled with hipcc for gfx950 only, with packed FP32 math
 disabled (-packed-fp32-ops) and no FMA contraction (the kernels write their
 fused multiply-adds explicitly, and the fp64 bin re-evaluation must follow
-its stated operation order).
+its stated operation order).  The compiler's wave-aggregation of atomics is
+off: every atomic here is already issued once per wavefront or per lane with
+its own address, and the rewrite would wait for a claimed work chunk at once
+instead of where its value is used.
 """
 from __future__ import annotations
 
@@ -22,7 +25,7 @@ SOURCES = ["nlos_geometry.hip", "nlos_forward.hip", "nlos_smooth.hip", "nlos_noi
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function",
+    "-munsafe-fp-atomics", "-mllvm", "-amdgpu-atomic-optimizer-strategy=None", "-Wall", "-Wno-unused-function",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 

@@ -54,7 +54,7 @@ size_t lds_bytes_for(int slots, int stride, int q_cap)
     b += (size_t)slots * 8;                            // fp64 path offset per slot
     b += (size_t)slots * 8;                            // output row per slot
     b += (size_t)slots * 4 * 8;                        // fp32 tables
-    b += kQueueWaves * 4 + 64 * 4;                     // queue fill per wave, reduction scratch
+    b += kQueueWaves * 4 + 64 * 4 + 16;                // queue fill per wave, reduction scratch, chunk counter
     return (b + 255) & ~(size_t)255;
 }
 
@@ -74,6 +74,7 @@ struct Lds {
     float* pad;
     uint32_t* qcount;   // [kQueueWaves] entries in each segment
     float* red;     // [64] per-wave reduction scratch
+    uint32_t* next; // next 64-record chunk of the pair loop
 };
 
 __device__ __forceinline__ Lds lds_layout(unsigned char* base, int slots, int stride, int q_cap)
@@ -93,6 +94,7 @@ __device__ __forceinline__ Lds lds_layout(unsigned char* base, int slots, int st
     L.pad = L.gg + slots;
     L.qcount = (uint32_t*)(L.pad + slots);
     L.red = (float*)(L.qcount + kQueueWaves);
+    L.next = (uint32_t*)(L.red + 64);
     return L;
 }
 
@@ -574,6 +576,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
     for (int k = 0; k < NU; ++k) uvalid[k] = unit[k] >= 0;
 
     for (int i = threadIdx.x; i < NS * a.stride; i += blockDim.x) L.hist[i] = 0ull;
+    if (threadIdx.x == 0) *L.next = 0u;
     if (threadIdx.x < NS) {
         const int j = threadIdx.x;
         const int k = j / NH, jl = j % NH;
@@ -679,13 +682,23 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
     const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
     const int qw = a.q_cap / kQueueWaves;
     int qn = 0;
-    for (int base = pb; base < pe; base += blockDim.x) {
+    // Wavefronts take 64-record chunks from a counter in LDS (the next one is
+    // claimed while the current one is evaluated), so they finish together
+    // however unevenly culling thins the chunks.
+    int chunk_id = 0;
+    if (lane == 0) chunk_id = (int)atomicAdd(L.next, 1u);
+    chunk_id = __builtin_amdgcn_readfirstlane(chunk_id);
+    for (;;) {
+        const int base = pb + chunk_id * 64;
+        if (base >= pe) break;
         // lanes past the range read the last record, moved to dummy_x: every
         // arrival of that position lies past the window
-        const int p = base + (int)threadIdx.x;
+        const int p = base + lane;
         const int pl = min(p, pe - 1);
         float4 A = load4(a.patches, 2 * (size_t)pl);
         const float4 B = load4(a.patches, 2 * (size_t)pl + 1);
+        int next_id = 0;
+        if (lane == 0) next_id = (int)atomicAdd(L.next, 1u);
         if (p >= pe) A.x = a.dummy_x;
         const PatchC pc = patch_consts(A, B, COS);
 #pragma unroll
@@ -775,6 +788,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
                 }
             }
         }
+        chunk_id = __builtin_amdgcn_readfirstlane(next_id);
     }
     if (lane == 0) L.qcount[wave] = (uint32_t)qn;
     __syncthreads();
