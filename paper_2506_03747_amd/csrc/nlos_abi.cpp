@@ -205,9 +205,9 @@ int make_plan(const nlos_params* p, int32_t n_patches, int R, int64_t target, nl
 
     // u64 bins per histogram row (at least tl + 1: bin tl is a spare that
     // takes the pairs just past the window), even, and reused by the flush as
-    // float rows padded with PAD = RM + 8 zeros on both sides (RM = R rounded
-    // up to 4, 8, 16), so 2 * stride >= tl + 2 PAD
-    const int RM = R <= 4 ? 4 : (R <= 8 ? 8 : (R <= 16 ? 16 : R));
+    // float rows padded with PAD = RM + 8 zeros on both sides (RM = the
+    // jitter radius rounded up to a compiled variant), so 2 * stride >= tl + 2 PAD
+    const int RM = nlos::jitter_rm(R);
     const int PAD = RM + 8;
     auto stride_of = [PAD](int tl) { return std::max((tl + 2) & ~1, ((tl + 2 * PAD + 1) / 2 + 1) & ~1); };
     auto units_of = [&](const Cand& c) {

@@ -410,10 +410,12 @@ __device__ __forceinline__ void pick_units(const FwdArgs& a, int grp, int* u)
 
 // Jitter of one row segment: each lane produces V consecutive outputs from a
 // register window of V + 2 RM values (V odd, so lanes read LDS words V apart
-// without bank conflicts); taps zero-padded to radius RM.
+// without bank conflicts); taps zero-padded to radius RM.  With a staging
+// area (64 V floats per wavefront, LDS), the segment's outputs are transposed
+// there so that every store instruction writes 64 consecutive floats.
 template <int RM>
 __device__ __forceinline__ void jitter_rows(const FwdArgs& a, const Lds& L, const float* F, const float* gp, int NS,
-                                            int P, int PAD, int hb, int t0w, int t1w)
+                                            int P, int PAD, int hb, int t0w, int t1w, float* stg)
 {
     constexpr int V = 5;
     constexpr int K = 2 * RM + 1;
@@ -424,75 +426,147 @@ __device__ __forceinline__ void jitter_rows(const FwdArgs& a, const Lds& L, cons
     const int nt = t1w - t0w;
     const int seg = 64 * V;
     const int nseg = (nt + seg - 1) / seg;
+    float* ws = stg ? stg + wave * seg : nullptr;
     for (int sj = wave; sj < NS * nseg; sj += n_waves) {
         const int j = sj / nseg, sidx = sj - j * nseg;
         const long long row = L.row[j];
         if (row < 0) continue;
-        const int t0 = t0w + sidx * seg + lane * V;
-        if (t0 >= t1w) continue;
-        // H[x] = F[j P + PAD + x - hb]; window w[q] = H[t0 - RM + q]
-        const float* h = F + (size_t)j * P + PAD + (t0 - hb) - RM;
+        const int ts = t0w + sidx * seg;                  // first output of the segment
+        const int t0 = ts + lane * V;
+        // H[x] = F[j P + PAD + x - hb]; window w[q] = H[t0 - RM + q] (lanes past
+        // the end read the window of t1w - 1, inside the padded row; their
+        // outputs are dropped)
+        const float* h = F + (size_t)j * P + PAD + ((t0 < t1w ? t0 : t1w - 1) - hb) - RM;
         float w[V + 2 * RM];
 #pragma unroll
         for (int q = 0; q < V + 2 * RM; ++q) w[q] = h[q];
         const float gg = L.gg[j];
-        __attribute__((address_space(1))) float* out = gmem(a.out) + (size_t)row * (size_t)a.T + t0;
+        float acc[V];
 #pragma unroll
         for (int m = 0; m < V; ++m) {
             // out[t0 + m] = sum_k gp[k] H[t0 + m + RM - k]
-            float acc = 0.f;
+            float s = 0.f;
 #pragma unroll
-            for (int k = 0; k < K; ++k) acc = fmaf(g[k], w[m + 2 * RM - k], acc);
-            if (t0 + m < t1w) {
-                if (a.atomic_out)
-                    unsafeAtomicAdd((float*)(out + m), acc * gg);
-                else
-                    out[m] = acc * gg;
+            for (int k = 0; k < K; ++k) s = fmaf(g[k], w[m + 2 * RM - k], s);
+            acc[m] = s * gg;
+        }
+        __attribute__((address_space(1))) float* orow = gmem(a.out) + (size_t)row * (size_t)a.T;
+        if (ws) {
+#pragma unroll
+            for (int m = 0; m < V; ++m) ws[lane * V + m] = acc[m];
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int m = 0; m < V; ++m) {
+                const int t = ts + m * 64 + lane;
+                const float v = ws[m * 64 + lane];
+                if (t < t1w) {
+                    if (a.atomic_out)
+                        unsafeAtomicAdd((float*)(orow + t), v);
+                    else
+                        orow[t] = v;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        } else {
+#pragma unroll
+            for (int m = 0; m < V; ++m) {
+                if (t0 + m < t1w) {
+                    if (a.atomic_out)
+                        unsafeAtomicAdd((float*)(orow + t0 + m), acc[m]);
+                    else
+                        orow[t0 + m] = acc[m];
+                }
             }
         }
     }
 }
 
+// A 64-bit fixed-point sum (low, high words) as fp32: exact enough, since the
+// sum is < 2^56 and only fp32 precision is kept.  The empty asm keeps each
+// word a 32-bit operand (otherwise the conversion is widened to a 64-bit one).
+__device__ __forceinline__ float u64_to_float(uint2 x)
+{
+    uint32_t hi = x.y, lo = x.x;
+    asm("" : "+v"(hi), "+v"(lo));
+    return fmaf((float)hi, 4294967296.0f, (float)lo);
+}
+
 // Flush: histograms (fixed point in LDS) -> float rows (zero-padded by PAD on
 // both sides, in place) -> Gaussian jitter -> output.  Values are moved
-// through registers (at most 160 KB / 8 bytes / 1024 threads = 20 per thread).
+// through registers (at most 160 KB / 8 bytes / 1024 threads = 20 per
+// thread), read in batches of 8 with no wait in between.
 template <int NS>
 __device__ __forceinline__ void flush(const FwdArgs& a, const Lds& L, float s, int hb, int Tl, int t0w, int t1w)
 {
     constexpr int kMaxPer = 24;
+    constexpr int kBatch = 8;
     const int R = a.R;
-    const int RM = R <= 4 ? 4 : (R <= 8 ? 8 : (R <= 16 ? 16 : R));
+    const int RM = jitter_rm(R);
     const int PAD = RM + 8;
     const int P = Tl + 2 * PAD;
     const float inv_s = 1.0f / s;
     float* F = reinterpret_cast<float*>(L.hist);
+    const uint2* H2 = reinterpret_cast<const uint2*>(L.hist);
     float* gp = reinterpret_cast<float*>(L.q);      // padded taps [2 RM + 1]
+    const int per = (NS * Tl + (int)blockDim.x - 1) / (int)blockDim.x;   // values per thread, uniform
     const int sj = (int)blockDim.x / Tl, st = (int)blockDim.x % Tl;
+    const int j0 = (int)threadIdx.x / Tl, t0 = (int)threadIdx.x % Tl;
+    // value k of this thread: flat index threadIdx.x + k blockDim.x = (row j, bin t)
     float v[kMaxPer];
-    {
-        int j = (int)threadIdx.x / Tl, t = (int)threadIdx.x % Tl;
+    if (st == 0) {
+        // Tl divides the workgroup: t fixed, j = j0 + k sj; rows past the last
+        // read the last row again (in bounds, never written back)
+        const int last = (NS - 1) * a.stride + t0, step = sj * a.stride;
+        int idx = j0 * a.stride + t0;
 #pragma unroll
-        for (int k = 0; k < kMaxPer; ++k) {
-            if (j < NS) {
-                // exact enough: the sum is < 2^56 and only fp32 precision is kept
-                const u64 x = L.hist[(size_t)j * a.stride + t];
-                const float hi = (float)(uint32_t)(x >> 32), lo = (float)(uint32_t)x;
-                v[k] = fmaf(hi, 4294967296.0f, lo) * inv_s;
+        for (int k0 = 0; k0 < kMaxPer; k0 += kBatch) {
+            if (k0 >= per) break;
+            uint2 x[kBatch];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                x[k] = H2[min(idx, last)];
+                idx += step;
             }
-            j += sj;
-            t += st;
-            if (t >= Tl) {
-                t -= Tl;
-                ++j;
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) v[k0 + k] = u64_to_float(x[k]) * inv_s;
+        }
+    } else {
+        int j = j0, t = t0;
+#pragma unroll
+        for (int k0 = 0; k0 < kMaxPer; k0 += kBatch) {
+            if (k0 >= per) break;
+            uint2 x[kBatch];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                x[k] = H2[__umul24((unsigned)min(j, NS - 1), (unsigned)a.stride) + t];
+                j += sj;
+                t += st;
+                if (t >= Tl) {
+                    t -= Tl;
+                    ++j;
+                }
             }
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) v[k0 + k] = u64_to_float(x[k]) * inv_s;
         }
     }
     __syncthreads();
-    {
-        int j = (int)threadIdx.x / Tl, t = (int)threadIdx.x % Tl;
+    if (st == 0) {
+        const int nv = j0 < NS ? (NS - j0 + sj - 1) / sj : 0;   // values of this thread in the rows
+        const int fstep = sj * P;
+        int fidx = j0 * P + PAD + t0;
 #pragma unroll
         for (int k = 0; k < kMaxPer; ++k) {
-            if (j < NS) F[(size_t)j * P + PAD + t] = v[k];
+            if (k >= per) break;
+            if (k < nv) F[fidx] = v[k];
+            fidx += fstep;
+        }
+    } else {
+        int j = j0, t = t0;
+#pragma unroll
+        for (int k = 0; k < kMaxPer; ++k) {
+            if (k >= per) break;
+            if (j < NS) F[__umul24((unsigned)j, (unsigned)P) + PAD + t] = v[k];
             j += sj;
             t += st;
             if (t >= Tl) {
@@ -510,12 +584,22 @@ __device__ __forceinline__ void flush(const FwdArgs& a, const Lds& L, float s, i
         gp[k] = (i >= 0 && i <= 2 * R) ? a.taps[i] : 0.f;
     }
     __syncthreads();
-    if (RM == 4) {
-        jitter_rows<4>(a, L, F, gp, NS, P, PAD, hb, t0w, t1w);
+    // staging for coalesced stores: the part of the histogram rows the float
+    // rows leave free, when it holds 64 V floats per wavefront
+    const int free_f = NS * (2 * a.stride - P);
+    float* stg = free_f >= (int)blockDim.x * 5 ? F + NS * P : nullptr;
+    if (RM == 2) {
+        jitter_rows<2>(a, L, F, gp, NS, P, PAD, hb, t0w, t1w, stg);
+    } else if (RM == 4) {
+        jitter_rows<4>(a, L, F, gp, NS, P, PAD, hb, t0w, t1w, stg);
+    } else if (RM == 6) {
+        jitter_rows<6>(a, L, F, gp, NS, P, PAD, hb, t0w, t1w, stg);
     } else if (RM == 8) {
-        jitter_rows<8>(a, L, F, gp, NS, P, PAD, hb, t0w, t1w);
+        jitter_rows<8>(a, L, F, gp, NS, P, PAD, hb, t0w, t1w, stg);
+    } else if (RM == 12) {
+        jitter_rows<12>(a, L, F, gp, NS, P, PAD, hb, t0w, t1w, stg);
     } else if (RM == 16) {
-        jitter_rows<16>(a, L, F, gp, NS, P, PAD, hb, t0w, t1w);
+        jitter_rows<16>(a, L, F, gp, NS, P, PAD, hb, t0w, t1w, stg);
     } else {
         // wide kernels: one output per lane, generic tap loop
         const int nt = t1w - t0w;

@@ -11,6 +11,13 @@ namespace nlos {
 
 constexpr int kMaxRadius = 127;
 constexpr int kMaxTaps = 2 * kMaxRadius + 1;
+
+// Radius the jitter taps are zero-padded to in the pair kernels' flush (one
+// compiled variant per value); the host sizes the histogram rows from it.
+__host__ __device__ inline int jitter_rm(int R)
+{
+    return R <= 2 ? 2 : (R <= 4 ? 4 : (R <= 6 ? 6 : (R <= 8 ? 8 : (R <= 12 ? 12 : (R <= 16 ? 16 : R)))));
+}
 constexpr int kBlock = 1024;           // threads per workgroup of the pair kernels
 constexpr int kBlockPx = 16;           // record order: 16x16-pixel blocks, 4 stride-2 phases
 
