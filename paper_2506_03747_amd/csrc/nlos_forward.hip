@@ -54,7 +54,7 @@ size_t lds_bytes_for(int slots, int stride, int q_cap)
     b += (size_t)slots * 8;                            // fp64 path offset per slot
     b += (size_t)slots * 8;                            // output row per slot
     b += (size_t)slots * 4 * 8;                        // fp32 tables
-    b += kQueueWaves * 4 + 64 * 4 + 16;                // queue fill per wave, reduction scratch, chunk counter
+    b += 64 * 4 + 16;                                  // reduction scratch, chunk counter
     return (b + 255) & ~(size_t)255;
 }
 
@@ -72,7 +72,6 @@ struct Lds {
     float* oid;     // [slots] fp32(o_d * inv)           (confocal: unused)
     float* gg;      // [slots] g_l * g_d
     float* pad;
-    uint32_t* qcount;   // [kQueueWaves] entries in each segment
     float* red;     // [64] per-wave reduction scratch
     uint32_t* next; // next 64-record chunk of the pair loop
 };
@@ -92,8 +91,7 @@ __device__ __forceinline__ Lds lds_layout(unsigned char* base, int slots, int st
     L.oid = L.oil + slots;
     L.gg = L.oid + slots;
     L.pad = L.gg + slots;
-    L.qcount = (uint32_t*)(L.pad + slots);
-    L.red = (float*)(L.qcount + kQueueWaves);
+    L.red = L.pad + slots;
     L.next = (uint32_t*)(L.red + 64);
     return L;
 }
@@ -242,19 +240,19 @@ __device__ __forceinline__ float fast_arrival(const FwdArgs& a, const Lds& L, fl
     return fmaf(ll.rr, a.inv_f, L.oil[j]) + fmaf(ld.rr, a.inv_f, L.oid[j]);
 }
 
-// After the pair loop (segment fills published in L.qcount, barrier passed).
+// After the wavefront's pair loop: its own segment (qn entries), one entry
+// per lane; other wavefronts may still be adding (all adds commute).
 template <bool CONF>
-__device__ __forceinline__ void guard_drain(const Lds& L, const FwdArgs& a, int hb, int Tl, int qw)
+__device__ __forceinline__ void guard_drain(const Lds& L, const FwdArgs& a, int hb, int Tl, int wave, int qw, int qn)
 {
-    for (int i = threadIdx.x; i < kQueueWaves * qw; i += blockDim.x) {
-        if (i % qw >= (int)L.qcount[i / qw]) continue;
-        const uint2 e = L.q[i];
-        const int p = (int)(e.x >> 8), j = (int)(e.x & 255u);
+    for (int e = (int)threadIdx.x & 63; e < qn; e += 64) {
+        const uint2 q = L.q[wave * qw + e];
+        const int p = (int)(q.x >> 8), j = (int)(q.x & 255u);
         const float4 A = load4(a.patches, 2 * (size_t)p);
         const float4 B = load4(a.patches, 2 * (size_t)p + 1);
         const int kf = decide(fast_arrival<CONF>(a, L, A, B, j), a.two_delta).k - hb;
         const int ke = exact_bin(A.x, A.y, A.z, L.wlx[j], L.wly[j], L.wdx[j], L.wdy[j], L.so[j], a.inv) - hb;
-        guard_fix(L.hist + (size_t)j * a.stride, kf, ke, Tl, e.y);
+        guard_fix(L.hist + (size_t)j * a.stride, kf, ke, Tl, q.y);
     }
 }
 
@@ -496,7 +494,8 @@ __device__ __forceinline__ float u64_to_float(uint2 x)
 // through registers (at most 160 KB / 8 bytes / 1024 threads = 20 per
 // thread), read in batches of 8 with no wait in between.
 template <int NS>
-__device__ __forceinline__ void flush(const FwdArgs& a, const Lds& L, float s, int hb, int Tl, int t0w, int t1w)
+__device__ __forceinline__ void flush(const FwdArgs& a, const Lds& L, float s, int hb, int Tl, int t0w, int t1w,
+                                      float tap)
 {
     constexpr int kMaxPer = 24;
     constexpr int kBatch = 8;
@@ -579,10 +578,7 @@ __device__ __forceinline__ void flush(const FwdArgs& a, const Lds& L, float s, i
         const int j = i / (2 * PAD), e = i - j * 2 * PAD;
         F[(size_t)j * P + (e < PAD ? e : Tl + e)] = 0.f;
     }
-    for (int k = threadIdx.x; k < 2 * RM + 1; k += blockDim.x) {
-        const int i = k - (RM - R);
-        gp[k] = (i >= 0 && i <= 2 * R) ? a.taps[i] : 0.f;
-    }
+    if ((int)threadIdx.x < 2 * RM + 1) gp[threadIdx.x] = tap;
     __syncthreads();
     // staging for coalesced stores: the part of the histogram rows the float
     // rows leave free, when it holds 64 V floats per wavefront
@@ -659,8 +655,14 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
 #pragma unroll
     for (int k = 0; k < NU; ++k) uvalid[k] = unit[k] >= 0;
 
-    for (int i = threadIdx.x; i < NS * a.stride; i += blockDim.x) L.hist[i] = 0ull;
+    for (int i = threadIdx.x; i < NS * a.stride / 2; i += blockDim.x) reinterpret_cast<uint4*>(L.hist)[i] = uint4{0, 0, 0, 0};
     if (threadIdx.x == 0) *L.next = 0u;
+    // the flush's jitter tap of this thread (taps zero-padded to radius RM)
+    float tap = 0.f;
+    {
+        const int RM = jitter_rm(a.R), i = (int)threadIdx.x - (RM - a.R);
+        if ((int)threadIdx.x < 2 * RM + 1 && i >= 0 && i <= 2 * a.R) tap = a.taps[i];
+    }
     if (threadIdx.x < NS) {
         const int j = threadIdx.x;
         const int k = j / NH, jl = j % NH;
@@ -874,11 +876,9 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
         }
         chunk_id = __builtin_amdgcn_readfirstlane(next_id);
     }
-    if (lane == 0) L.qcount[wave] = (uint32_t)qn;
+    guard_drain<CONF>(L, a, hb, Tl, wave, qw, qn);
     __syncthreads();
-    guard_drain<CONF>(L, a, hb, Tl, qw);
-    __syncthreads();
-    flush<NS>(a, L, s, hb, Tl, t0w, t1w);
+    flush<NS>(a, L, s, hb, Tl, t0w, t1w, tap);
 }
 
 template <bool CONF, int TL, int TX, int TY, bool COS, bool WIN, bool PAIR>
