@@ -357,10 +357,9 @@ __device__ __forceinline__ UnitRect unit_rect(const FwdArgs& a, int u)
 // Upper bound of every pair weight of unit u: a_max / (r_l,min^2 r_d,min^2)
 // over the record summaries (cosine factors are at most 1).
 template <bool CONF, int TL, int TX, int TY>
-__device__ float unit_weight_bound(const FwdArgs& a, int u, int i)
+__device__ float unit_weight_bound(const FwdArgs& a, int u, const StatF& c)
 {
     const UnitRect R = unit_rect<CONF, TL, TX, TY>(a, u);
-    const StatF c = load_stat(a.stats, i);
     if (c.count <= 0) return 0.f;
     const float z2 = c.z0 * c.z0;
     const float rd2 = rect_rect_d2(R.dx0, R.dx1, R.dy0, R.dy1, c.x0, c.x1, c.y0, c.y1) + z2;
@@ -635,7 +634,12 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
     constexpr int NS = NU * NH;
     extern __shared__ __align__(16) unsigned char smem[];
     const Lds L = lds_layout(smem, NS, a.stride, a.q_cap);
+    // the global reads of the set-up first, so that their latency overlaps the
+    // LDS clear and the tables below
     const int n_act = active_count(a);
+    StatF st0;
+    st0.count = 0;
+    if ((int)threadIdx.x < a.n_stats) st0 = load_stat(a.stats, threadIdx.x);
 
     int id = block_id;
     const int split = id % a.n_split;
@@ -703,9 +707,10 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
     // weight bound over the record summaries -> fixed-point scale
     float wb = 0.f;
     for (int i = threadIdx.x; i < a.n_stats; i += blockDim.x) {
+        const StatF c = i == (int)threadIdx.x ? st0 : load_stat(a.stats, i);
 #pragma unroll
         for (int k = 0; k < NU; ++k)
-            if (uvalid[k]) wb = fmaxf(wb, unit_weight_bound<CONF, TL, TX, TY>(a, unit[k], i));
+            if (uvalid[k]) wb = fmaxf(wb, unit_weight_bound<CONF, TL, TX, TY>(a, unit[k], c));
     }
     const float W = block_max(wb, L.red);   // includes a barrier: the tables above are visible
     const float s = W > 0.f ? 2147483648.0f / W : 1.0f;
