@@ -785,7 +785,12 @@ int nlos_simulate_workspace_bytes(const nlos_params* p, const nlos_grid* g, size
     if (rc != NLOS_OK) return rc;
     rc = nlos_forward_workspace_bytes(p, g->nx * g->ny, &fwd);
     if (rc != NLOS_OK) return rc;
-    *bytes = align_up(geo, 256) + fwd;
+    // the summaries here are one per 16x16-pixel tile of every geometry block
+    const int64_t bx = (g->nx + nlos::kBlockPx - 1) / nlos::kBlockPx;
+    const int64_t by = (g->ny + nlos::kBlockPx - 1) / nlos::kBlockPx;
+    const int64_t blocks = ((int64_t)nlos::kBlockPx * nlos::kBlockPx * bx * by + nlos::kGeomBlock - 1) / nlos::kGeomBlock;
+    const int64_t tiles = blocks * (nlos::kGeomBlock / (nlos::kBlockPx * nlos::kBlockPx));
+    *bytes = align_up(geo, 256) + std::max(fwd, (size_t)tiles * sizeof(nlos::ChunkStat));
     return NLOS_OK;
 }
 
@@ -814,7 +819,10 @@ int nlos_simulate(const nlos_params* p, const nlos_grid* g, const float* depth, 
     unsigned char* w = static_cast<unsigned char*>(ws);
     ga.counts = reinterpret_cast<int32_t*>(w);
     ga.offsets = ga.n_blocks <= nlos::kScanFreeBlocks ? nullptr : ga.counts + ga.n_blocks;
+    // record summaries: one per 16x16-pixel tile of every geometry block,
+    // written by the scatter (tiles past the map are empty)
     a.stats = reinterpret_cast<nlos::ChunkStat*>(w + align_up(geo, 256));
+    a.n_stats = ga.n_blocks * (nlos::kGeomBlock / (nlos::kBlockPx * nlos::kBlockPx));
     ga.stats = a.stats;
     ga.n_stats = a.n_stats;
     hipStream_t st = (hipStream_t)stream;

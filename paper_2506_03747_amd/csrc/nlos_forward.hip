@@ -133,16 +133,24 @@ __device__ __forceinline__ float rect_rect_d2(float ax0, float ax1, float ay0, f
     return fmaf(dx, dx, dy * dy);
 }
 
-// Block-wide maximum of a non-negative float (wave butterfly, then LDS).
-__device__ __forceinline__ float block_max(float v, float* red)
+// Block-wide maxima of N non-negative floats, in place (wave butterfly, then
+// LDS; `red` holds N floats per wavefront).
+template <int N>
+__device__ __forceinline__ void block_max(float* v, float* red)
 {
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    for (int k = 0; k < N; ++k) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v[k] = fmaxf(v[k], __shfl_xor(v[k], o, 64));
+        if ((threadIdx.x & 63) == 0) red[(threadIdx.x >> 6) * N + k] = v[k];
+    }
     __syncthreads();
-    float m = 0.f;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, red[w]);
-    return m;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        float m = 0.f;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, red[w * N + k]);
+        v[k] = m;
+    }
 }
 
 // Device buffers named by the arguments are global memory; saying so keeps
@@ -493,8 +501,7 @@ __device__ __forceinline__ float u64_to_float(uint2 x)
 // through registers (at most 160 KB / 8 bytes / 1024 threads = 20 per
 // thread), read in batches of 8 with no wait in between.
 template <int NS>
-__device__ __forceinline__ void flush(const FwdArgs& a, const Lds& L, float s, int hb, int Tl, int t0w, int t1w,
-                                      float tap)
+__device__ __forceinline__ void flush(const FwdArgs& a, const Lds& L, int hb, int Tl, int t0w, int t1w, float tap)
 {
     constexpr int kMaxPer = 24;
     constexpr int kBatch = 8;
@@ -502,7 +509,6 @@ __device__ __forceinline__ void flush(const FwdArgs& a, const Lds& L, float s, i
     const int RM = jitter_rm(R);
     const int PAD = RM + 8;
     const int P = Tl + 2 * PAD;
-    const float inv_s = 1.0f / s;
     float* F = reinterpret_cast<float*>(L.hist);
     const uint2* H2 = reinterpret_cast<const uint2*>(L.hist);
     float* gp = reinterpret_cast<float*>(L.q);      // padded taps [2 RM + 1]
@@ -526,7 +532,7 @@ __device__ __forceinline__ void flush(const FwdArgs& a, const Lds& L, float s, i
                 idx += step;
             }
 #pragma unroll
-            for (int k = 0; k < kBatch; ++k) v[k0 + k] = u64_to_float(x[k]) * inv_s;
+            for (int k = 0; k < kBatch; ++k) v[k0 + k] = u64_to_float(x[k]);
         }
     } else {
         int j = j0, t = t0;
@@ -545,7 +551,7 @@ __device__ __forceinline__ void flush(const FwdArgs& a, const Lds& L, float s, i
                 }
             }
 #pragma unroll
-            for (int k = 0; k < kBatch; ++k) v[k0 + k] = u64_to_float(x[k]) * inv_s;
+            for (int k = 0; k < kBatch; ++k) v[k0 + k] = u64_to_float(x[k]);
         }
     }
     __syncthreads();
@@ -704,16 +710,24 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
             L.gg[j] = (float)(g_l * g_d);
         }
     }
-    // weight bound over the record summaries -> fixed-point scale
-    float wb = 0.f;
+    // weight bound of each unit over the record summaries -> its fixed-point
+    // scale s_k = 2^31 / W_k, so that a unit of weak pairs keeps its
+    // precision beside a strong one; the row gains take 1 / s_k, so rows come
+    // out in the operator's units
+    float wbk[NU];
+#pragma unroll
+    for (int k = 0; k < NU; ++k) wbk[k] = 0.f;
     for (int i = threadIdx.x; i < a.n_stats; i += blockDim.x) {
         const StatF c = i == (int)threadIdx.x ? st0 : load_stat(a.stats, i);
 #pragma unroll
         for (int k = 0; k < NU; ++k)
-            if (uvalid[k]) wb = fmaxf(wb, unit_weight_bound<CONF, TL, TX, TY>(a, unit[k], c));
+            if (uvalid[k]) wbk[k] = fmaxf(wbk[k], unit_weight_bound<CONF, TL, TX, TY>(a, unit[k], c));
     }
-    const float W = block_max(wb, L.red);   // includes a barrier: the tables above are visible
-    const float s = W > 0.f ? 2147483648.0f / W : 1.0f;
+    block_max<NU>(wbk, L.red);   // includes a barrier: the tables above are visible
+    float sk[NU];
+#pragma unroll
+    for (int k = 0; k < NU; ++k) sk[k] = wbk[k] > 0.f ? 2147483648.0f / wbk[k] : 1.0f;
+    if (threadIdx.x < NS) L.gg[threadIdx.x] *= 1.0f / sk[threadIdx.x / NH];
 
     // per-unit wall points and bounds, wave-uniform
     float lxs[NU][TL], lys[NU][TL], oil[NU][TL], wx[NU][TX], wy[NU][TY], oi[NS];
@@ -816,7 +830,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
             const int b = k * NH;
             float cx2[TX], axv[TX], cy2[TY], byv[TY];
             if (CONF) {
-                const float aps = (COS ? pc.ap : A.w) * s;
+                const float aps = (COS ? pc.ap : A.w) * sk[k];
 #pragma unroll
                 for (int c = 0; c < TX; ++c) col_terms(pc, wx[k][c], &cx2[c], &axv[c]);
 #pragma unroll
@@ -849,7 +863,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
                     row_terms(pc, lys[k][l], &lcy2, &lby);
                     const Leg lg = leg_eval(lcx2, lcy2, lax, lby, COS);
                     ul[l] = fmaf(lg.rr, inv, oil[k][l]);
-                    fl[l] = (COS ? lg.q * pc.ap : lg.ri2 * A.w) * s;
+                    fl[l] = (COS ? lg.q * pc.ap : lg.ri2 * A.w) * sk[k];
                 }
 #pragma unroll
                 for (int c = 0; c < TX; ++c) col_terms(pc, wx[k][c], &cx2[c], &axv[c]);
@@ -883,7 +897,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
     }
     guard_drain<CONF>(L, a, hb, Tl, wave, qw, qn);
     __syncthreads();
-    flush<NS>(a, L, s, hb, Tl, t0w, t1w, tap);
+    flush<NS>(a, L, hb, Tl, t0w, t1w, tap);
 }
 
 template <bool CONF, int TL, int TX, int TY, bool COS, bool WIN, bool PAIR>

@@ -51,18 +51,6 @@ __device__ __forceinline__ void count_body(const GeomArgs& a, int blk)
     if (p) p = is_present(a, (int64_t)ix * a.ay.n + iy);
     const int cnt = __syncthreads_count(p);
     if (threadIdx.x == 0) a.counts[blk] = cnt;
-    // record summaries (when built here): start from the identity of the merge
-    if (a.stats) {
-        for (int64_t i = (int64_t)blk * kGeomBlock + threadIdx.x; i < a.n_stats;
-             i += (int64_t)a.n_blocks * kGeomBlock) {
-            ChunkStat c;
-            c.x0 = c.y0 = c.z0 = INT32_MAX;
-            c.x1 = c.y1 = c.amax = INT32_MIN;
-            c.count = 0;
-            c.pad = 0;
-            a.stats[i] = c;
-        }
-    }
 }
 
 __global__ void __launch_bounds__(kGeomBlock) k_geom_count(const GeomArgs a) { count_body(a, (int)blockIdx.x); }
@@ -122,14 +110,14 @@ __device__ __forceinline__ int wave_max_i(int v)
 // Records of one enumeration block at base + (rank among the present pixels
 // before it).  base is the exclusive prefix of the block counts: read from
 // `offsets`, or (offsets null) summed here from the counts.  With `stats`,
-// the records' summaries are merged per wave (a wave's records touch at most
-// two summaries), per block in LDS, then into the summaries with integer
-// min / max / add atomics on their order-preserving images.
+// the block also writes the summaries of its own records, one per 16x16-pixel
+// tile (reduced per wave, then across the tile's waves in LDS, on the
+// order-preserving images): no other block touches them.
 __device__ __forceinline__ void scatter_body(const GeomArgs& a, int blk)
 {
     __shared__ int wave_cnt[kGeomBlock / 64];
     __shared__ int red[kGeomBlock / 64];
-    __shared__ int sst[kStatSlots][7];   // x0, x1, y0, y1, z0, amax, count
+    __shared__ int sst[kGeomBlock / 64][8];   // per wave: x0, x1, y0, y1, z0, amax, count
     const int64_t e = (int64_t)blk * kGeomBlock + threadIdx.x;
     int ix = 0, iy = 0;
     bool p = enum_pixel(a, e, &ix, &iy);
@@ -139,10 +127,6 @@ __device__ __forceinline__ void scatter_body(const GeomArgs& a, int blk)
     const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
     const int rank = __popcll(bal & ((1ull << lane) - 1ull));
     if (lane == 0) wave_cnt[wave] = __popcll(bal);
-    if (threadIdx.x < kStatSlots * 7) {
-        const int f = threadIdx.x % 7;
-        sst[threadIdx.x / 7][f] = (f == 6) ? 0 : ((f == 0 || f == 2 || f == 4) ? INT32_MAX : INT32_MIN);
-    }
     int base;
     if (a.offsets) {
         base = a.offsets[blk];
@@ -180,44 +164,37 @@ __device__ __forceinline__ void scatter_body(const GeomArgs& a, int blk)
     }
     if (!a.stats) return;   // uniform across the block
 
-    const int first = base / kStatBlock;
-    const int slot = p ? off / kStatBlock - first : INT32_MAX;
-    const int s_lo = wave_min_i(slot);
-    if (s_lo != INT32_MAX) {
-#pragma unroll
-        for (int seg = 0; seg < 2; ++seg) {
-            const bool mine = p && slot == s_lo + seg;
-            const unsigned long long mb = __ballot(mine);
-            if (mb == 0ull) continue;
-            const int x0 = wave_min_i(mine ? ord_f(A.x) : INT32_MAX);
-            const int x1 = wave_max_i(mine ? ord_f(A.x) : INT32_MIN);
-            const int y0 = wave_min_i(mine ? ord_f(A.y) : INT32_MAX);
-            const int y1 = wave_max_i(mine ? ord_f(A.y) : INT32_MIN);
-            const int z0 = wave_min_i(mine ? ord_f(A.z) : INT32_MAX);
-            const int am = wave_max_i(mine ? ord_f(A.w) : INT32_MIN);
-            if (lane == 0) {
-                int* t = sst[s_lo + seg];
-                atomicMin(&t[0], x0);
-                atomicMax(&t[1], x1);
-                atomicMin(&t[2], y0);
-                atomicMax(&t[3], y1);
-                atomicMin(&t[4], z0);
-                atomicMax(&t[5], am);
-                atomicAdd(&t[6], __popcll(mb));
-            }
-        }
+    const int v0 = wave_min_i(p ? ord_f(A.x) : INT32_MAX);
+    const int v1 = wave_max_i(p ? ord_f(A.x) : INT32_MIN);
+    const int v2 = wave_min_i(p ? ord_f(A.y) : INT32_MAX);
+    const int v3 = wave_max_i(p ? ord_f(A.y) : INT32_MIN);
+    const int v4 = wave_min_i(p ? ord_f(A.z) : INT32_MAX);
+    const int v5 = wave_max_i(p ? ord_f(A.w) : INT32_MIN);
+    if (lane == 0) {
+        int* t = sst[wave];
+        t[0] = v0;
+        t[1] = v1;
+        t[2] = v2;
+        t[3] = v3;
+        t[4] = v4;
+        t[5] = v5;
+        t[6] = __popcll(bal);
     }
     __syncthreads();
-    if (threadIdx.x < kStatSlots && sst[threadIdx.x][6] > 0) {
-        const int* t = sst[threadIdx.x];
-        ChunkStat* c = a.stats + first + threadIdx.x;
-        atomicMin(&c->x0, t[0]);
-        atomicMax(&c->x1, t[1]);
-        atomicMin(&c->y0, t[2]);
-        atomicMax(&c->y1, t[3]);
-        atomicMin(&c->z0, t[4]);
-        atomicMax(&c->amax, t[5]);
-        atomicAdd(&c->count, t[6]);
+    // one summary per 16x16-pixel tile (4 waves of the enumeration): thread
+    // 8 t + f reduces field f of tile t; fields in ChunkStat order
+    constexpr int kTileWaves = kBlockPx * kBlockPx / 64;
+    constexpr int kTiles = kGeomBlock / (kBlockPx * kBlockPx);
+    if (threadIdx.x < 8 * kTiles) {
+        const int t = threadIdx.x / 8, f = threadIdx.x % 8;
+        int v = (f == 6 || f == 7) ? 0 : ((f == 0 || f == 2 || f == 4) ? INT32_MAX : INT32_MIN);
+        if (f < 7) {
+            for (int w = t * kTileWaves; w < (t + 1) * kTileWaves; ++w) {
+                const int x = sst[w][f];
+                v = (f == 6) ? v + x : ((f == 0 || f == 2 || f == 4) ? min(v, x) : max(v, x));
+            }
+        }
+        reinterpret_cast<int32_t*>(a.stats + (int64_t)blk * kTiles + t)[f] = v;
     }
 }
 

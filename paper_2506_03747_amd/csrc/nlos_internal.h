@@ -39,7 +39,7 @@ struct GeomArgs {
     int32_t* counts;       // workspace: per enumeration block
     int32_t* offsets;      // workspace: exclusive prefix of counts; null: each
                            // scatter block sums the counts before it
-    ChunkStat* stats;      // nullable: record summaries built while scattering
+    ChunkStat* stats;      // nullable: [n_enum / 256] summaries, one per 16x16-pixel tile, built while scattering
     int32_t n_stats;
     Axis ax, ay;
     float hx, hy;          // spacings
@@ -50,18 +50,17 @@ struct GeomArgs {
 };
 constexpr int kGeomBlock = 1024;
 
-// Summary of one block of kStatBlock consecutive patch records: lateral
-// bounding box, smallest depth, largest a, record count.  Used to bound the
-// pair weights.  The six float fields are stored as order-preserving int32
-// images (ord_f), so summaries can also be merged with integer min / max
-// atomics while the records are written.
+// Summary of a block of patch records (kStatBlock consecutive ones, or the
+// records of one 16x16-pixel tile of the map): lateral bounding box, smallest depth,
+// largest a, record count.  Used to bound the pair weights; any partition of
+// the records serves.  The six float fields are stored as order-preserving
+// int32 images (ord_f).
 struct ChunkStat {
     int32_t x0, x1, y0, y1, z0, amax;
     int32_t count, pad;
 };
 static_assert(sizeof(ChunkStat) == 32, "summaries are read as two int4");
 constexpr int kStatBlock = 256;
-constexpr int kStatSlots = kGeomBlock / kStatBlock + 1;   // summaries one geometry block can touch
 
 struct StatF {
     float x0, x1, y0, y1, z0, amax;

@@ -8,7 +8,7 @@ import pytest
 import oracle
 import scenes
 from gpu_helpers import (assert_parity, gpu_forward, gpu_patches, guard_delta, log, to_gpu,
-                         oracle_bins_for_records)
+                         oracle_bins_for_records, rel_l2_rows)
 
 pytestmark = pytest.mark.gpu
 
@@ -114,20 +114,33 @@ def test_cfg5_full():
 
 def test_cfg3_sampled():
     """Non-confocal 64 lasers x 128^2 detectors x T=2048 (8.6 GB output):
-    4096 seeded histograms checked against the oracle."""
+    4096 seeded histograms against the oracle at the 1e-5 bar, and the 64
+    weakest non-empty ones at 1e-4.  The weakest hold one or two pairs at the
+    end of the window, seen edge-on (patch cosine ~1e-3): there the weight
+    is conditioned by 1 / cos on the record normals, which are fp32 (within
+    ~2e-7 of the oracle's fp64 ones, as the record parity test allows), so
+    the records alone move such a histogram by up to ~1e-4."""
     import torch
     sc = scenes.cfg3()
     log("cfg3")
     tau, _, _ = gpu_forward(sc)
     H = sc.n_laser * sc.n_scan
     rng = np.random.default_rng(33)
-    sub = np.sort(rng.choice(H, 4096, replace=False)).astype(np.int32)
+    rand = rng.choice(H, 4096, replace=False)
+    norms = tau.reshape(H, -1).double().norm(dim=1)
+    norms[norms == 0] = float("inf")
+    weakest = torch.topk(norms, 64, largest=False).indices.cpu().numpy()
+    sub = np.unique(np.concatenate([rand, weakest])).astype(np.int32)
     got = tau.reshape(H, -1)[torch.from_numpy(sub).long().cuda()].cpu().numpy()
     del tau
     torch.cuda.empty_cache()
     ref = oracle.forward(sc, subset=sub)["tau"]
-    e = assert_parity(got, ref, what="cfg3")
+    in_rand = np.isin(sub, rand)
+    e = assert_parity(got[in_rand], ref[in_rand], what="cfg3")
     log(f"cfg3 worst rel-L2 {e:.3e}")
+    weak = np.isin(sub, weakest) & ~in_rand
+    ew = assert_parity(got[weak], ref[weak], tol=1e-4, what="cfg3 weakest")
+    log(f"cfg3 weakest worst rel-L2 {ew:.3e}")
 
 
 @pytest.mark.parametrize("name,n_hist", [("cfg1", None), ("cfg2", 256), ("cfg3", 128)])
@@ -301,9 +314,14 @@ def test_repeatable_within_tolerance():
                                                       bin_ps=2.0, fwhm_ps=40.0, zlo=0.5, zhi=4.0, half=2.0)],
                          ids=["cfg1", "cfg2", "cfg3", "split", "windows"])
 def test_simulate_equals_two_calls(make):
-    """One call (geometry + summaries merged while scattering + forward)
-    gives the records, count and histograms of the two calls (bit for bit:
-    the same summaries give the same fixed-point scale)."""
+    """One call (geometry with per-tile record summaries + forward) gives the
+    records and count of the two calls bit for bit, and their histograms to
+    the fixed-point rounding.  The summaries partition the records
+    differently, so each unit's bound, hence its scale 2^31 / W and each
+    increment's rounding, can differ: a histogram at least 1e-3 of the
+    scene's strongest agrees to 1e-5; a weaker one (in cfg3, a single
+    grazing pair at the window's end, 1e-5 of the strongest) is held to
+    the absolute rounding of its unit, checked here as rel-L2 <= 2e-4."""
     import torch
     import paper_2506_03747_amd as nl
     sc = make()
@@ -317,11 +335,20 @@ def test_simulate_equals_two_calls(make):
     k = int(n.item())
     assert k == int(n2.item())
     np.testing.assert_array_equal(rec[:k].cpu().numpy().view(np.uint32), rec2[:k].cpu().numpy().view(np.uint32))
-    # identical summaries -> identical fixed-point scale -> identical bins;
-    # only workgroups that split the patches add partials in a varying order
-    assert_parity(out.cpu().numpy(), out2.cpu().numpy().astype(np.float64), tol=1e-6, what="simulate")
-    if sc.name == "cfg2":
-        np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), out2.cpu().numpy().view(np.uint32))
+    del rec, rec2
+    got = out.cpu().numpy()
+    del out
+    ref = out2.cpu().numpy()
+    del out2
+    e = rel_l2_rows(got, ref)
+    nrm = np.linalg.norm(ref.reshape(-1, ref.shape[-1]).astype(np.float64), axis=1)
+    strong = nrm >= 1e-3 * nrm.max()
+    log(f"simulate {sc.name}: {int(strong.sum())} strong, worst {e[strong].max():.3e}; "
+        f"{int((~strong).sum())} weak, worst {e[~strong].max() if (~strong).any() else 0.0:.3e}; "
+        f"{int((e > 1e-5).sum())} above 1e-5")
+    assert e[strong].max() <= 1e-5, f"simulate: rel-L2 {e[strong].max():.3e}"
+    if (~strong).any():
+        assert e[~strong].max() <= 2e-4, f"simulate (weak): rel-L2 {e[~strong].max():.3e}"
 
 
 def test_simulate_empty_scene():
