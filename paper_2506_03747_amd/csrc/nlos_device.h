@@ -125,6 +125,31 @@ __device__ __forceinline__ Leg leg_eval(float cx2, float cy2, float ax, float by
     return l;
 }
 
+// The same for a record whose coordinates are multiplied by sig (bins per
+// metre of one leg) before anything else, with the arrival offset folded in:
+// rr = r + off in bins by a single fma.  q is unchanged (its numerator and
+// r^4 both carry sig^4); ri2, ri4 and PatchC::ap carry sig^-2, sig^-4 and
+// sig^-4, which the caller folds into its fixed-point scale.
+__device__ __forceinline__ PatchC patch_consts_scaled(float4 A, float4 B, bool cosines, float sig)
+{
+    A.x *= sig;
+    A.y *= sig;
+    A.z *= sig;
+    return patch_consts(A, B, cosines);
+}
+
+__device__ __forceinline__ Leg leg_eval_at(float cx2, float cy2, float ax, float by, float off, bool cosines)
+{
+    Leg l;
+    const float r2 = cx2 + cy2;
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    l.rr = fmaf(r2, ri, off);
+    l.ri2 = ri * ri;
+    l.ri4 = l.ri2 * l.ri2;
+    l.q = cosines ? __builtin_amdgcn_fmed3f((ax + by) * l.ri4, 0.0f, 1.0f) : 1.0f;
+    return l;
+}
+
 // Fast-path decision on w = u + delta (delta folded into the offset):
 // k = floor(w); when frac(w) >= 2 delta the bin is k for certain, else the
 // pair is re-evaluated in fp64 (k - 1 or k).

@@ -170,6 +170,16 @@ __device__ __forceinline__ float4 load4(const float4* p, size_t i)
     return make_float4(v.x, v.y, v.z, v.w);
 }
 
+// The first three words of record half i (the pair loop does not read the
+// fourth; a 12-byte load leaves no dead register that an in-flight load
+// would still be writing).
+typedef float v3f __attribute__((ext_vector_type(3)));
+__device__ __forceinline__ float4 load3(const float4* p, size_t i)
+{
+    const v3f v = *gmem(reinterpret_cast<const v3f*>(p + i));
+    return make_float4(v.x, v.y, v.z, 0.f);
+}
+
 __device__ __forceinline__ int active_count(const FwdArgs& a)
 {
     int n = a.n_cap;
@@ -232,20 +242,22 @@ __device__ __forceinline__ void guard_push(const Lds& L, const FwdArgs& a, uint6
 }
 
 // fp32 arrival (in bins, + delta) of record (A, B) at slot j, by the same
-// operations as the pair loop.
+// operations as the pair loop: coordinates in bins (times sig), then one fma
+// per leg.
 template <bool CONF>
 __device__ __forceinline__ float fast_arrival(const FwdArgs& a, const Lds& L, float4 A, float4 B, int j)
 {
-    const PatchC pc = patch_consts(A, B, a.cosines != 0);
+    const float sig = CONF ? a.inv2_f : a.inv_f;
+    const PatchC pc = patch_consts_scaled(A, B, a.cosines != 0, sig);
     float cx2, axv, cy2, byv;
-    col_terms(pc, L.wdx[j], &cx2, &axv);
-    row_terms(pc, L.wdy[j], &cy2, &byv);
-    const Leg ld = leg_eval(cx2, cy2, axv, byv, false);
-    if (CONF) return fmaf(ld.rr, a.inv2_f, L.oil[j]);
-    col_terms(pc, L.wlx[j], &cx2, &axv);
-    row_terms(pc, L.wly[j], &cy2, &byv);
-    const Leg ll = leg_eval(cx2, cy2, axv, byv, false);
-    return fmaf(ll.rr, a.inv_f, L.oil[j]) + fmaf(ld.rr, a.inv_f, L.oid[j]);
+    col_terms(pc, L.wdx[j] * sig, &cx2, &axv);
+    row_terms(pc, L.wdy[j] * sig, &cy2, &byv);
+    const Leg ld = leg_eval_at(cx2, cy2, axv, byv, CONF ? L.oil[j] : L.oid[j], false);
+    if (CONF) return ld.rr;
+    col_terms(pc, L.wlx[j] * sig, &cx2, &axv);
+    row_terms(pc, L.wly[j] * sig, &cy2, &byv);
+    const Leg ll = leg_eval_at(cx2, cy2, axv, byv, L.oil[j], false);
+    return ll.rr + ld.rr;
 }
 
 // After the wavefront's pair loop: its own segment (qn entries), one entry
@@ -728,6 +740,12 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
 #pragma unroll
     for (int k = 0; k < NU; ++k) sk[k] = wbk[k] > 0.f ? 2147483648.0f / wbk[k] : 1.0f;
     if (threadIdx.x < NS) L.gg[threadIdx.x] *= 1.0f / sk[threadIdx.x / NH];
+    // the pair loop works in bins: coordinates times sig, so its weights
+    // carry sig^-4, which the scale it applies takes back
+    const float sig = CONF ? a.inv2_f : a.inv_f;
+    const float s4 = (sig * sig) * (sig * sig);
+#pragma unroll
+    for (int k = 0; k < NU; ++k) sk[k] = fminf(sk[k] * s4, 3.0e38f);
 
     // per-unit wall points and bounds, wave-uniform
     float lxs[NU][TL], lys[NU][TL], oil[NU][TL], wx[NU][TX], wy[NU][TY], oi[NS];
@@ -740,8 +758,8 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
         omax[k] = 0.f;
 #pragma unroll
         for (int l = 0; l < TL; ++l) {
-            lxs[k][l] = uniform(L.wlx[b + l * ND]);
-            lys[k][l] = uniform(L.wly[b + l * ND]);
+            lxs[k][l] = uniform(L.wlx[b + l * ND] * sig);
+            lys[k][l] = uniform(L.wly[b + l * ND] * sig);
             oil[k][l] = uniform(L.oil[b + l * ND]);
             lx0[k] = fminf(lx0[k], lxs[k][l]);
             lx1[k] = fmaxf(lx1[k], lxs[k][l]);
@@ -750,13 +768,13 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
         }
 #pragma unroll
         for (int c = 0; c < TX; ++c) {
-            wx[k][c] = uniform(L.wdx[b + c * TY]);
+            wx[k][c] = uniform(L.wdx[b + c * TY] * sig);
             x0[k] = fminf(x0[k], wx[k][c]);
             x1[k] = fmaxf(x1[k], wx[k][c]);
         }
 #pragma unroll
         for (int r = 0; r < TY; ++r) {
-            wy[k][r] = uniform(L.wdy[b + r]);
+            wy[k][r] = uniform(L.wdy[b + r] * sig);
             y0[k] = fminf(y0[k], wy[k][r]);
             y1[k] = fmaxf(y1[k], wy[k][r]);
         }
@@ -770,7 +788,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
             omax[k] = fmaxf(omax[k], ov);
         }
     }
-    const float inv = a.inv_f, inv2 = a.inv2_f, two_delta = a.two_delta;
+    const float two_delta = a.two_delta;
     // a wavefront skips a unit when every arrival is at least 2 bins past the
     // window (the bound is exact up to fp32 rounding, far below 2 bins)
     const float cut_hi = (float)(hb + Tl + 2);
@@ -778,34 +796,48 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
     float cut_r2[NU];
 #pragma unroll
     for (int k = 0; k < NU; ++k) {
-        // squared distance past which every confocal arrival is beyond cut_hi
-        // (enlarged by 1e-5 relative: the fp32 square and division round)
-        const float rc = fmaxf((cut_hi - omin[k]) / inv2, 0.f);
+        // squared distance (in bins) past which every confocal arrival is
+        // beyond cut_hi (enlarged by 1e-5 relative: the fp32 square rounds)
+        const float rc = fmaxf(cut_hi - omin[k], 0.f);
         cut_r2[k] = rc * rc * 1.00001f;
     }
 
     const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
     const int qw = a.q_cap / kQueueWaves;
     int qn = 0;
-    // Wavefronts take 64-record chunks from a counter in LDS (the next one is
-    // claimed while the current one is evaluated), so they finish together
-    // however unevenly culling thins the chunks.
+    // Wavefronts take 64-record chunks from a counter in LDS, so they finish
+    // together however unevenly culling thins the chunks.  A wavefront holds
+    // two: the records of the next one are loaded while the current one is
+    // evaluated, and the one after is claimed meanwhile.
     int chunk_id = 0;
-    if (lane == 0) chunk_id = (int)atomicAdd(L.next, 1u);
+    if (lane == 0) chunk_id = (int)atomicAdd(L.next, 2u);
     chunk_id = __builtin_amdgcn_readfirstlane(chunk_id);
+    int next_id = chunk_id + 1;
+    float4 An = make_float4(0.f, 0.f, 0.f, 0.f), Bn = An;
+    if (pb + chunk_id * 64 < pe) {
+        const int pl = min(pb + chunk_id * 64 + lane, pe - 1);
+        An = load4(a.patches, 2 * (size_t)pl);
+        Bn = load3(a.patches, 2 * (size_t)pl + 1);
+    }
     for (;;) {
         const int base = pb + chunk_id * 64;
         if (base >= pe) break;
         // lanes past the range read the last record, moved to dummy_x: every
         // arrival of that position lies past the window
         const int p = base + lane;
-        const int pl = min(p, pe - 1);
-        float4 A = load4(a.patches, 2 * (size_t)pl);
-        const float4 B = load4(a.patches, 2 * (size_t)pl + 1);
-        int next_id = 0;
-        if (lane == 0) next_id = (int)atomicAdd(L.next, 1u);
+        float4 A = An;
         if (p >= pe) A.x = a.dummy_x;
-        const PatchC pc = patch_consts(A, B, COS);
+        const PatchC pc = patch_consts_scaled(A, Bn, COS, sig);
+        const float aw = A.w;
+        // records of the next chunk, into the registers the current ones
+        // have just left (past the range: the last record, never used)
+        {
+            const int pl = min(pb + next_id * 64 + lane, pe - 1);
+            An = load4(a.patches, 2 * (size_t)pl);
+            Bn = load3(a.patches, 2 * (size_t)pl + 1);
+        }
+        int claim = 0;
+        if (lane == 0) claim = (int)atomicAdd(L.next, 1u);
 #pragma unroll
         for (int k = 0; k < NU; ++k) {
             if (!uvalid[k]) continue;
@@ -816,21 +848,21 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
                 } else {
                     const float rd = __builtin_amdgcn_sqrtf(rect_r2_min(pc.px, pc.py, pc.pz2, x0[k], x1[k], y0[k], y1[k]));
                     const float rl = __builtin_amdgcn_sqrtf(rect_r2_min(pc.px, pc.py, pc.pz2, lx0[k], lx1[k], ly0[k], ly1[k]));
-                    out = fmaf(rl + rd, inv, omin[k]) >= cut_hi;
+                    out = (rl + rd) + omin[k] >= cut_hi;
                 }
                 if (WIN) {
                     const float Rd = __builtin_amdgcn_sqrtf(rect_r2_max(pc.px, pc.py, pc.pz2, x0[k], x1[k], y0[k], y1[k]));
                     const float Rl = CONF ? Rd
                                           : __builtin_amdgcn_sqrtf(
                                                 rect_r2_max(pc.px, pc.py, pc.pz2, lx0[k], lx1[k], ly0[k], ly1[k]));
-                    out = out || fmaf(Rl + Rd, inv, omax[k]) < cut_lo;
+                    out = out || (Rl + Rd) + omax[k] < cut_lo;
                 }
                 if (__all(out)) continue;
             }
             const int b = k * NH;
             float cx2[TX], axv[TX], cy2[TY], byv[TY];
             if (CONF) {
-                const float aps = (COS ? pc.ap : A.w) * sk[k];
+                const float aps = (COS ? pc.ap : aw) * sk[k];
 #pragma unroll
                 for (int c = 0; c < TX; ++c) col_terms(pc, wx[k][c], &cx2[c], &axv[c]);
 #pragma unroll
@@ -840,8 +872,8 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
 #pragma unroll
                     for (int r = 0; r < TY; ++r) {
                         const int j = b + c * TY + r;
-                        const Leg lg = leg_eval(cx2[c], cy2[r], axv[c], byv[r], COS);
-                        const float w = fmaf(lg.rr, inv2, oi[j]);
+                        const Leg lg = leg_eval_at(cx2[c], cy2[r], axv[c], byv[r], oi[j], COS);
+                        const float w = lg.rr;
                         const Decision d = decide(w, two_delta);
                         const uint32_t inc = (uint32_t)fmaf(COS ? lg.q * lg.q : lg.ri4, aps, 0.5f);
                         const int kl = d.k - hb;
@@ -861,9 +893,9 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
                     float lcx2, lax, lcy2, lby;
                     col_terms(pc, lxs[k][l], &lcx2, &lax);
                     row_terms(pc, lys[k][l], &lcy2, &lby);
-                    const Leg lg = leg_eval(lcx2, lcy2, lax, lby, COS);
-                    ul[l] = fmaf(lg.rr, inv, oil[k][l]);
-                    fl[l] = (COS ? lg.q * pc.ap : lg.ri2 * A.w) * sk[k];
+                    const Leg lg = leg_eval_at(lcx2, lcy2, lax, lby, oil[k][l], COS);
+                    ul[l] = lg.rr;
+                    fl[l] = (COS ? lg.q * pc.ap : lg.ri2 * aw) * sk[k];
                 }
 #pragma unroll
                 for (int c = 0; c < TX; ++c) col_terms(pc, wx[k][c], &cx2[c], &axv[c]);
@@ -874,8 +906,8 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
 #pragma unroll
                     for (int r = 0; r < TY; ++r) {
                         const int dj = c * TY + r;
-                        const Leg lg = leg_eval(cx2[c], cy2[r], axv[c], byv[r], COS);
-                        const float ud = fmaf(lg.rr, inv, oi[b + dj]);
+                        const Leg lg = leg_eval_at(cx2[c], cy2[r], axv[c], byv[r], oi[b + dj], COS);
+                        const float ud = lg.rr;
                         const float fd = COS ? lg.q : lg.ri2;
 #pragma unroll
                         for (int l = 0; l < TL; ++l) {
@@ -893,7 +925,8 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
                 }
             }
         }
-        chunk_id = __builtin_amdgcn_readfirstlane(next_id);
+        chunk_id = next_id;
+        next_id = __builtin_amdgcn_readfirstlane(claim);
     }
     guard_drain<CONF>(L, a, hb, Tl, wave, qw, qn);
     __syncthreads();
@@ -959,7 +992,8 @@ __global__ void __launch_bounds__(256) k_debug_bins(const DebugArgs d)
         }
         const float4 A = a.patches[2 * (size_t)p];
         const float4 B = a.patches[2 * (size_t)p + 1];
-        const PatchC pc = patch_consts(A, B, a.cosines != 0);
+        const float sig = d.confocal ? a.inv2_f : a.inv_f;
+        const PatchC pc = patch_consts_scaled(A, B, a.cosines != 0, sig);
         double off_l, g_l, off_d, g_d;
         device_leg(lx, ly, a.cx, a.cy, a.s, &off_l, &g_l);
         device_leg(wx, wy, a.cx, a.cy, a.s, &off_d, &g_d);
@@ -968,21 +1002,20 @@ __global__ void __launch_bounds__(256) k_debug_bins(const DebugArgs d)
         if (d.confocal) {
             const float oi = (float)(o * a.inv + (double)a.delta);
             float cx2, axv, cy2, byv;
-            col_terms(pc, wx, &cx2, &axv);
-            row_terms(pc, wy, &cy2, &byv);
-            const Leg lg = leg_eval(cx2, cy2, axv, byv, a.cosines != 0);
-            w = fmaf(lg.rr, a.inv2_f, oi);
+            col_terms(pc, wx * sig, &cx2, &axv);
+            row_terms(pc, wy * sig, &cy2, &byv);
+            w = leg_eval_at(cx2, cy2, axv, byv, oi, a.cosines != 0).rr;
         } else {
             const float oil = (float)(off_l * a.inv + (double)a.delta);
             const float oid = (float)(off_d * a.inv);
             float cx2, axv, cy2, byv;
-            col_terms(pc, lx, &cx2, &axv);
-            row_terms(pc, ly, &cy2, &byv);
-            const Leg ll = leg_eval(cx2, cy2, axv, byv, a.cosines != 0);
-            col_terms(pc, wx, &cx2, &axv);
-            row_terms(pc, wy, &cy2, &byv);
-            const Leg ld = leg_eval(cx2, cy2, axv, byv, a.cosines != 0);
-            w = fmaf(ll.rr, a.inv_f, oil) + fmaf(ld.rr, a.inv_f, oid);
+            col_terms(pc, lx * sig, &cx2, &axv);
+            row_terms(pc, ly * sig, &cy2, &byv);
+            const Leg ll = leg_eval_at(cx2, cy2, axv, byv, oil, a.cosines != 0);
+            col_terms(pc, wx * sig, &cx2, &axv);
+            row_terms(pc, wy * sig, &cy2, &byv);
+            const Leg ld = leg_eval_at(cx2, cy2, axv, byv, oid, a.cosines != 0);
+            w = ll.rr + ld.rr;
         }
         const Decision dc = decide(w, a.two_delta);
         double ue;
