@@ -211,6 +211,24 @@ def test_empty_scene():
     assert not tau.cpu().numpy().any()
 
 
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 127, 129, 1023, 1025])
+def test_record_counts_around_chunks(n):
+    """Record counts on both sides of the pair loop's 64-record chunks (a
+    wavefront holds two, the next one's records loaded ahead): a mask with
+    exactly n present pixels."""
+    sc = scenes.tiny(seed=520 + n, scan=(5, 4), patches=(40, 40), n_bins=128)
+    rng = np.random.default_rng(n)
+    m = np.zeros(40 * 40, np.uint8)
+    m[rng.choice(40 * 40, n, replace=False)] = 1
+    sc.mask = m.reshape(40, 40)
+    log(f"records {n}")
+    tau, _, n_act = gpu_forward(sc)
+    assert int(n_act.item()) == n
+    ref = oracle.forward(sc)["tau"]
+    assert ref.any()
+    assert_parity(tau.cpu().numpy(), ref, what=f"n={n}")
+
+
 def test_without_n_active_pointer():
     sc = scenes.tiny(seed=501, scan=(5, 5), patches=(12, 12), standoff_m=0.3)
     tau, _, _ = gpu_forward(sc, use_n_active=False)
