@@ -166,7 +166,7 @@ def main():
 
     graph = None
     if not args.no_graph:
-        graph = graph_leg(step, stream, args.steps, pairs)
+        graph = [graph_leg(step, stream, args.steps, pairs, k) for k in (1, 10)]
     noise = noise_leg(out)
 
     kern_ms = np.array([a.elapsed_time(b) for a, b in evs])
@@ -241,8 +241,9 @@ def noise_leg(tau, reps=20):
     return {"elements": tau.numel(), "ms": round(ms, 4), "gelem_s": round(tau.numel() / (ms * 1e-3) / 1e9, 3)}
 
 
-def graph_leg(step, stream, steps, pairs):
-    """The same step captured once in a HIP graph and replayed."""
+def graph_leg(step, stream, steps, pairs, per_replay=1):
+    """The same step captured in a HIP graph (per_replay steps back to back
+    in one graph) and replayed."""
     import torch
     g = torch.cuda.CUDAGraph()
     side = torch.cuda.Stream()
@@ -251,17 +252,20 @@ def graph_leg(step, stream, steps, pairs):
         step()                      # warm-up on the capture stream
         torch.cuda.synchronize()
         with torch.cuda.graph(g, stream=side):
-            step()
+            for _ in range(per_replay):
+                step()
     torch.cuda.synchronize()
     for _ in range(5):
         g.replay()
     torch.cuda.synchronize()
+    reps = max(1, steps // per_replay)
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for _ in range(reps):
         g.replay()
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
-    return {"ms_per_step": round(ms, 5), "gpairs_s": round(pairs / (ms * 1e-3) / 1e9, 3)}
+    ms = (time.perf_counter() - t0) * 1e3 / (reps * per_replay)
+    return {"steps_per_replay": per_replay, "ms_per_step": round(ms, 5),
+            "gpairs_s": round(pairs / (ms * 1e-3) / 1e9, 3)}
 
 
 def adjoint_leg(reps=10):
