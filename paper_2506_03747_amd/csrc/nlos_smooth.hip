@@ -91,8 +91,12 @@ __device__ __forceinline__ PairS pair_smooth(float4 A, float4 B, float wx, float
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Smooth forward.
-template <int TX, int TY, bool COS>
+// Smooth forward.  RS > 0: the support radius is RS (= a.Rs), known at
+// compile time, so a pair whose whole support lies inside the window takes a
+// straight-line tap sequence with no bounds tests and the tap offsets folded
+// into the LDS instructions; RS = 0, or a support that crosses the window's
+// ends, takes the general loop.
+template <int TX, int TY, bool COS, int RS>
 __global__ void __launch_bounds__(kBlock) k_smooth(const SmoothArgs a)
 {
     constexpr int NH = TX * TY;
@@ -171,6 +175,26 @@ __global__ void __launch_bounds__(kBlock) k_smooth(const SmoothArgs a)
                 float e = __expf(-0.5f * x0 * x0 * inv_s2);
                 const float e0 = e;
                 float qm = __expf(-(1.0f - f) * inv_s2);
+                if (RS > 0 && k0 >= RS && k0 + RS < T) {
+                    u64s* ctr = row + k0;
+#pragma unroll
+                    for (int m = 0; m <= RS; ++m) {
+                        __hip_atomic_fetch_add(ctr + m, (u64s)(uint32_t)fmaf(amp, e, 0.5f), __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                        e *= qm;
+                        qm *= c1;
+                    }
+                    e = e0;
+                    float dm = __expf(-f * inv_s2);
+#pragma unroll
+                    for (int m = 1; m <= RS; ++m) {
+                        e *= dm;
+                        dm *= c1;
+                        __hip_atomic_fetch_add(ctr - m, (u64s)(uint32_t)fmaf(amp, e, 0.5f), __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                    continue;
+                }
                 for (int m = 0; m <= Rs; ++m) {
                     const int k = k0 + m;
                     if (k >= T) break;
@@ -216,8 +240,9 @@ __global__ void __launch_bounds__(kBlock) k_smooth(const SmoothArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint gather.
-template <bool COS>
+// Adjoint gather.  RS as in k_smooth: a support inside the window takes a
+// straight-line tap sequence (G1 = x0 G0 + sum g N(x) m there).
+template <bool COS, int RS>
 __global__ void __launch_bounds__(kBlock) k_adjoint(const SmoothArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -280,28 +305,52 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(const SmoothArgs a)
             float e = __expf(-0.5f * x0 * x0 * inv_s2);
             const float e0 = e;
             float qm = __expf(-(1.0f - f) * inv_s2);
-            for (int m = 0; m <= Rs; ++m) {
-                const int k = k0 + m;
-                if (k >= T) break;
-                if (k >= 0) {
-                    const float gv = g[k] * e;
+            if (RS > 0 && k0 >= RS && k0 + RS < T) {
+                const float* gc = g + k0;
+                float G1m = 0.f;
+#pragma unroll
+                for (int m = 0; m <= RS; ++m) {
+                    const float gv = gc[m] * e;
                     G0 += gv;
-                    G1 = fmaf(gv, x0 + (float)m, G1);
+                    G1m = fmaf(gv, (float)m, G1m);
+                    e *= qm;
+                    qm *= c1;
                 }
-                e *= qm;
-                qm *= c1;
-            }
-            e = e0;
-            float dm = __expf(-f * inv_s2);
-            for (int m = -1; m >= -Rs; --m) {
-                e *= dm;
-                dm *= c1;
-                const int k = k0 + m;
-                if (k < 0) break;
-                if (k < T) {
-                    const float gv = g[k] * e;
+                e = e0;
+                float dm = __expf(-f * inv_s2);
+#pragma unroll
+                for (int m = 1; m <= RS; ++m) {
+                    e *= dm;
+                    dm *= c1;
+                    const float gv = gc[-m] * e;
                     G0 += gv;
-                    G1 = fmaf(gv, x0 + (float)m, G1);
+                    G1m = fmaf(gv, -(float)m, G1m);
+                }
+                G1 = fmaf(x0, G0, G1m);
+            } else {
+                for (int m = 0; m <= Rs; ++m) {
+                    const int k = k0 + m;
+                    if (k >= T) break;
+                    if (k >= 0) {
+                        const float gv = g[k] * e;
+                        G0 += gv;
+                        G1 = fmaf(gv, x0 + (float)m, G1);
+                    }
+                    e *= qm;
+                    qm *= c1;
+                }
+                e = e0;
+                float dm = __expf(-f * inv_s2);
+                for (int m = -1; m >= -Rs; --m) {
+                    e *= dm;
+                    dm *= c1;
+                    const int k = k0 + m;
+                    if (k < 0) break;
+                    if (k < T) {
+                        const float gv = g[k] * e;
+                        G0 += gv;
+                        G1 = fmaf(gv, x0 + (float)m, G1);
+                    }
                 }
             }
             G0 *= a.norm;
@@ -433,17 +482,29 @@ __global__ void __launch_bounds__(256) k_grad_gather(const GradMapArgs g, int64_
 
 // ---------------------------------------------------------------------------
 // Launchers.
-template <int TX, int TY>
-static hipError_t launch_smooth_shape(const SmoothArgs& a, int64_t n_blocks, size_t lds, hipStream_t st)
+template <int TX, int TY, int RS>
+static hipError_t launch_smooth_rs(const SmoothArgs& a, int64_t n_blocks, size_t lds, hipStream_t st)
 {
-    const void* k = a.cosines ? (const void*)k_smooth<TX, TY, true> : (const void*)k_smooth<TX, TY, false>;
+    const void* k = a.cosines ? (const void*)k_smooth<TX, TY, true, RS> : (const void*)k_smooth<TX, TY, false, RS>;
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (a.cosines)
-        hipLaunchKernelGGL((k_smooth<TX, TY, true>), dim3((unsigned)n_blocks), dim3(kBlock), lds, st, a);
+        hipLaunchKernelGGL((k_smooth<TX, TY, true, RS>), dim3((unsigned)n_blocks), dim3(kBlock), lds, st, a);
     else
-        hipLaunchKernelGGL((k_smooth<TX, TY, false>), dim3((unsigned)n_blocks), dim3(kBlock), lds, st, a);
+        hipLaunchKernelGGL((k_smooth<TX, TY, false, RS>), dim3((unsigned)n_blocks), dim3(kBlock), lds, st, a);
     return hipGetLastError();
+}
+
+// Support radii with a straight-line tap sequence: ceil(6 sigma) for the
+// jitter widths of the paper's configurations (FWHM / bin = 70/16, 50/8,
+// 30/4 ps give 12, 16, 20); any other radius runs the general loop.
+template <int TX, int TY>
+static hipError_t launch_smooth_shape(const SmoothArgs& a, int64_t n_blocks, size_t lds, hipStream_t st)
+{
+    if (a.Rs == 12) return launch_smooth_rs<TX, TY, 12>(a, n_blocks, lds, st);
+    if (a.Rs == 16) return launch_smooth_rs<TX, TY, 16>(a, n_blocks, lds, st);
+    if (a.Rs == 20) return launch_smooth_rs<TX, TY, 20>(a, n_blocks, lds, st);
+    return launch_smooth_rs<TX, TY, 0>(a, n_blocks, lds, st);
 }
 
 hipError_t launch_smooth(const SmoothArgs& a, int tx, int ty, int64_t n_blocks, size_t lds, hipStream_t st)
@@ -458,20 +519,28 @@ hipError_t launch_smooth(const SmoothArgs& a, int tx, int ty, int64_t n_blocks, 
     return hipErrorInvalidValue;
 }
 
+template <int RS>
+static hipError_t launch_adjoint_rs(const SmoothArgs& a, const dim3& grid, size_t lds, hipStream_t st)
+{
+    const void* k = a.cosines ? (const void*)k_adjoint<true, RS> : (const void*)k_adjoint<false, RS>;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (a.cosines)
+        hipLaunchKernelGGL((k_adjoint<true, RS>), grid, dim3(kBlock), lds, st, a);
+    else
+        hipLaunchKernelGGL((k_adjoint<false, RS>), grid, dim3(kBlock), lds, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_adjoint(const SmoothArgs& a, int64_t patch_blocks, size_t lds, hipStream_t st)
 {
     if (patch_blocks > 0) {
         if (patch_blocks > 0x7fffffff || a.n_split > 65535) return hipErrorInvalidValue;
-        const void* k = a.cosines ? (const void*)k_adjoint<true> : (const void*)k_adjoint<false>;
-        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
         const dim3 grid((unsigned)patch_blocks, (unsigned)a.n_split);
-        if (a.cosines)
-            hipLaunchKernelGGL(k_adjoint<true>, grid, dim3(kBlock), lds, st, a);
-        else
-            hipLaunchKernelGGL(k_adjoint<false>, grid, dim3(kBlock), lds, st, a);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        if (a.Rs == 12) return launch_adjoint_rs<12>(a, grid, lds, st);
+        if (a.Rs == 16) return launch_adjoint_rs<16>(a, grid, lds, st);
+        if (a.Rs == 20) return launch_adjoint_rs<20>(a, grid, lds, st);
+        return launch_adjoint_rs<0>(a, grid, lds, st);
     }
     return hipSuccess;
 }
