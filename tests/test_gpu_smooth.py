@@ -38,9 +38,16 @@ SCENES = [
     dict(seed=605, scan=(1, 1), patches=(9, 9), fwhm_ps=30.0),
     dict(seed=606, scan=(5, 6), patches=(12, 10), n_bins=97, bin_ps=30.0, fwhm_ps=45.0),  # T not a multiple of 4
 ]
+# support radii ceil(6 sigma) = 12, 16, 20, which the kernels run as
+# straight-line tap sequences (the scenes above have other radii: general loop)
+RADII = [
+    dict(seed=608, bin_ps=16.0, fwhm_ps=70.0),
+    dict(seed=609, bin_ps=8.0, fwhm_ps=50.0, scan=(4, 5)),
+    dict(seed=610, bin_ps=4.0, fwhm_ps=30.0, n_bins=1024, standoff_m=0.0),
+]
 
 
-@pytest.mark.parametrize("kw", SCENES, ids=[str(k["seed"]) for k in SCENES])
+@pytest.mark.parametrize("kw", SCENES + RADII, ids=[str(k["seed"]) for k in SCENES + RADII])
 def test_smooth_forward_parity(kw):
     import torch
     import paper_2506_03747_amd as nl
@@ -67,7 +74,7 @@ def test_smooth_window_edges():
     assert_parity(tau.cpu().numpy(), ref, what="edges")
 
 
-@pytest.mark.parametrize("kw", SCENES[:4], ids=[str(k["seed"]) for k in SCENES[:4]])
+@pytest.mark.parametrize("kw", SCENES[:4] + RADII, ids=[str(k["seed"]) for k in SCENES[:4] + RADII])
 def test_adjoint_records_parity(kw):
     import torch
     import paper_2506_03747_amd as nl
