@@ -176,13 +176,14 @@ int nlos_forward(const nlos_params* p, const float* patches, int32_t n_patches,
 /*
  * The whole path in one call: nlos_patches_from_depth for the depth map on
  * grid g (flags = p->flags) followed by nlos_forward over its records, with
- * the record summaries (one per 16x16-pixel tile of the map) built while
- * the records are written (no separate pass).  patches
- * [g.nx*g.ny][8] and n_active are written as by nlos_patches_from_depth,
- * bit for bit; out as by nlos_forward, with the same bins and values equal
- * to rounding (the summaries, and so the fixed-point scale, differ).  ws: at least nlos_simulate_workspace_bytes, 256-byte
- * aligned.  forward_mark: a hipEvent_t recorded on the stream right before
- * the pair kernel (for timing it), or NULL.
+ * the record summaries (one per 16x16-pixel tile of the map) built while the
+ * records are written (no separate pass).  patches [g.nx*g.ny][8] and
+ * n_active are written as by nlos_patches_from_depth, bit for bit; out as by
+ * nlos_forward, with the same bins and values equal to rounding (the
+ * summaries, and so the fixed-point scales, differ).  ws: at least
+ * nlos_simulate_workspace_bytes, 256-byte aligned.  forward_mark: a
+ * hipEvent_t recorded on the stream right before the pair kernel (for timing
+ * it), or NULL.
  */
 int nlos_simulate_workspace_bytes(const nlos_params* p, const nlos_grid* g, size_t* bytes);
 
