@@ -27,6 +27,9 @@ METRIC = "Gpairs/s (scan pt×patch) + % FP32 peak; p50/p99 latency, batched vs p
 FLOPS_CONFOCAL = 29      # nominal flops per confocal pair (formula written without FMA)
 FLOPS_NONCONFOCAL = 48   # per non-confocal (laser, detector, patch) triple
 FP32_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
+# the same peak without packed FP32 (256 CU x 4 SIMD x 16 lanes x 2 flops per
+# FMA x 2.4 GHz): the ceiling of kernels built with packed FP32 disabled
+FP32_FMA_CEILING_TFLOPS = 78.6
 
 # HBM bytes per launch of the cfg2 pair kernel from rocprofv3 counters
 # (FETCH_SIZE 4324.5 KiB x 2.0 + WRITE_SIZE 16384 KiB x 1.0; the factors are
@@ -212,7 +215,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                      "traffic": traffic_for_sources() if args.workload == "cfg2" else None, "kernel": "k_forward",
-                     "kernel_ms": round(kern_avg, 5), "flops_per_pair": F},
+                     "kernel_ms": round(kern_avg, 5), "flops_per_pair": F,
+                     "frac_of_unpacked_ceiling": round(achieved / FP32_FMA_CEILING_TFLOPS, 4)},
         "cpu_baseline": cpu,
         "graph": graph,
         "noise": noise,
