@@ -555,14 +555,41 @@ struct SmoothPlan {
     int tx, ty;
     int64_t tiles, n_blocks;
     size_t lds;
+    int moments;   // 1: k_smooth_mom (moment rows), 0: k_smooth (taps)
+    int stride;    // u64 bins per LDS row
 };
 
 size_t smooth_lds(int nh, int stride) { return (size_t)nh * stride * 8 + (size_t)nh * 12 + 64 * 4 + 64; }
 
-int smooth_plan(const nlos_params* p, int32_t n_patches, SmoothPlan* sp, int* split)
+int smooth_plan(const nlos_params* p, int32_t n_patches, int rs, SmoothPlan* sp, int* split)
 {
     static const int shapes[5][2] = {{4, 4}, {4, 2}, {2, 2}, {2, 1}, {1, 1}};
     const int T = p->n_bins;
+    // moments of the sub-bin offset when the support radius has a compiled
+    // variant and the moment rows (with a halo of rs bins on both sides) fit
+    sp->moments = 0;
+    sp->stride = T;
+    if (nlos::smooth_moments_radius(rs)) {
+        const int stride = (T + 2 * rs + 1) & ~1;
+        const int64_t rows = (int64_t)nlos::kSmoothPoints * nlos::kSmoothMoments;
+        const size_t lds = (size_t)rows * stride * 8 + 2048;
+        if (lds <= kLdsMax && rows * (T + 2 * rs) <= 24 * (int64_t)nlos::kBlock) {
+            sp->moments = 1;
+            sp->stride = stride;
+            sp->tx = nlos::kSmoothPoints;
+            sp->ty = 1;
+            sp->tiles = (int64_t)((p->relay.nx + sp->tx - 1) / sp->tx) * p->relay.ny;
+            int64_t sv = 1;
+            if (sp->tiles < kTargetBlocks) {
+                sv = (kTargetBlocks + sp->tiles - 1) / sp->tiles;
+                sv = std::min<int64_t>(sv, std::max<int64_t>(1, n_patches / nlos::kBlock));
+            }
+            *split = (int)sv;
+            sp->n_blocks = sp->tiles * sv;
+            sp->lds = lds;
+            return NLOS_OK;
+        }
+    }
     int chosen = -1, largest = -1;
     for (int i = 0; i < 5; ++i) {
         if (smooth_lds(shapes[i][0] * shapes[i][1], T) > kLdsMax) continue;
@@ -915,7 +942,7 @@ int nlos_forward_smooth_workspace_bytes(const nlos_params* p, int32_t n_patches,
     if (n_patches < 0 || n_patches > NLOS_MAX_PATCHES) return NLOS_EINVAL;
     SmoothPlan sp;
     int split = 1;
-    rc = smooth_plan(p, n_patches, &sp, &split);
+    rc = smooth_plan(p, n_patches, a.Rs, &sp, &split);
     if (rc != NLOS_OK) return rc;
     *bytes = stats_bytes(n_patches);
     return NLOS_OK;
@@ -930,7 +957,7 @@ int nlos_forward_smooth(const nlos_params* p, const float* patches, int32_t n_pa
     if (!out || !aligned(out, 16)) return NLOS_EINVAL;
     SmoothPlan sp;
     int split = 1;
-    rc = smooth_plan(p, n_patches, &sp, &split);
+    rc = smooth_plan(p, n_patches, a.Rs, &sp, &split);
     if (rc != NLOS_OK) return rc;
     const size_t need = stats_bytes(n_patches);
     if (ws_bytes < need) return NLOS_ENOSPC;
@@ -941,7 +968,7 @@ int nlos_forward_smooth(const nlos_params* p, const float* patches, int32_t n_pa
     a.tiles_x = (p->relay.nx + sp.tx - 1) / sp.tx;
     a.tiles_y = (p->relay.ny + sp.ty - 1) / sp.ty;
     a.n_split = split;
-    a.stride = p->n_bins;
+    a.stride = sp.stride;
     a.atomic_out = split > 1 ? 1 : 0;
     a.stats = reinterpret_cast<nlos::ChunkStat*>(ws);
     a.n_stats = (int32_t)stats_count(n_patches);
@@ -959,7 +986,8 @@ int nlos_forward_smooth(const nlos_params* p, const float* patches, int32_t n_pa
         e = nlos::launch_fill(out, (size_t)n_hist(p) * (size_t)p->n_bins, st);
         if (e != hipSuccess) return hip_fail(e);
     }
-    e = nlos::launch_smooth(a, sp.tx, sp.ty, sp.n_blocks, sp.lds, st);
+    e = sp.moments ? nlos::launch_smooth_moments(a, sp.n_blocks, sp.lds, st)
+                   : nlos::launch_smooth(a, sp.tx, sp.ty, sp.n_blocks, sp.lds, st);
     return e == hipSuccess ? NLOS_OK : hip_fail(e);
 }
 

@@ -231,6 +231,12 @@ hipError_t launch_fill(float* out, size_t n, hipStream_t st);
 hipError_t launch_debug(const DebugArgs& a, hipStream_t st);
 
 hipError_t launch_smooth(const SmoothArgs& a, int tx, int ty, int64_t n_blocks, size_t lds, hipStream_t st);
+// Smooth forward by moments of the sub-bin offset (support radii 12, 16, 20):
+// kSmoothPoints scan points per workgroup, kSmoothMoments LDS rows each.
+constexpr int kSmoothMoments = 8;
+constexpr int kSmoothPoints = 2;
+bool smooth_moments_radius(int rs);
+hipError_t launch_smooth_moments(const SmoothArgs& a, int64_t n_blocks, size_t lds, hipStream_t st);
 hipError_t launch_adjoint(const SmoothArgs& a, int64_t patch_blocks, size_t lds, hipStream_t st);
 hipError_t launch_adjoint_reduce(const SmoothArgs& a, float* grad_rec, hipStream_t st);
 hipError_t launch_grad_maps(const GradMapArgs& g, hipStream_t st);

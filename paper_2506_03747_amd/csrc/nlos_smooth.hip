@@ -10,10 +10,13 @@
 // extensions).  Arrivals are computed in fp64: an fp32 distance puts u off by
 // ~1e-4 bins at u ~ 1000, which would move the Gaussian samples by ~1e-5.
 //
-// k_smooth       forward: a workgroup owns a tile of scan points (LDS rows of
-//                64-bit fixed-point bins), a lane one patch; 2 Rs + 1 LDS
-//                adds per pair, Gaussian samples by a three-exponential
-//                recurrence.
+// k_smooth_mom   forward for support radii 12, 16, 20: eight moments of the
+//                sub-bin offset per pair into LDS rows, then a convolution of
+//                each moment row with the matching Gaussian-derivative kernel.
+// k_smooth       forward otherwise: a workgroup owns a tile of scan points
+//                (LDS rows of 64-bit fixed-point bins), a lane one patch;
+//                2 Rs + 1 LDS adds per pair, Gaussian samples by a
+//                three-exponential recurrence.
 // k_adjoint      gather: a lane owns one patch and loops over a range of scan
 //                points whose upstream-gradient rows are staged in LDS; per
 //                pair G0 = sum g N(x), G1 = sum g (x / sigma^2) N(x) give
@@ -241,6 +244,155 @@ __global__ void __launch_bounds__(kBlock) k_smooth(const SmoothArgs a)
             unsafeAtomicAdd(o, v);
         else
             *o = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Smooth forward by moments.  With t = f - 1/2 the pair's sub-bin offset
+// about the centre of its bin k0 = floor(u), its contribution w N(d + 1/2 - f)
+// to bin k0 + d is the Taylor series sum_m (-t)^m / m! w N^(m)(d).  A pair
+// therefore adds w (-t)^m to moment row m at bin k0 (kSmoothMoments rows, one
+// LDS add each instead of 2 Rs + 1), and the flush convolves each moment row
+// with K_m(d) = N^(m)(d) / m! over |d| <= Rs, the same support as the direct
+// sum.  N^(m)(d) = N(d) (-1/sigma)^m He_m(d / sigma) (He: probabilists'
+// Hermite polynomials).  With |t| <= 1/2 and sigma >= 1.86 bins (Rs >= 12),
+// the series cut after m = 7 is within 6e-8 (relative L2 over the support)
+// of the direct sum for every t.  Moments are signed 64-bit fixed point
+// (two's complement sums), increments |w (-t)^m| s <= 2^30.
+template <bool COS, int RS>
+__global__ void __launch_bounds__(kBlock) k_smooth_mom(const SmoothArgs a)
+{
+    constexpr int NP = kSmoothPoints, NM = kSmoothMoments, NR = NP * NM, ND = 2 * RS + 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    u64s* hist = reinterpret_cast<u64s*>(smem);   // row (point c, moment m) = c NM + m; bin k0 at k0 + RS
+    double* so = reinterpret_cast<double*>(smem + (size_t)NR * a.stride * 8);
+    float* sg = reinterpret_cast<float*>(so + NP);
+    float* red = sg + NP;
+    float* kt = red + 64;                          // [NM][ND]
+    const int n_act = smooth_active(a);
+    const int split = (int)(blockIdx.x % a.n_split);
+    const int tile = (int)(blockIdx.x / a.n_split);
+    const int tx0 = (tile / a.tiles_y) * NP, ty0 = tile % a.tiles_y;
+    const int chunk = (n_act + a.n_split - 1) / a.n_split;
+    const int pb = min(n_act, split * chunk), pe = min(n_act, pb + chunk);
+    const int T = a.T, stride = a.stride;
+
+    for (int i = threadIdx.x; i < NR * stride; i += kBlock) hist[i] = 0ull;
+    if (threadIdx.x < NP) {
+        const int c = threadIdx.x;
+        double off, g;
+        device_leg(canon(a.rx, min(tx0 + c, a.rx.n - 1)), canon(a.ry, ty0), a.cx, a.cy, a.s, &off, &g);
+        so[c] = off + off;
+        sg[c] = (float)(g * g);
+    }
+    if (threadIdx.x < NM * ND) {
+        const int m = threadIdx.x / ND, d = (int)threadIdx.x % ND - RS;
+        const double sig = (double)a.sigma, x = d / sig;
+        double h0 = 1.0, h1 = x;   // He_0, He_1
+        for (int n = 1; n < m; ++n) {
+            const double h2 = x * h1 - n * h0;
+            h0 = h1;
+            h1 = h2;
+        }
+        const double he = m == 0 ? 1.0 : h1;
+        double f = 1.0;
+        for (int n = 2; n <= m; ++n) f *= n;
+        kt[threadIdx.x] = (float)((double)a.norm * exp(-0.5 * x * x) * he * pow(-1.0 / sig, m) / f);
+    }
+    float wx[NP];
+#pragma unroll
+    for (int c = 0; c < NP; ++c) wx[c] = canon(a.rx, min(tx0 + c, a.rx.n - 1));
+    const float wy = canon(a.ry, ty0);
+    // weight bound over the record summaries: a_max / r_min^4 -> scale
+    float wb = 0.f;
+    {
+        const float x0 = fminf(wx[0], wx[NP - 1]), x1 = fmaxf(wx[0], wx[NP - 1]);
+        for (int i = threadIdx.x; i < a.n_stats; i += kBlock) {
+            const StatF c = load_stat(a.stats, i);
+            if (c.count <= 0) continue;
+            const float ddx = fmaxf(fmaxf(x0 - c.x1, c.x0 - x1), 0.f);
+            const float ddy = fmaxf(fmaxf(wy - c.y1, c.y0 - wy), 0.f);
+            const float r2 = fmaf(ddx, ddx, fmaf(ddy, ddy, c.z0 * c.z0));
+            wb = fmaxf(wb, c.amax / (r2 * r2));
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) wb = fmaxf(wb, __shfl_xor(wb, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = wb;
+    __syncthreads();
+    float W = 0.f;
+    for (int w = 0; w < kBlock / 64; ++w) W = fmaxf(W, red[w]);
+    const float s = W > 0.f ? 1073741824.0f / W : 1.0f;   // |increments| <= 2^30
+
+    for (int base = pb; base < pe; base += kBlock) {
+        const int p = base + (int)threadIdx.x;
+        if (p >= pe) continue;
+        const float4 A = a.patches[2 * (size_t)p];
+        const float4 B = a.patches[2 * (size_t)p + 1];
+#pragma unroll
+        for (int c = 0; c < NP; ++c) {
+            if (tx0 + c >= a.rx.n) continue;
+            const PairS q = pair_smooth(A, B, wx[c], wy, so[c], sg[c], a.inv, COS, false);
+            const double k0d = floor(q.u);
+            if (q.w <= 0.f || k0d + RS < 0.0 || k0d - RS > (double)(T - 1)) continue;
+            const int k0 = (int)k0d;
+            const float mt = 0.5f - (float)(q.u - k0d);   // -t
+            float v = q.w * s;
+            u64s* r0 = hist + (size_t)(c * NM) * stride + (k0 + RS);
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+                const long long iv = (long long)__float2int_rn(v);
+                __hip_atomic_fetch_add(r0 + (size_t)m * stride, (u64s)iv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                v *= mt;
+            }
+        }
+    }
+    __syncthreads();
+    // moment rows -> float, in place (row r keeps its byte offset; values
+    // pass through registers so that no thread overwrites what another reads)
+    const int L = T + 2 * RS;
+    constexpr int kMaxPer = 24;
+    float vals[kMaxPer];
+    const int n_vals = NR * L;
+#pragma unroll
+    for (int k = 0; k < kMaxPer; ++k) {
+        const int i = (int)threadIdx.x + k * kBlock;
+        vals[k] = 0.f;
+        if (i < n_vals) {
+            const int r = i / L, b = i - r * L;
+            const u64s x = hist[(size_t)r * stride + b];
+            vals[k] = fmaf((float)(int32_t)(uint32_t)(x >> 32), 4294967296.0f, (float)(uint32_t)x);
+        }
+    }
+    __syncthreads();
+    float* F = reinterpret_cast<float*>(smem);     // row r at float offset 2 r stride
+#pragma unroll
+    for (int k = 0; k < kMaxPer; ++k) {
+        const int i = (int)threadIdx.x + k * kBlock;
+        if (i < n_vals) {
+            const int r = i / L, b = i - r * L;
+            F[(size_t)r * 2 * stride + b] = vals[k];
+        }
+    }
+    __syncthreads();
+    const float inv_sc = 1.0f / s;
+    for (int o = threadIdx.x; o < NP * T; o += kBlock) {
+        const int c = o / T, k = o - c * T;
+        if (tx0 + c >= a.rx.n) continue;
+        float acc = 0.f;
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            // F index of bin k - d, d = dd - RS: k + 2 RS - dd
+            const float* f = F + (size_t)(c * NM + m) * 2 * stride + k + 2 * RS;
+            const float* km = kt + m * ND;
+#pragma unroll
+            for (int dd = 0; dd < ND; ++dd) acc = fmaf(f[-dd], km[dd], acc);
+        }
+        float* dst = a.out + ((size_t)(tx0 + c) * a.ry.n + ty0) * (size_t)T + k;
+        if (a.atomic_out)
+            unsafeAtomicAdd(dst, acc * inv_sc);
+        else
+            *dst = acc * inv_sc;
     }
 }
 
@@ -521,6 +673,34 @@ hipError_t launch_smooth(const SmoothArgs& a, int tx, int ty, int64_t n_blocks, 
     if (tx == 2 && ty == 2) return launch_smooth_shape<2, 2>(a, n_blocks, lds, st);
     if (tx == 2 && ty == 1) return launch_smooth_shape<2, 1>(a, n_blocks, lds, st);
     if (tx == 1 && ty == 1) return launch_smooth_shape<1, 1>(a, n_blocks, lds, st);
+    return hipErrorInvalidValue;
+}
+
+bool smooth_moments_radius(int rs) { return rs == 12 || rs == 16 || rs == 20; }
+
+template <int RS>
+static hipError_t launch_smooth_mom_rs(const SmoothArgs& a, int64_t n_blocks, size_t lds, hipStream_t st)
+{
+    const void* k = a.cosines ? (const void*)k_smooth_mom<true, RS> : (const void*)k_smooth_mom<false, RS>;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (a.cosines)
+        hipLaunchKernelGGL((k_smooth_mom<true, RS>), dim3((unsigned)n_blocks), dim3(kBlock), lds, st, a);
+    else
+        hipLaunchKernelGGL((k_smooth_mom<false, RS>), dim3((unsigned)n_blocks), dim3(kBlock), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_smooth_moments(const SmoothArgs& a, int64_t n_blocks, size_t lds, hipStream_t st)
+{
+    if (n_blocks <= 0) return hipSuccess;
+    if (n_blocks > 0x7fffffff) return hipErrorInvalidValue;
+    // the flush keeps at most 24 values per thread in registers
+    if ((int64_t)kSmoothPoints * kSmoothMoments * (a.T + 2 * a.Rs) > 24 * (int64_t)kBlock) return hipErrorInvalidValue;
+    if (a.stride < a.T + 2 * a.Rs) return hipErrorInvalidValue;
+    if (a.Rs == 12) return launch_smooth_mom_rs<12>(a, n_blocks, lds, st);
+    if (a.Rs == 16) return launch_smooth_mom_rs<16>(a, n_blocks, lds, st);
+    if (a.Rs == 20) return launch_smooth_mom_rs<20>(a, n_blocks, lds, st);
     return hipErrorInvalidValue;
 }
 
