@@ -1,0 +1,70 @@
+"""The moment form of the smooth response (the GPU's k_smooth_mom), checked on
+the host: with t = f - 1/2, the Taylor series sum_{m<=7} (-t)^m / m! N^(m)(d),
+N^(m)(d) = N(d) (-1/sigma)^m He_m(d / sigma), reproduces the direct Gaussian
+samples N(d + 1/2 - f) over the support |d| <= ceil(6 sigma) to the stated
+bound for every sub-bin offset, at the widths that take that kernel."""
+import math
+
+import numpy as np
+import pytest
+
+
+def hermite_e(n, x):
+    """Probabilists' Hermite polynomial He_n by its three-term recurrence."""
+    h0, h1 = np.ones_like(x), x
+    if n == 0:
+        return h0
+    for k in range(1, n):
+        h0, h1 = h1, x * h1 - k * h0
+    return h1
+
+
+def moment_kernels(sigma, rs, n_moments=8):
+    d = np.arange(-rs, rs + 1, dtype=np.float64)
+    g = np.exp(-0.5 * (d / sigma) ** 2) / (sigma * math.sqrt(2 * math.pi))
+    return d, [g * (-1.0 / sigma) ** m * hermite_e(m, d / sigma) / math.factorial(m) for m in range(n_moments)]
+
+
+@pytest.mark.parametrize("fwhm_ps,bin_ps", [(70.0, 16.0), (50.0, 8.0), (30.0, 4.0)])
+def test_moment_series_matches_direct_samples(fwhm_ps, bin_ps):
+    sigma = fwhm_ps / (2 * math.sqrt(2 * math.log(2))) / bin_ps
+    rs = math.ceil(6 * sigma)
+    assert rs in (12, 16, 20)
+    d, K = moment_kernels(sigma, rs)
+    worst = 0.0
+    for f in np.linspace(0.0, 1.0, 101, endpoint=False):
+        t = f - 0.5
+        direct = np.exp(-0.5 * ((d + 0.5 - f) / sigma) ** 2) / (sigma * math.sqrt(2 * math.pi))
+        series = sum((-t) ** m * K[m] for m in range(len(K)))
+        worst = max(worst, np.linalg.norm(series - direct) / np.linalg.norm(direct))
+    assert worst <= 7e-8
+
+
+def test_moment_series_shifted_histogram():
+    """A set of arrivals binned into moment rows and convolved gives the
+    histogram of the direct sum (sigma = 2.65 bins, Rs = 16)."""
+    sigma, rs, T = 50.0 / (2 * math.sqrt(2 * math.log(2))) / 8.0, 16, 128
+    rng = np.random.default_rng(7)
+    u = rng.uniform(-10.0, T + 10.0, 500)
+    w = rng.uniform(0.1, 1.0, 500)
+    direct = np.zeros(T)
+    for ui, wi in zip(u, w):
+        k0 = math.floor(ui)
+        for k in range(max(0, k0 - rs), min(T, k0 + rs + 1)):
+            x = k + 0.5 - ui
+            direct[k] += wi * math.exp(-0.5 * (x / sigma) ** 2) / (sigma * math.sqrt(2 * math.pi))
+    d, K = moment_kernels(sigma, rs)
+    H = np.zeros((len(K), T + 2 * rs))
+    for ui, wi in zip(u, w):
+        k0 = math.floor(ui)
+        if k0 + rs < 0 or k0 - rs > T - 1:
+            continue
+        t = (ui - k0) - 0.5
+        for m in range(len(K)):
+            H[m, k0 + rs] += wi * (-t) ** m
+    series = np.zeros(T)
+    for k in range(T):
+        for m in range(len(K)):
+            for j, dd in enumerate(d.astype(int)):
+                series[k] += H[m, k - dd + rs] * K[m][j]
+    assert np.linalg.norm(series - direct) <= 1e-7 * np.linalg.norm(direct)
