@@ -255,7 +255,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth(const SmoothArgs a)
 // LDS add each instead of 2 Rs + 1), and the flush convolves each moment row
 // with K_m(d) = N^(m)(d) / m! over |d| <= Rs, the same support as the direct
 // sum.  N^(m)(d) = N(d) (-1/sigma)^m He_m(d / sigma) (He: probabilists'
-// Hermite polynomials).  With |t| <= 1/2 and sigma >= 1.86 bins (Rs >= 12),
+// Hermite polynomials).  With |t| <= 1/2 and sigma > 11/6 bins (Rs >= 12),
 // the series cut after m = 7 is within 7e-8 (relative L2 over the support)
 // of the direct sum for every t.  Moments are signed 64-bit fixed point
 // (two's complement sums), increments |w (-t)^m| s <= 2^30.
