@@ -636,6 +636,50 @@ int adjoint_rows(int T)
 
 size_t adjoint_lds(int rows, int T) { return (((size_t)rows * T * 4 + 15) & ~(size_t)15) + (size_t)rows * 24; }
 
+// Plan of the adjoint: by moments (correlation rows computed once per scan
+// point, in the workspace ahead of the partials) when the support radius has
+// a compiled variant and its rows fit in LDS, else the tap gather.
+struct AdjPlan {
+    int moments, rows, split, mlen;
+    int64_t pbk;       // patch blocks of the gather
+    size_t c_bytes;    // correlation rows [S][kAdjMoments][mlen] fp32, 256-byte aligned
+    size_t lds;
+};
+
+int adjoint_plan(const nlos_params* p, int32_t n_patches, int rs, AdjPlan* ap)
+{
+    const int T = p->n_bins;
+    const int64_t S = (int64_t)p->relay.nx * p->relay.ny;
+    ap->moments = 0;
+    ap->mlen = 0;
+    ap->c_bytes = 0;
+    if (nlos::smooth_moments_radius(rs)) {
+        const int L = T + 2 * rs;
+        const int64_t per_row = (int64_t)nlos::kAdjMoments * L * 4;
+        const int64_t rows = std::min<int64_t>(4, ((int64_t)kLdsMax - 1024) / per_row);
+        const size_t lds_pre = (size_t)(nlos::kAdjMoments * (2 * rs + 1) + T + 4 * rs) * 4;
+        if (rows >= 1 && lds_pre <= kLdsMax) {
+            ap->moments = 1;
+            ap->rows = (int)rows;
+            ap->mlen = L;
+            const int64_t per_block = (int64_t)nlos::kAdjPatches * nlos::kBlock;
+            ap->pbk = ((int64_t)n_patches + per_block - 1) / per_block;
+            const int64_t pb = std::max<int64_t>(1, ap->pbk);
+            int64_t sv = (2 * kTargetBlocks + pb - 1) / pb;
+            ap->split = (int)std::max<int64_t>(1, std::min<int64_t>(sv, std::min<int64_t>(S, 65535)));
+            ap->c_bytes = ((size_t)S * nlos::kAdjMoments * L * 4 + 255) & ~(size_t)255;
+            ap->lds = (((size_t)rows * nlos::kAdjMoments * L * 4 + 15) & ~(size_t)15) + (size_t)rows * 24;
+            return NLOS_OK;
+        }
+    }
+    ap->rows = adjoint_rows(T);
+    if (ap->rows < 1) return NLOS_EINVAL;
+    ap->split = adjoint_split(p, n_patches);
+    ap->pbk = ((int64_t)n_patches + nlos::kBlock - 1) / nlos::kBlock;
+    ap->lds = adjoint_lds(ap->rows, T);
+    return NLOS_OK;
+}
+
 // ---------------------------------------------------------------------------
 // FFT (light-cone) route.
 int lct_setup(const nlos_params* p, nlos::LctArgs* a, int64_t* n3)
@@ -997,8 +1041,11 @@ int nlos_adjoint_workspace_bytes(const nlos_params* p, int32_t n_patches, size_t
     if (!bytes) return NLOS_EINVAL;
     int rc = smooth_setup(p, nullptr, 0, nullptr, &a);
     if (rc != NLOS_OK) return rc;
-    if (n_patches < 0 || n_patches > NLOS_MAX_PATCHES || adjoint_rows(p->n_bins) < 1) return NLOS_EINVAL;
-    *bytes = (size_t)adjoint_split(p, n_patches) * (size_t)n_patches * nlos::kAdjStride * sizeof(double);
+    if (n_patches < 0 || n_patches > NLOS_MAX_PATCHES) return NLOS_EINVAL;
+    AdjPlan ap;
+    rc = adjoint_plan(p, n_patches, a.Rs, &ap);
+    if (rc != NLOS_OK) return rc;
+    *bytes = ap.c_bytes + (size_t)ap.split * (size_t)n_patches * nlos::kAdjStride * sizeof(double);
     return NLOS_OK;
 }
 
@@ -1009,22 +1056,25 @@ int nlos_adjoint(const nlos_params* p, const float* patches, int32_t n_patches, 
     int rc = smooth_setup(p, patches, n_patches, n_active, &a);
     if (rc != NLOS_OK) return rc;
     if (!grad_out || !aligned(grad_out, 16) || !grad_patches || !aligned(grad_patches, 16)) return NLOS_EINVAL;
-    const int rows = adjoint_rows(p->n_bins);
-    if (rows < 1) return NLOS_EINVAL;
+    AdjPlan ap;
+    rc = adjoint_plan(p, n_patches, a.Rs, &ap);
+    if (rc != NLOS_OK) return rc;
     size_t need = 0;
     rc = nlos_adjoint_workspace_bytes(p, n_patches, &need);
     if (rc != NLOS_OK) return rc;
     if (ws_bytes < need) return NLOS_ENOSPC;
-    if (need > 0 && (!ws || !aligned(ws, 16))) return NLOS_EINVAL;
+    if (need > 0 && (!ws || !aligned(ws, 256))) return NLOS_EINVAL;
     const int dev = device_check();
     if (dev != NLOS_OK) return dev;
     a.grad_out = grad_out;
-    a.partial = static_cast<double*>(ws);
-    a.n_split = adjoint_split(p, n_patches);
-    a.rows = rows;
+    a.moments = ap.moments ? static_cast<float*>(ws) : nullptr;
+    a.mlen = ap.mlen;
+    a.partial = reinterpret_cast<double*>(static_cast<char*>(ws) + ap.c_bytes);
+    a.n_split = ap.split;
+    a.rows = ap.rows;
     hipStream_t st = (hipStream_t)stream;
-    const int64_t pbk = ((int64_t)n_patches + nlos::kBlock - 1) / nlos::kBlock;
-    hipError_t e = nlos::launch_adjoint(a, pbk, adjoint_lds(rows, p->n_bins), st);
+    hipError_t e = ap.moments ? nlos::launch_adjoint_moments(a, ap.pbk, ap.lds, st)
+                              : nlos::launch_adjoint(a, ap.pbk, ap.lds, st);
     if (e != hipSuccess) return hip_fail(e);
     e = nlos::launch_adjoint_reduce(a, grad_patches, st);
     return e == hipSuccess ? NLOS_OK : hip_fail(e);

@@ -166,6 +166,8 @@ struct SmoothArgs {
     int32_t cosines;
     ChunkStat* stats;
     int32_t n_stats;
+    float* moments;            // adjoint by moments: [S][kAdjMoments][mlen] correlations
+    int32_t mlen;              // T + 2 Rs
 };
 
 // Record gradients -> map gradients (depth-stencil adjoint).
@@ -237,6 +239,11 @@ constexpr int kSmoothMoments = 8;
 constexpr int kSmoothPoints = 2;
 bool smooth_moments_radius(int rs);
 hipError_t launch_smooth_moments(const SmoothArgs& a, int64_t n_blocks, size_t lds, hipStream_t st);
+// Adjoint by moments (the same radii): kAdjMoments correlation rows per scan
+// point, kAdjPatches patches per thread in the gather.
+constexpr int kAdjMoments = 9;
+constexpr int kAdjPatches = 4;
+hipError_t launch_adjoint_moments(const SmoothArgs& a, int64_t patch_blocks, size_t lds, hipStream_t st);
 hipError_t launch_adjoint(const SmoothArgs& a, int64_t patch_blocks, size_t lds, hipStream_t st);
 hipError_t launch_adjoint_reduce(const SmoothArgs& a, float* grad_rec, hipStream_t st);
 hipError_t launch_grad_maps(const GradMapArgs& g, hipStream_t st);

@@ -17,7 +17,11 @@
 //                (LDS rows of 64-bit fixed-point bins), a lane one patch;
 //                2 Rs + 1 LDS adds per pair, Gaussian samples by a
 //                three-exponential recurrence.
-// k_adjoint      gather: a lane owns one patch and loops over a range of scan
+// k_adj_moments, k_adjoint_mom   adjoint for support radii 12, 16, 20: the
+//                upstream gradient's correlations with the Gaussian's
+//                derivatives once per scan point, then per pair two series in
+//                the sub-bin offset.
+// k_adjoint      gather otherwise: a lane owns one patch and loops over a range of scan
 //                points whose upstream-gradient rows are staged in LDS; per
 //                pair G0 = sum g N(x), G1 = sum g (x / sigma^2) N(x) give
 //                dL/dw = G0 and dL/du = w G1; per-record partial gradients
@@ -259,6 +263,28 @@ __global__ void __launch_bounds__(kBlock) k_smooth(const SmoothArgs a)
 // the series cut after m = 7 is within 7e-8 (relative L2 over the support)
 // of the direct sum for every t.  Moments are signed 64-bit fixed point
 // (two's complement sums), increments |w (-t)^m| s <= 2^30.
+// Taps K_m(d) = N^(m)(d) / m! = N(d) (-1/sigma)^m He_m(d / sigma) / m!,
+// m < n_moments, |d| <= RS, into kt[m (2 RS + 1) + d + RS] (fp64, then fp32).
+template <int RS>
+__device__ __forceinline__ void moment_taps(const SmoothArgs& a, float* kt, int n_moments)
+{
+    constexpr int ND = 2 * RS + 1;
+    for (int i = threadIdx.x; i < n_moments * ND; i += blockDim.x) {
+        const int m = i / ND, d = i % ND - RS;
+        const double sig = (double)a.sigma, x = d / sig;
+        double h0 = 1.0, h1 = x;   // He_0, He_1
+        for (int n = 1; n < m; ++n) {
+            const double h2 = x * h1 - n * h0;
+            h0 = h1;
+            h1 = h2;
+        }
+        const double he = m == 0 ? 1.0 : h1;
+        double f = 1.0;
+        for (int n = 2; n <= m; ++n) f *= n;
+        kt[i] = (float)((double)a.norm * exp(-0.5 * x * x) * he * pow(-1.0 / sig, m) / f);
+    }
+}
+
 template <bool COS, int RS>
 __global__ void __launch_bounds__(kBlock) k_smooth_mom(const SmoothArgs a)
 {
@@ -285,20 +311,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_mom(const SmoothArgs a)
         so[c] = off + off;
         sg[c] = (float)(g * g);
     }
-    if (threadIdx.x < NM * ND) {
-        const int m = threadIdx.x / ND, d = (int)threadIdx.x % ND - RS;
-        const double sig = (double)a.sigma, x = d / sig;
-        double h0 = 1.0, h1 = x;   // He_0, He_1
-        for (int n = 1; n < m; ++n) {
-            const double h2 = x * h1 - n * h0;
-            h0 = h1;
-            h1 = h2;
-        }
-        const double he = m == 0 ? 1.0 : h1;
-        double f = 1.0;
-        for (int n = 2; n <= m; ++n) f *= n;
-        kt[threadIdx.x] = (float)((double)a.norm * exp(-0.5 * x * x) * he * pow(-1.0 / sig, m) / f);
-    }
+    moment_taps<RS>(a, kt, NM);
     float wx[NP];
 #pragma unroll
     for (int c = 0; c < NP; ++c) wx[c] = canon(a.rx, min(tx0 + c, a.rx.n - 1));
@@ -534,6 +547,143 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(const SmoothArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint by moments.  For a pair with bin k0 and t = f - 1/2 (as in
+// k_smooth_mom), G0 = sum_k g[k] N(x) and G1 = sum_k g[k] (x / sigma^2) N(x)
+// = -sum_k g[k] N'(x) over the support are the series
+//     G0 = sum_m (-t)^m C_m[k0],   G1 = -sum_m (-t)^m (m + 1) C_{m+1}[k0]
+// (m = 0..7) of the correlations C_m[k0] = sum_{|d|<=Rs} g[k0 + d] K_m(d),
+// K_m = N^(m) / m!.  k_adj_moments computes C_0..C_8 once per scan point
+// (bins k0 = -Rs .. T + Rs - 1, stored at k0 + Rs); k_adjoint_mom then needs
+// 9 LDS reads and two Horner sums per pair instead of 2 Rs + 1 taps.
+template <int RS>
+__global__ void __launch_bounds__(256) k_adj_moments(const SmoothArgs a)
+{
+    constexpr int ND = 2 * RS + 1, NM = kAdjMoments;
+    extern __shared__ __align__(16) unsigned char smem[];
+    float* kt = reinterpret_cast<float*>(smem);    // [NM][ND]
+    float* gl = kt + NM * ND;                      // g with 2 RS zeros on both sides
+    const int T = a.T, L = a.mlen, s = (int)blockIdx.x;
+    const float* g = a.grad_out + (size_t)s * T;
+    for (int i = threadIdx.x; i < T + 4 * RS; i += blockDim.x) {
+        const int k = i - 2 * RS;
+        gl[i] = (k >= 0 && k < T) ? g[k] : 0.f;
+    }
+    moment_taps<RS>(a, kt, NM);
+    __syncthreads();
+    float* out = a.moments + (size_t)s * NM * L;
+    for (int j = threadIdx.x; j < L; j += blockDim.x) {
+        // bin k0 = j - RS: C_m = sum_d g[k0 + d] K_m(d), g[k0 + d] = gl[j + d + RS]
+        float acc[NM];
+#pragma unroll
+        for (int m = 0; m < NM; ++m) acc[m] = 0.f;
+#pragma unroll
+        for (int dd = 0; dd < ND; ++dd) {
+            const float gv = gl[j + dd];
+#pragma unroll
+            for (int m = 0; m < NM; ++m) acc[m] = fmaf(gv, kt[m * ND + dd], acc[m]);
+        }
+#pragma unroll
+        for (int m = 0; m < NM; ++m) out[(size_t)m * L + j] = acc[m];
+    }
+}
+
+template <bool COS, int RS>
+__global__ void __launch_bounds__(kBlock) k_adjoint_mom(const SmoothArgs a)
+{
+    constexpr int NM = kAdjMoments, PPT = kAdjPatches;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int T = a.T, L = a.mlen, NR = a.rows;
+    float* rowbuf = reinterpret_cast<float*>(smem);                        // [NR][NM][L]
+    double* so = reinterpret_cast<double*>(smem + (((size_t)NR * NM * L * 4 + 15) & ~(size_t)15));
+    float* swx = reinterpret_cast<float*>(so + NR);
+    float* swy = swx + NR;
+    float* sg = swy + NR;
+    const int n_act = smooth_active(a);
+    const int split = (int)blockIdx.y;
+    const int S = a.rx.n * a.ry.n;
+    const int per = (S + a.n_split - 1) / a.n_split;
+    const int s0 = min(S, split * per), s1 = min(S, s0 + per);
+    float4 A[PPT], B[PPT];
+    bool live[PPT];
+    double gz[PPT], ga[PPT], gnx[PPT], gny[PPT], gnz[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+        const int p = ((int)blockIdx.x * PPT + i) * kBlock + (int)threadIdx.x;
+        live[i] = p < n_act;
+        A[i] = make_float4(0.f, 0.f, 1.f, 0.f);
+        B[i] = make_float4(0.f, 0.f, -1.f, 0.f);
+        if (live[i]) {
+            A[i] = a.patches[2 * (size_t)p];
+            B[i] = a.patches[2 * (size_t)p + 1];
+        }
+        gz[i] = ga[i] = gnx[i] = gny[i] = gnz[i] = 0.0;
+    }
+    for (int j0 = s0; j0 < s1; j0 += NR) {
+        const int nr = min(NR, s1 - j0);
+        __syncthreads();
+        // stage the correlation rows of scan points [j0, j0 + nr): contiguous
+        const float* src = a.moments + (size_t)j0 * NM * L;
+        if ((L & 3) == 0) {
+            const float4* s4 = reinterpret_cast<const float4*>(src);
+            float4* d4 = reinterpret_cast<float4*>(rowbuf);
+            for (int i = threadIdx.x; i < nr * NM * (L >> 2); i += kBlock) d4[i] = s4[i];
+        } else {
+            for (int i = threadIdx.x; i < nr * NM * L; i += kBlock) rowbuf[i] = src[i];
+        }
+        if (threadIdx.x < nr) {
+            const int h = j0 + threadIdx.x;
+            const float wx = canon(a.rx, h / a.ry.n), wy = canon(a.ry, h % a.ry.n);
+            double off, g;
+            device_leg(wx, wy, a.cx, a.cy, a.s, &off, &g);
+            so[threadIdx.x] = off + off;
+            swx[threadIdx.x] = wx;
+            swy[threadIdx.x] = wy;
+            sg[threadIdx.x] = (float)(g * g);
+        }
+        __syncthreads();
+        for (int jj = 0; jj < nr; ++jj) {
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) {
+                if (!live[i]) continue;
+                const PairS q = pair_smooth(A[i], B[i], swx[jj], swy[jj], so[jj], sg[jj], a.inv, COS, true);
+                const double k0d = floor(q.u);
+                if (k0d + RS < 0.0 || k0d - RS > (double)(T - 1)) continue;
+                const float mt = 0.5f - (float)(q.u - k0d);   // -t
+                const float* c = rowbuf + (size_t)jj * NM * L + ((int)k0d + RS);
+                float G0 = c[7 * L], G1 = 8.f * c[8 * L];
+#pragma unroll
+                for (int m = 6; m >= 0; --m) {
+                    G0 = fmaf(G0, mt, c[m * L]);
+                    G1 = fmaf(G1, mt, (float)(m + 1) * c[(m + 1) * L]);
+                }
+                G1 = -G1;
+                // dL/dw = G0, dL/du = w G1
+                const float dz = fmaf(G0, q.dw_dz, q.w * G1 * q.du_dz);
+                gz[i] += (double)dz;
+                ga[i] += (double)(G0 * q.w_a);
+                if (COS) {
+                    const float gn = G0 * q.dwn;
+                    gnx[i] += (double)(gn * (A[i].x - swx[jj]));
+                    gny[i] += (double)(gn * (A[i].y - swy[jj]));
+                    gnz[i] += (double)(gn * A[i].z);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+        const int p = ((int)blockIdx.x * PPT + i) * kBlock + (int)threadIdx.x;
+        if (!live[i]) continue;
+        double* o = a.partial + ((size_t)split * a.n_cap + p) * kAdjStride;
+        o[0] = gz[i];
+        o[1] = ga[i];
+        o[2] = gnx[i];
+        o[3] = gny[i];
+        o[4] = gnz[i];
+    }
+}
+
 // Sum the per-split partials in split order -> grad_rec [n_cap][8] floats
 // {0, 0, dL/dpz, dL/da, dL/dn_x, dL/dn_y, dL/dn_z, 0}; zeros past n_active.
 __global__ void __launch_bounds__(256) k_adjoint_reduce(const SmoothArgs a, float* grad_rec)
@@ -728,6 +878,38 @@ hipError_t launch_adjoint(const SmoothArgs& a, int64_t patch_blocks, size_t lds,
         return launch_adjoint_rs<0>(a, grid, lds, st);
     }
     return hipSuccess;
+}
+
+template <int RS>
+static hipError_t launch_adjoint_mom_rs(const SmoothArgs& a, int64_t patch_blocks, size_t lds, hipStream_t st)
+{
+    const int S = a.rx.n * a.ry.n;
+    const size_t lds_m = (size_t)(kAdjMoments * (2 * RS + 1) + a.T + 4 * RS) * 4;
+    hipError_t e = hipFuncSetAttribute((const void*)k_adj_moments<RS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds_m);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_moments<RS>, dim3((unsigned)S), dim3(256), lds_m, st, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const void* k = a.cosines ? (const void*)k_adjoint_mom<true, RS> : (const void*)k_adjoint_mom<false, RS>;
+    e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const dim3 grid((unsigned)patch_blocks, (unsigned)a.n_split);
+    if (a.cosines)
+        hipLaunchKernelGGL((k_adjoint_mom<true, RS>), grid, dim3(kBlock), lds, st, a);
+    else
+        hipLaunchKernelGGL((k_adjoint_mom<false, RS>), grid, dim3(kBlock), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_moments(const SmoothArgs& a, int64_t patch_blocks, size_t lds, hipStream_t st)
+{
+    if (patch_blocks <= 0) return hipSuccess;
+    if (patch_blocks > 0x7fffffff || a.n_split > 65535 || a.rows < 1 || a.mlen != a.T + 2 * a.Rs) return hipErrorInvalidValue;
+    if (a.Rs == 12) return launch_adjoint_mom_rs<12>(a, patch_blocks, lds, st);
+    if (a.Rs == 16) return launch_adjoint_mom_rs<16>(a, patch_blocks, lds, st);
+    if (a.Rs == 20) return launch_adjoint_mom_rs<20>(a, patch_blocks, lds, st);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_adjoint_reduce(const SmoothArgs& a, float* grad_rec, hipStream_t st)

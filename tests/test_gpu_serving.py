@@ -27,7 +27,10 @@ def test_same_result_alone_and_in_mix(mode):
     reqs = _mix()
     sizes = [serving.footprint_bytes(r) for r in reqs]
     budget = 3 * max(sizes)                      # admission must bind
+    # the first six wait at the start (so a batched tick forms whatever the
+    # GPU's speed), the rest arrive over time while ticks are in flight
     arrivals = serving.poisson_arrivals(len(reqs), 2000.0, seed=5)
+    arrivals[:6] = 0.0
     log(f"serving {mode}: {len(reqs)} requests, budget {budget} B")
     srv = serving.Server(budget_bytes=budget, max_batch=6, depth=2, mode=mode)
     res = srv.serve(reqs, arrivals, keep_outputs=True)
