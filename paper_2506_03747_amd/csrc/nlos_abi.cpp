@@ -642,7 +642,8 @@ size_t adjoint_lds(int rows, int T) { return (((size_t)rows * T * 4 + 15) & ~(si
 struct AdjPlan {
     int moments, rows, split, mlen;
     int64_t pbk;       // patch blocks of the gather
-    size_t c_bytes;    // correlation rows [S][kAdjMoments][mlen] fp32, 256-byte aligned
+    size_t c_bytes;    // kernel taps (256 bytes per 64 floats), then correlation rows [S][kAdjMoments][mlen] fp32
+    size_t taps_bytes; // the taps' share of c_bytes
     size_t lds;
 };
 
@@ -653,6 +654,7 @@ int adjoint_plan(const nlos_params* p, int32_t n_patches, int rs, AdjPlan* ap)
     ap->moments = 0;
     ap->mlen = 0;
     ap->c_bytes = 0;
+    ap->taps_bytes = 0;
     if (nlos::smooth_moments_radius(rs)) {
         const int L = T + 2 * rs;
         const int64_t per_row = (int64_t)nlos::kAdjMoments * L * 4;
@@ -667,7 +669,8 @@ int adjoint_plan(const nlos_params* p, int32_t n_patches, int rs, AdjPlan* ap)
             const int64_t pb = std::max<int64_t>(1, ap->pbk);
             int64_t sv = (2 * kTargetBlocks + pb - 1) / pb;
             ap->split = (int)std::max<int64_t>(1, std::min<int64_t>(sv, std::min<int64_t>(S, 65535)));
-            ap->c_bytes = ((size_t)S * nlos::kAdjMoments * L * 4 + 255) & ~(size_t)255;
+            ap->taps_bytes = ((size_t)nlos::kAdjMoments * (2 * rs + 1) * 4 + 255) & ~(size_t)255;
+            ap->c_bytes = ap->taps_bytes + (((size_t)S * nlos::kAdjMoments * L * 4 + 255) & ~(size_t)255);
             ap->lds = (((size_t)rows * nlos::kAdjMoments * L * 4 + 15) & ~(size_t)15) + (size_t)rows * 24;
             return NLOS_OK;
         }
@@ -1067,7 +1070,8 @@ int nlos_adjoint(const nlos_params* p, const float* patches, int32_t n_patches, 
     const int dev = device_check();
     if (dev != NLOS_OK) return dev;
     a.grad_out = grad_out;
-    a.moments = ap.moments ? static_cast<float*>(ws) : nullptr;
+    a.mtaps = ap.moments ? static_cast<float*>(ws) : nullptr;
+    a.moments = ap.moments ? reinterpret_cast<float*>(static_cast<char*>(ws) + ap.taps_bytes) : nullptr;
     a.mlen = ap.mlen;
     a.partial = reinterpret_cast<double*>(static_cast<char*>(ws) + ap.c_bytes);
     a.n_split = ap.split;

@@ -167,6 +167,7 @@ struct SmoothArgs {
     ChunkStat* stats;
     int32_t n_stats;
     float* moments;            // adjoint by moments: [S][kAdjMoments][mlen] correlations
+    float* mtaps;              // adjoint by moments: kernels K_m(d), [kAdjMoments][2 Rs + 1]
     int32_t mlen;              // T + 2 Rs
 };
 

@@ -557,34 +557,50 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(const SmoothArgs a)
 // (bins k0 = -Rs .. T + Rs - 1, stored at k0 + Rs); k_adjoint_mom then needs
 // 9 LDS reads and two Horner sums per pair instead of 2 Rs + 1 taps.
 template <int RS>
+__global__ void __launch_bounds__(256) k_adj_taps(const SmoothArgs a)
+{
+    moment_taps<RS>(a, a.mtaps, kAdjMoments);
+}
+
+// One workgroup per scan point; a thread produces V consecutive bins of all
+// nine rows from a register window of its gradient samples, the kernels K_m
+// read with wave-uniform addresses (scalar loads).
+template <int RS>
 __global__ void __launch_bounds__(256) k_adj_moments(const SmoothArgs a)
 {
-    constexpr int ND = 2 * RS + 1, NM = kAdjMoments;
+    constexpr int ND = 2 * RS + 1, NM = kAdjMoments, V = 5;
     extern __shared__ __align__(16) unsigned char smem[];
-    float* kt = reinterpret_cast<float*>(smem);    // [NM][ND]
-    float* gl = kt + NM * ND;                      // g with 2 RS zeros on both sides
+    float* gl = reinterpret_cast<float*>(smem);   // g with 2 RS zeros before, 2 RS + V after
     const int T = a.T, L = a.mlen, s = (int)blockIdx.x;
     const float* g = a.grad_out + (size_t)s * T;
-    for (int i = threadIdx.x; i < T + 4 * RS; i += blockDim.x) {
+    for (int i = threadIdx.x; i < T + 4 * RS + V; i += blockDim.x) {
         const int k = i - 2 * RS;
         gl[i] = (k >= 0 && k < T) ? g[k] : 0.f;
     }
-    moment_taps<RS>(a, kt, NM);
     __syncthreads();
+    const float* __restrict__ kt = a.mtaps;
     float* out = a.moments + (size_t)s * NM * L;
-    for (int j = threadIdx.x; j < L; j += blockDim.x) {
-        // bin k0 = j - RS: C_m = sum_d g[k0 + d] K_m(d), g[k0 + d] = gl[j + d + RS]
-        float acc[NM];
+    for (int j0 = (int)threadIdx.x * V; j0 < L; j0 += (int)blockDim.x * V) {
+        // bins k0 = j - RS, j = j0 .. j0 + V - 1: C_m = sum_d g[k0 + d] K_m(d),
+        // g[k0 + d] = gl[j + d + RS] = w[j - j0 + dd], dd = d + RS
+        float w[V + 2 * RS];
 #pragma unroll
-        for (int m = 0; m < NM; ++m) acc[m] = 0.f;
+        for (int q = 0; q < V + 2 * RS; ++q) w[q] = gl[j0 + q];
+#pragma unroll 1
+        for (int m = 0; m < NM; ++m) {
+            float acc[V];
 #pragma unroll
-        for (int dd = 0; dd < ND; ++dd) {
-            const float gv = gl[j + dd];
+            for (int v = 0; v < V; ++v) acc[v] = 0.f;
 #pragma unroll
-            for (int m = 0; m < NM; ++m) acc[m] = fmaf(gv, kt[m * ND + dd], acc[m]);
+            for (int dd = 0; dd < ND; ++dd) {
+                const float k = kt[m * ND + dd];
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[v] = fmaf(w[v + dd], k, acc[v]);
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                if (j0 + v < L) out[(size_t)m * L + j0 + v] = acc[v];
         }
-#pragma unroll
-        for (int m = 0; m < NM; ++m) out[(size_t)m * L + j] = acc[m];
     }
 }
 
@@ -884,9 +900,11 @@ template <int RS>
 static hipError_t launch_adjoint_mom_rs(const SmoothArgs& a, int64_t patch_blocks, size_t lds, hipStream_t st)
 {
     const int S = a.rx.n * a.ry.n;
-    const size_t lds_m = (size_t)(kAdjMoments * (2 * RS + 1) + a.T + 4 * RS) * 4;
-    hipError_t e = hipFuncSetAttribute((const void*)k_adj_moments<RS>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds_m);
+    hipLaunchKernelGGL(k_adj_taps<RS>, dim3(1), dim3(256), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds_m = (size_t)(a.T + 4 * RS + 8) * 4;
+    e = hipFuncSetAttribute((const void*)k_adj_moments<RS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_m);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_adj_moments<RS>, dim3((unsigned)S), dim3(256), lds_m, st, a);
     e = hipGetLastError();
