@@ -38,12 +38,15 @@ SCENES = [
     dict(seed=605, scan=(1, 1), patches=(9, 9), fwhm_ps=30.0),
     dict(seed=606, scan=(5, 6), patches=(12, 10), n_bins=97, bin_ps=30.0, fwhm_ps=45.0),  # T not a multiple of 4
 ]
-# support radii ceil(6 sigma) = 12, 16, 20, which the kernels run as
-# straight-line tap sequences (the scenes above have other radii: general loop)
+# support radii ceil(6 sigma) = 12, 16, 20: the forward and the adjoint by
+# moments (the scenes above have other radii: the general tap loops)
 RADII = [
     dict(seed=608, bin_ps=16.0, fwhm_ps=70.0),
     dict(seed=609, bin_ps=8.0, fwhm_ps=50.0, scan=(4, 5)),
     dict(seed=610, bin_ps=4.0, fwhm_ps=30.0, n_bins=1024, standoff_m=0.0),
+    # T = 2048: the forward's moment rows do not fit in LDS, so it takes the
+    # straight-line taps at radius 20; the adjoint stages two scan points
+    dict(seed=614, bin_ps=4.0, fwhm_ps=30.0, n_bins=2048, scan=(3, 2)),
 ]
 
 
