@@ -571,12 +571,13 @@ int smooth_plan(const nlos_params* p, int32_t n_patches, int rs, SmoothPlan* sp,
     sp->stride = T;
     if (nlos::smooth_moments_radius(rs)) {
         const int stride = (T + 2 * rs + 1) & ~1;
-        const int64_t rows = (int64_t)nlos::kSmoothPoints * nlos::kSmoothMoments;
+        const nlos::SmoothMomShape sh = nlos::smooth_mom_shape(rs);
+        const int64_t rows = (int64_t)sh.points * sh.moments;
         const size_t lds = (size_t)rows * stride * 8 + 2048;
         if (lds <= kLdsMax && rows * (T + 2 * rs) <= 24 * (int64_t)nlos::kBlock) {
             sp->moments = 1;
             sp->stride = stride;
-            sp->tx = nlos::kSmoothPoints;
+            sp->tx = sh.points;
             sp->ty = 1;
             sp->tiles = (int64_t)((p->relay.nx + sp->tx - 1) / sp->tx) * p->relay.ny;
             int64_t sv = 1;

@@ -235,9 +235,13 @@ hipError_t launch_debug(const DebugArgs& a, hipStream_t st);
 
 hipError_t launch_smooth(const SmoothArgs& a, int tx, int ty, int64_t n_blocks, size_t lds, hipStream_t st);
 // Smooth forward by moments of the sub-bin offset (support radii 12, 16, 20):
-// kSmoothPoints scan points per workgroup, kSmoothMoments LDS rows each.
-constexpr int kSmoothMoments = 8;
-constexpr int kSmoothPoints = 2;
+// scan points per workgroup and moment rows per point (the series is cut
+// after m = moments - 1: 7 at radius 12, 5 at 16 and 20, where sigma > 2.5
+// bins makes the terms fall faster).
+struct SmoothMomShape {
+    int points, moments;
+};
+constexpr SmoothMomShape smooth_mom_shape(int rs) { return rs == 12 ? SmoothMomShape{2, 8} : SmoothMomShape{3, 6}; }
 bool smooth_moments_radius(int rs);
 hipError_t launch_smooth_moments(const SmoothArgs& a, int64_t n_blocks, size_t lds, hipStream_t st);
 // Adjoint by moments (the same radii): kAdjMoments correlation rows per scan

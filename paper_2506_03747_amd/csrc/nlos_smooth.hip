@@ -255,14 +255,15 @@ __global__ void __launch_bounds__(kBlock) k_smooth(const SmoothArgs a)
 // Smooth forward by moments.  With t = f - 1/2 the pair's sub-bin offset
 // about the centre of its bin k0 = floor(u), its contribution w N(d + 1/2 - f)
 // to bin k0 + d is the Taylor series sum_m (-t)^m / m! w N^(m)(d).  A pair
-// therefore adds w (-t)^m to moment row m at bin k0 (kSmoothMoments rows, one
-// LDS add each instead of 2 Rs + 1), and the flush convolves each moment row
-// with K_m(d) = N^(m)(d) / m! over |d| <= Rs, the same support as the direct
-// sum.  N^(m)(d) = N(d) (-1/sigma)^m He_m(d / sigma) (He: probabilists'
-// Hermite polynomials).  With |t| <= 1/2 and sigma > 11/6 bins (Rs >= 12),
-// the series cut after m = 7 is within 7e-8 (relative L2 over the support)
-// of the direct sum for every t.  Moments are signed 64-bit fixed point
-// (two's complement sums), increments |w (-t)^m| s <= 2^30.
+// therefore adds w (-t)^m to moment row m at bin k0 (one LDS add per moment
+// instead of 2 Rs + 1), and the flush convolves each moment row with
+// K_m(d) = N^(m)(d) / m! over |d| <= Rs, the same support as the direct sum.
+// N^(m)(d) = N(d) (-1/sigma)^m He_m(d / sigma) (He: probabilists' Hermite
+// polynomials).  With |t| <= 1/2, the series cut after m = 7 (radius 12,
+// sigma > 11/6 bins) is within 7e-8 of the direct sum (relative L2 over the
+// support, every t), and cut after m = 5 (radii 16 and 20, sigma > 2.5 bins)
+// within 1.2e-6.  Moments are signed 64-bit fixed point (two's complement
+// sums), increments |w (-t)^m| s <= 2^30.
 // Taps K_m(d) = N^(m)(d) / m! = N(d) (-1/sigma)^m He_m(d / sigma) / m!,
 // m < n_moments, |d| <= RS, into kt[m (2 RS + 1) + d + RS] (fp64, then fp32).
 template <int RS>
@@ -288,7 +289,7 @@ __device__ __forceinline__ void moment_taps(const SmoothArgs& a, float* kt, int 
 template <bool COS, int RS>
 __global__ void __launch_bounds__(kBlock) k_smooth_mom(const SmoothArgs a)
 {
-    constexpr int NP = kSmoothPoints, NM = kSmoothMoments, NR = NP * NM, ND = 2 * RS + 1;
+    constexpr int NP = smooth_mom_shape(RS).points, NM = smooth_mom_shape(RS).moments, NR = NP * NM, ND = 2 * RS + 1;
     extern __shared__ __align__(16) unsigned char smem[];
     u64s* hist = reinterpret_cast<u64s*>(smem);   // row (point c, moment m) = c NM + m; bin k0 at k0 + RS
     double* so = reinterpret_cast<double*>(smem + (size_t)NR * a.stride * 8);
@@ -862,7 +863,8 @@ hipError_t launch_smooth_moments(const SmoothArgs& a, int64_t n_blocks, size_t l
     if (n_blocks <= 0) return hipSuccess;
     if (n_blocks > 0x7fffffff) return hipErrorInvalidValue;
     // the flush keeps at most 24 values per thread in registers
-    if ((int64_t)kSmoothPoints * kSmoothMoments * (a.T + 2 * a.Rs) > 24 * (int64_t)kBlock) return hipErrorInvalidValue;
+    const SmoothMomShape sh = smooth_mom_shape(a.Rs);
+    if ((int64_t)sh.points * sh.moments * (a.T + 2 * a.Rs) > 24 * (int64_t)kBlock) return hipErrorInvalidValue;
     if (a.stride < a.T + 2 * a.Rs) return hipErrorInvalidValue;
     if (a.Rs == 12) return launch_smooth_mom_rs<12>(a, n_blocks, lds, st);
     if (a.Rs == 16) return launch_smooth_mom_rs<16>(a, n_blocks, lds, st);
