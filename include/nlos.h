@@ -272,7 +272,8 @@ int nlos_forward_smooth(const nlos_params* p, const float* patches, int32_t n_pa
 /* Workspace of nlos_adjoint: per-record partial gradients (fp64) of each
  * range of scan points; for support radii ceil(6 sigma) of 12, 16 or 20 bins
  * it starts with the correlations of the upstream gradient rows with the
- * Gaussian's derivatives (fp32 [nx*ny][9][T + 2 radius]).  256-byte aligned. */
+ * Gaussian's derivatives (fp32 [nx*ny][n][T + 2 radius], n = 9 at radius 12,
+ * 7 at 16 and 20).  256-byte aligned. */
 int nlos_adjoint_workspace_bytes(const nlos_params* p, int32_t n_patches, size_t* bytes);
 
 /*
@@ -286,8 +287,8 @@ int nlos_adjoint_workspace_bytes(const nlos_params* p, int32_t n_patches, size_t
  * through w(z, n, a) and u(z).  The step of the support with floor(u) is
  * not differentiated (below the tail at 6 sigma).  For support radii of 12,
  * 16 or 20 bins both sums are evaluated as series in the sub-bin offset
- * (t = u - floor(u) - 1/2, terms up to t^7) of precomputed correlations of G
- * with the Gaussian's derivatives.  Deterministic: partial sums per scan
+ * (t = u - floor(u) - 1/2, terms up to t^7 at radius 12, t^5 at 16 and 20)
+ * of precomputed correlations of G with the Gaussian's derivatives.  Deterministic: partial sums per scan
  * range are added in a fixed order.
  */
 int nlos_adjoint(const nlos_params* p, const float* patches, int32_t n_patches, const int32_t* n_active,

@@ -643,7 +643,7 @@ size_t adjoint_lds(int rows, int T) { return (((size_t)rows * T * 4 + 15) & ~(si
 struct AdjPlan {
     int moments, rows, split, mlen;
     int64_t pbk;       // patch blocks of the gather
-    size_t c_bytes;    // kernel taps (256 bytes per 64 floats), then correlation rows [S][kAdjMoments][mlen] fp32
+    size_t c_bytes;    // kernel taps (256 bytes per 64 floats), then correlation rows [S][adj_moments][mlen] fp32
     size_t taps_bytes; // the taps' share of c_bytes
     size_t lds;
 };
@@ -658,9 +658,10 @@ int adjoint_plan(const nlos_params* p, int32_t n_patches, int rs, AdjPlan* ap)
     ap->taps_bytes = 0;
     if (nlos::smooth_moments_radius(rs)) {
         const int L = T + 2 * rs;
-        const int64_t per_row = (int64_t)nlos::kAdjMoments * L * 4;
-        const int64_t rows = std::min<int64_t>(4, ((int64_t)kLdsMax - 1024) / per_row);
-        const size_t lds_pre = (size_t)(nlos::kAdjMoments * (2 * rs + 1) + T + 4 * rs) * 4;
+        const int nm = nlos::adj_moments(rs);
+        const int64_t per_row = (int64_t)nm * L * 4;
+        const int64_t rows = std::min<int64_t>(5, ((int64_t)kLdsMax - 1024) / per_row);
+        const size_t lds_pre = (size_t)(T + 4 * rs + 8) * 4;
         if (rows >= 1 && lds_pre <= kLdsMax) {
             ap->moments = 1;
             ap->rows = (int)rows;
@@ -670,9 +671,9 @@ int adjoint_plan(const nlos_params* p, int32_t n_patches, int rs, AdjPlan* ap)
             const int64_t pb = std::max<int64_t>(1, ap->pbk);
             int64_t sv = (2 * kTargetBlocks + pb - 1) / pb;
             ap->split = (int)std::max<int64_t>(1, std::min<int64_t>(sv, std::min<int64_t>(S, 65535)));
-            ap->taps_bytes = ((size_t)nlos::kAdjMoments * (2 * rs + 1) * 4 + 255) & ~(size_t)255;
-            ap->c_bytes = ap->taps_bytes + (((size_t)S * nlos::kAdjMoments * L * 4 + 255) & ~(size_t)255);
-            ap->lds = (((size_t)rows * nlos::kAdjMoments * L * 4 + 15) & ~(size_t)15) + (size_t)rows * 24;
+            ap->taps_bytes = ((size_t)nm * (2 * rs + 1) * 4 + 255) & ~(size_t)255;
+            ap->c_bytes = ap->taps_bytes + (((size_t)S * nm * L * 4 + 255) & ~(size_t)255);
+            ap->lds = (((size_t)rows * nm * L * 4 + 15) & ~(size_t)15) + (size_t)rows * 24;
             return NLOS_OK;
         }
     }

@@ -166,8 +166,8 @@ struct SmoothArgs {
     int32_t cosines;
     ChunkStat* stats;
     int32_t n_stats;
-    float* moments;            // adjoint by moments: [S][kAdjMoments][mlen] correlations
-    float* mtaps;              // adjoint by moments: kernels K_m(d), [kAdjMoments][2 Rs + 1]
+    float* moments;            // adjoint by moments: [S][adj_moments(Rs)][mlen] correlations
+    float* mtaps;              // adjoint by moments: kernels K_m(d), [adj_moments(Rs)][2 Rs + 1]
     int32_t mlen;              // T + 2 Rs
 };
 
@@ -244,9 +244,12 @@ struct SmoothMomShape {
 constexpr SmoothMomShape smooth_mom_shape(int rs) { return rs == 12 ? SmoothMomShape{2, 8} : SmoothMomShape{3, 6}; }
 bool smooth_moments_radius(int rs);
 hipError_t launch_smooth_moments(const SmoothArgs& a, int64_t n_blocks, size_t lds, hipStream_t st);
-// Adjoint by moments (the same radii): kAdjMoments correlation rows per scan
+// Adjoint by moments (the same radii): adj_moments correlation rows per scan
 // point, kAdjPatches patches per thread in the gather.
-constexpr int kAdjMoments = 9;
+// Correlation rows per scan point: C_0 .. C_{n-1} give G0 to the power
+// n - 2 of the sub-bin offset and G1 to the same power; 9 at radius 12, 7 at
+// 16 and 20 (sigma > 2.5 bins).
+constexpr int adj_moments(int rs) { return rs == 12 ? 9 : 7; }
 constexpr int kAdjPatches = 4;
 hipError_t launch_adjoint_moments(const SmoothArgs& a, int64_t patch_blocks, size_t lds, hipStream_t st);
 hipError_t launch_adjoint(const SmoothArgs& a, int64_t patch_blocks, size_t lds, hipStream_t st);

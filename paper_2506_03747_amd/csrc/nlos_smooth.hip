@@ -553,14 +553,15 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(const SmoothArgs a)
 // k_smooth_mom), G0 = sum_k g[k] N(x) and G1 = sum_k g[k] (x / sigma^2) N(x)
 // = -sum_k g[k] N'(x) over the support are the series
 //     G0 = sum_m (-t)^m C_m[k0],   G1 = -sum_m (-t)^m (m + 1) C_{m+1}[k0]
-// (m = 0..7) of the correlations C_m[k0] = sum_{|d|<=Rs} g[k0 + d] K_m(d),
-// K_m = N^(m) / m!.  k_adj_moments computes C_0..C_8 once per scan point
-// (bins k0 = -Rs .. T + Rs - 1, stored at k0 + Rs); k_adjoint_mom then needs
-// 9 LDS reads and two Horner sums per pair instead of 2 Rs + 1 taps.
+// (m = 0 .. n - 2, n = adj_moments(Rs)) of the correlations
+// C_m[k0] = sum_{|d|<=Rs} g[k0 + d] K_m(d), K_m = N^(m) / m!.  k_adj_moments
+// computes C_0 .. C_{n-1} once per scan point (bins k0 = -Rs .. T + Rs - 1,
+// stored at k0 + Rs); k_adjoint_mom then needs n LDS reads and two Horner
+// sums per pair instead of 2 Rs + 1 taps.
 template <int RS>
 __global__ void __launch_bounds__(256) k_adj_taps(const SmoothArgs a)
 {
-    moment_taps<RS>(a, a.mtaps, kAdjMoments);
+    moment_taps<RS>(a, a.mtaps, adj_moments(RS));
 }
 
 // One workgroup per scan point; a thread produces V consecutive bins of all
@@ -569,7 +570,7 @@ __global__ void __launch_bounds__(256) k_adj_taps(const SmoothArgs a)
 template <int RS>
 __global__ void __launch_bounds__(256) k_adj_moments(const SmoothArgs a)
 {
-    constexpr int ND = 2 * RS + 1, NM = kAdjMoments, V = 5;
+    constexpr int ND = 2 * RS + 1, NM = adj_moments(RS), V = 5;
     extern __shared__ __align__(16) unsigned char smem[];
     float* gl = reinterpret_cast<float*>(smem);   // g with 2 RS zeros before, 2 RS + V after
     const int T = a.T, L = a.mlen, s = (int)blockIdx.x;
@@ -608,7 +609,7 @@ __global__ void __launch_bounds__(256) k_adj_moments(const SmoothArgs a)
 template <bool COS, int RS>
 __global__ void __launch_bounds__(kBlock) k_adjoint_mom(const SmoothArgs a)
 {
-    constexpr int NM = kAdjMoments, PPT = kAdjPatches;
+    constexpr int NM = adj_moments(RS), MT = NM - 2, PPT = kAdjPatches;
     extern __shared__ __align__(16) unsigned char smem[];
     const int T = a.T, L = a.mlen, NR = a.rows;
     float* rowbuf = reinterpret_cast<float*>(smem);                        // [NR][NM][L]
@@ -668,9 +669,9 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_mom(const SmoothArgs a)
                 if (k0d + RS < 0.0 || k0d - RS > (double)(T - 1)) continue;
                 const float mt = 0.5f - (float)(q.u - k0d);   // -t
                 const float* c = rowbuf + (size_t)jj * NM * L + ((int)k0d + RS);
-                float G0 = c[7 * L], G1 = 8.f * c[8 * L];
+                float G0 = c[MT * L], G1 = (float)(MT + 1) * c[(MT + 1) * L];
 #pragma unroll
-                for (int m = 6; m >= 0; --m) {
+                for (int m = MT - 1; m >= 0; --m) {
                     G0 = fmaf(G0, mt, c[m * L]);
                     G1 = fmaf(G1, mt, (float)(m + 1) * c[(m + 1) * L]);
                 }

@@ -77,18 +77,24 @@ def test_moment_series_shifted_histogram():
     assert np.linalg.norm(series - direct) <= 1e-7 * np.linalg.norm(direct)
 
 
-@pytest.mark.parametrize("fwhm_ps,bin_ps", [(70.0, 16.0), (50.0, 8.0), (30.0, 4.0)])
+# correlation rows per radius as the adjoint takes them
+ADJ_ROWS = {12: 9, 16: 7, 20: 7}
+
+
+@pytest.mark.parametrize("fwhm_ps,bin_ps", [(70.0, 16.0), (43.19, 10.0), (50.0, 8.0), (47.12, 8.0), (30.0, 4.0)])
 def test_adjoint_series_matches_direct_sums(fwhm_ps, bin_ps):
     """The adjoint's two sums over the support, G0 = sum_k g N(x) and
     G1 = sum_k g (x / sigma^2) N(x), x = k + 1/2 - u, from the correlations
-    C_m[k0] = sum_d g[k0 + d] K_m(d) (m <= 8): G0 = sum_{m<=7} (-t)^m C_m,
-    G1 = -sum_{m<=7} (-t)^m (m + 1) C_{m+1}."""
+    C_m[k0] = sum_d g[k0 + d] K_m(d), m < n: G0 = sum_{m<=n-2} (-t)^m C_m,
+    G1 = -sum_{m<=n-2} (-t)^m (m + 1) C_{m+1} (n = 9 at radius 12, 7 at 16
+    and 20)."""
     sigma = fwhm_ps / (2 * math.sqrt(2 * math.log(2))) / bin_ps
     rs = math.ceil(6 * sigma)
-    d, K = moment_kernels(sigma, rs, n_moments=9)
+    n = ADJ_ROWS[rs]
+    d, K = moment_kernels(sigma, rs, n_moments=n)
     rng = np.random.default_rng(11)
     g = rng.standard_normal(2 * rs + 1)              # upstream gradient over the support of one pair
-    C = [float(np.dot(g, K[m])) for m in range(9)]
+    C = [float(np.dot(g, K[m])) for m in range(n)]
     worst0 = worst1 = 0.0
     for f in np.linspace(0.0, 1.0, 51, endpoint=False):
         t = f - 0.5
@@ -96,11 +102,11 @@ def test_adjoint_series_matches_direct_sums(fwhm_ps, bin_ps):
         N = np.exp(-0.5 * (x / sigma) ** 2) / (sigma * math.sqrt(2 * math.pi))
         G0 = float(np.dot(g, N))
         G1 = float(np.dot(g, x / sigma ** 2 * N))
-        s0 = sum((-t) ** m * C[m] for m in range(8))
-        s1 = -sum((-t) ** m * (m + 1) * C[m + 1] for m in range(8))
+        s0 = sum((-t) ** m * C[m] for m in range(n - 1))
+        s1 = -sum((-t) ** m * (m + 1) * C[m + 1] for m in range(n - 1))
         scale0 = float(np.linalg.norm(g) * np.linalg.norm(N))
         scale1 = float(np.linalg.norm(g) * np.linalg.norm(x / sigma ** 2 * N))
         worst0 = max(worst0, abs(s0 - G0) / scale0)
         worst1 = max(worst1, abs(s1 - G1) / scale1)
-    assert worst0 <= 1e-7
-    assert worst1 <= 1e-6
+    assert worst0 <= 1e-6
+    assert worst1 <= 3e-6
