@@ -39,7 +39,7 @@ FP32_FMA_CEILING_TFLOPS = 78.6
 TRAFFIC_BYTES = (4324.5 * 2.0 + 16384.0 * 1.0) * 1024
 TRAFFIC_SOURCES = ("paper_2506_03747_amd/csrc/nlos_forward.hip", "paper_2506_03747_amd/csrc/nlos_device.h",
                    "paper_2506_03747_amd/csrc/nlos_internal.h")
-TRAFFIC_HASH = "d8a782c9f6d126e1"
+TRAFFIC_HASH = "3a7095435951eb49"
 
 
 def traffic_for_sources():
