@@ -47,6 +47,11 @@ RADII = [
     # T = 2048: the forward's moment rows do not fit in LDS, so it takes the
     # straight-line taps at radius 20; the adjoint stages two scan points
     dict(seed=614, bin_ps=4.0, fwhm_ps=30.0, n_bins=2048, scan=(3, 2)),
+    # the moment kernels without cosines, with a stand-off, and with the
+    # patches split over workgroups (few scan points, 4096 patches)
+    dict(seed=615, bin_ps=8.0, fwhm_ps=50.0, cosines=False),
+    dict(seed=616, bin_ps=16.0, fwhm_ps=70.0, standoff_m=0.7, n_bins=768),
+    dict(seed=617, bin_ps=8.0, fwhm_ps=50.0, scan=(3, 2), patches=(64, 64)),
 ]
 
 
