@@ -866,7 +866,9 @@ int nlos_simulate_workspace_bytes(const nlos_params* p, const nlos_grid* g, size
     const int64_t by = (g->ny + nlos::kBlockPx - 1) / nlos::kBlockPx;
     const int64_t blocks = ((int64_t)nlos::kBlockPx * nlos::kBlockPx * bx * by + nlos::kGeomBlock - 1) / nlos::kGeomBlock;
     const int64_t tiles = blocks * (nlos::kGeomBlock / (nlos::kBlockPx * nlos::kBlockPx));
-    *bytes = align_up(geo, 256) + std::max(fwd, (size_t)tiles * sizeof(nlos::ChunkStat));
+    // then the records' pair-loop constants, 32 bytes per record
+    *bytes = align_up(geo, 256) + align_up(std::max(fwd, (size_t)tiles * sizeof(nlos::ChunkStat)), 256) +
+             (size_t)g->nx * g->ny * 32;
     return NLOS_OK;
 }
 
@@ -901,6 +903,14 @@ int nlos_simulate(const nlos_params* p, const nlos_grid* g, const float* depth, 
     a.n_stats = ga.n_blocks * (nlos::kGeomBlock / (nlos::kBlockPx * nlos::kBlockPx));
     ga.stats = a.stats;
     ga.n_stats = a.n_stats;
+    // the scatter also writes each record's pair-loop constants (scaled as
+    // the pair loop scales: by 2 / (c dt) confocal, 1 / (c dt) otherwise)
+    size_t fwd = 0;
+    nlos_forward_workspace_bytes(p, n_patches, &fwd);
+    const size_t stats_b = std::max(fwd, (size_t)a.n_stats * sizeof(nlos::ChunkStat));
+    ga.prep = reinterpret_cast<float4*>(w + align_up(geo, 256) + align_up(stats_b, 256));
+    ga.prep_sig = is_confocal(p) ? a.inv2_f : a.inv_f;
+    a.prep = ga.prep;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = nlos::launch_geometry(ga, st);
     if (e != hipSuccess) return hip_fail(e);

@@ -813,11 +813,16 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
     if (lane == 0) chunk_id = (int)atomicAdd(L.next, 2u);
     chunk_id = __builtin_amdgcn_readfirstlane(chunk_id);
     int next_id = chunk_id + 1;
+    // records as written by the geometry, or (prep) their pair-loop
+    // constants, which the one-call path writes beside them
+    const bool prep = a.prep != nullptr;
+    const float4* src = prep ? a.prep : a.patches;
+    const float dummy_px = a.dummy_x * sig;
     float4 An = make_float4(0.f, 0.f, 0.f, 0.f), Bn = An;
     if (pb + chunk_id * 64 < pe) {
         const int pl = min(pb + chunk_id * 64 + lane, pe - 1);
-        An = load4(a.patches, 2 * (size_t)pl);
-        Bn = load3(a.patches, 2 * (size_t)pl + 1);
+        An = load4(src, 2 * (size_t)pl);
+        Bn = load3(src, 2 * (size_t)pl + 1);
     }
     for (;;) {
         const int base = pb + chunk_id * 64;
@@ -825,16 +830,29 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
         // lanes past the range read the last record, moved to dummy_x: every
         // arrival of that position lies past the window
         const int p = base + lane;
-        float4 A = An;
-        if (p >= pe) A.x = a.dummy_x;
-        const PatchC pc = patch_consts_scaled(A, Bn, COS, sig);
-        const float aw = A.w;
+        PatchC pc;
+        float aw;
+        if (prep) {
+            pc.px = p >= pe ? dummy_px : An.x;
+            pc.py = An.y;
+            pc.pz2 = An.z;
+            pc.ap = An.w;
+            pc.mnxs = Bn.x;
+            pc.mnys = Bn.y;
+            pc.c0s = Bn.z;
+            aw = An.w;
+        } else {
+            float4 A = An;
+            if (p >= pe) A.x = a.dummy_x;
+            pc = patch_consts_scaled(A, Bn, COS, sig);
+            aw = A.w;
+        }
         // records of the next chunk, into the registers the current ones
         // have just left (past the range: the last record, never used)
         {
             const int pl = min(pb + next_id * 64 + lane, pe - 1);
-            An = load4(a.patches, 2 * (size_t)pl);
-            Bn = load3(a.patches, 2 * (size_t)pl + 1);
+            An = load4(src, 2 * (size_t)pl);
+            Bn = load3(src, 2 * (size_t)pl + 1);
         }
         int claim = 0;
         if (lane == 0) claim = (int)atomicAdd(L.next, 1u);

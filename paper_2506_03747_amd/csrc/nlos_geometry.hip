@@ -159,8 +159,16 @@ __device__ __forceinline__ void scatter_body(const GeomArgs& a, int blk)
         const float len = sqrtf(1.f + gx * gx + gy * gy);
         const float area = a.hx * a.hy * (a.cosines ? len : 1.f);
         A = make_float4(canon(a.ax, ix), canon(a.ay, iy), z, rho * area);
+        const float4 B = make_float4(gx / len, gy / len, -1.f / len, __int_as_float((int)idx));
         a.patches[2 * (int64_t)off] = A;
-        a.patches[2 * (int64_t)off + 1] = make_float4(gx / len, gy / len, -1.f / len, __int_as_float((int)idx));
+        a.patches[2 * (int64_t)off + 1] = B;
+        if (a.prep) {
+            // the constants the pair loop derives from this record, by the
+            // same function, so that it need not derive them per chunk
+            const PatchC pc = patch_consts_scaled(A, B, a.cosines != 0, a.prep_sig);
+            a.prep[2 * (int64_t)off] = make_float4(pc.px, pc.py, pc.pz2, pc.ap);
+            a.prep[2 * (int64_t)off + 1] = make_float4(pc.mnxs, pc.mnys, pc.c0s, 0.f);
+        }
     }
     if (!a.stats) return;   // uniform across the block
 

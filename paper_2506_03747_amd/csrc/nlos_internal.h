@@ -47,6 +47,8 @@ struct GeomArgs {
     int64_t n_enum;        // 256 * bx * by
     int32_t n_blocks;      // ceil(n_enum / kGeomBlock)
     int32_t cosines;
+    float4* prep;          // nullable: [n][2] the pair loop's per-record constants
+    float prep_sig;        // the pair loop's bins per metre (its scale of coordinates)
 };
 constexpr int kGeomBlock = 1024;
 
@@ -95,6 +97,7 @@ __device__ __forceinline__ StatF load_stat(const ChunkStat* st, int i)
 // Arguments of the pair kernels (confocal and non-confocal).
 struct FwdArgs {
     const float4* patches;
+    const float4* prep;        // nullable: the records' pair-loop constants (PatchC), same order
     const int32_t* n_active;   // nullable
     int32_t n_cap;
     float* out;
