@@ -261,7 +261,12 @@ int nlos_forward_batched(const nlos_request* reqs, int32_t n, void* table, size_
  * Rs = ceil(6 sigma), 0 <= k < T, with w and u exactly as in nlos_forward.
  * Arrivals outside the window still reach in-window bins within Rs.
  * Requires fwhm_ps > 0 and sigma * 6 <= 1024 bins; one T-bin histogram of
- * 64-bit bins must fit in LDS (T <= ~20000).
+ * 64-bit bins must fit in LDS (T <= ~20000).  For Rs of 12, 16 or 20 bins
+ * (when the rows fit in LDS) the Gaussian samples are taken as a series in
+ * the sub-bin offset t = u - floor(u) - 1/2: each pair adds w (-t)^m,
+ * m <= 7 (Rs = 12) or m <= 5 (Rs = 16, 20), and the rows are convolved with
+ * N^(m) / m!; the series is within 7e-8 resp. 1.2e-6 (relative L2 over the
+ * support) of the samples.
  */
 int nlos_forward_smooth_workspace_bytes(const nlos_params* p, int32_t n_patches, size_t* bytes);
 
