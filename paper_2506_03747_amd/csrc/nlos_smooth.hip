@@ -264,6 +264,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth(const SmoothArgs a)
 // support, every t), and cut after m = 5 (radii 16 and 20, sigma > 2.5 bins)
 // within 1.2e-6.  Moments are signed 64-bit fixed point (two's complement
 // sums), increments |w (-t)^m| s <= 2^30.
+
 // Taps K_m(d) = N^(m)(d) / m! = N(d) (-1/sigma)^m He_m(d / sigma) / m!,
 // m < n_moments, |d| <= RS, into kt[m (2 RS + 1) + d + RS] (fp64, then fp32).
 template <int RS>
