@@ -644,9 +644,23 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_mom(const SmoothArgs a)
         // stage the correlation rows of scan points [j0, j0 + nr): contiguous
         const float* src = a.moments + (size_t)j0 * NM * L;
         if ((L & 3) == 0) {
+            // four loads in flight per thread before their LDS stores (a load
+            // past the end rereads the last element; its store is skipped)
             const float4* s4 = reinterpret_cast<const float4*>(src);
             float4* d4 = reinterpret_cast<float4*>(rowbuf);
-            for (int i = threadIdx.x; i < nr * NM * (L >> 2); i += kBlock) d4[i] = s4[i];
+            const int n4 = nr * NM * (L >> 2);
+            for (int i0 = threadIdx.x; i0 < n4; i0 += 4 * kBlock) {
+                const int last = n4 - 1;
+                const float4 v0 = s4[min(i0, last)];
+                const float4 v1 = s4[min(i0 + kBlock, last)];
+                const float4 v2 = s4[min(i0 + 2 * kBlock, last)];
+                const float4 v3 = s4[min(i0 + 3 * kBlock, last)];
+                __builtin_amdgcn_sched_barrier(0);
+                d4[i0] = v0;
+                if (i0 + kBlock < n4) d4[i0 + kBlock] = v1;
+                if (i0 + 2 * kBlock < n4) d4[i0 + 2 * kBlock] = v2;
+                if (i0 + 3 * kBlock < n4) d4[i0 + 3 * kBlock] = v3;
+            }
         } else {
             for (int i = threadIdx.x; i < nr * NM * L; i += kBlock) rowbuf[i] = src[i];
         }
