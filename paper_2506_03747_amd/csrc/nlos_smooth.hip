@@ -565,24 +565,15 @@ __global__ void __launch_bounds__(256) k_adj_taps(const SmoothArgs a)
     moment_taps<RS>(a, a.mtaps, adj_moments(RS));
 }
 
-// One workgroup per scan point; a thread produces V consecutive bins of all
-// nine rows from a register window of its gradient samples, the kernels K_m
-// read with wave-uniform addresses (scalar loads).
-template <int RS>
-__global__ void __launch_bounds__(256) k_adj_moments(const SmoothArgs a)
+// Rows of one scan point: a thread produces V consecutive bins of every row
+// from a register window of its gradient samples (gl: g with 2 RS zeros
+// before and 2 RS + 5 after), the kernels K_m read with wave-uniform
+// addresses (scalar loads).  VEC (V = 4, L a multiple of 4): the V bins go
+// out as one aligned 16-byte store, so a wavefront writes 1 KB contiguous.
+template <int RS, int V, bool VEC>
+__device__ __forceinline__ void adj_moment_rows(const float* gl, const float* __restrict__ kt, float* out, int L)
 {
-    constexpr int ND = 2 * RS + 1, NM = adj_moments(RS), V = 5;
-    extern __shared__ __align__(16) unsigned char smem[];
-    float* gl = reinterpret_cast<float*>(smem);   // g with 2 RS zeros before, 2 RS + V after
-    const int T = a.T, L = a.mlen, s = (int)blockIdx.x;
-    const float* g = a.grad_out + (size_t)s * T;
-    for (int i = threadIdx.x; i < T + 4 * RS + V; i += blockDim.x) {
-        const int k = i - 2 * RS;
-        gl[i] = (k >= 0 && k < T) ? g[k] : 0.f;
-    }
-    __syncthreads();
-    const float* __restrict__ kt = a.mtaps;
-    float* out = a.moments + (size_t)s * NM * L;
+    constexpr int ND = 2 * RS + 1, NM = adj_moments(RS);
     for (int j0 = (int)threadIdx.x * V; j0 < L; j0 += (int)blockDim.x * V) {
         // bins k0 = j - RS, j = j0 .. j0 + V - 1: C_m = sum_d g[k0 + d] K_m(d),
         // g[k0 + d] = gl[j + d + RS] = w[j - j0 + dd], dd = d + RS
@@ -600,11 +591,40 @@ __global__ void __launch_bounds__(256) k_adj_moments(const SmoothArgs a)
 #pragma unroll
                 for (int v = 0; v < V; ++v) acc[v] = fmaf(w[v + dd], k, acc[v]);
             }
+            if constexpr (VEC) {
+                // j0 and L are multiples of 4, so j0 + 3 < L
+                *reinterpret_cast<float4*>(out + (size_t)m * L + j0) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+            } else {
 #pragma unroll
-            for (int v = 0; v < V; ++v)
-                if (j0 + v < L) out[(size_t)m * L + j0 + v] = acc[v];
+                for (int v = 0; v < V; ++v)
+                    if (j0 + v < L) out[(size_t)m * L + j0 + v] = acc[v];
+            }
         }
     }
+}
+
+// One workgroup per scan point: its upstream-gradient row staged in LDS,
+// then every correlation row of that point.  The launch gives it one thread
+// per V bins of a row (whole wavefronts, at most 1024), so no second pass
+// runs with a few lanes.
+template <int RS>
+__global__ void __launch_bounds__(1024) k_adj_moments(const SmoothArgs a)
+{
+    constexpr int NM = adj_moments(RS);
+    extern __shared__ __align__(16) unsigned char smem[];
+    float* gl = reinterpret_cast<float*>(smem);   // g with 2 RS zeros before, 2 RS + 5 after
+    const int T = a.T, L = a.mlen, s = (int)blockIdx.x;
+    const float* g = a.grad_out + (size_t)s * T;
+    for (int i = threadIdx.x; i < T + 4 * RS + 5; i += blockDim.x) {
+        const int k = i - 2 * RS;
+        gl[i] = (k >= 0 && k < T) ? g[k] : 0.f;
+    }
+    __syncthreads();
+    float* out = a.moments + (size_t)s * NM * L;
+    if ((L & 3) == 0)
+        adj_moment_rows<RS, 4, true>(gl, a.mtaps, out, L);
+    else
+        adj_moment_rows<RS, 5, false>(gl, a.mtaps, out, L);
 }
 
 template <bool COS, int RS>
@@ -924,7 +944,10 @@ static hipError_t launch_adjoint_mom_rs(const SmoothArgs& a, int64_t patch_block
     const size_t lds_m = (size_t)(a.T + 4 * RS + 8) * 4;
     e = hipFuncSetAttribute((const void*)k_adj_moments<RS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_m);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_adj_moments<RS>, dim3((unsigned)S), dim3(256), lds_m, st, a);
+    const int per_thread = (a.mlen & 3) == 0 ? 4 : 5;   // bins per thread in k_adj_moments
+    const int need = ((a.mlen + per_thread - 1) / per_thread + 63) / 64 * 64;
+    const int threads = need < 1024 ? need : 1024;
+    hipLaunchKernelGGL(k_adj_moments<RS>, dim3((unsigned)S), dim3((unsigned)threads), lds_m, st, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const void* k = a.cosines ? (const void*)k_adjoint_mom<true, RS> : (const void*)k_adjoint_mom<false, RS>;
