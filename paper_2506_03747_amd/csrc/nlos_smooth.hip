@@ -567,8 +567,8 @@ __global__ void __launch_bounds__(256) k_adj_taps(const SmoothArgs a)
 
 // Rows of one scan point: a thread produces V consecutive bins of every row
 // from a register window of its gradient samples (gl: g with 2 RS zeros
-// before and 2 RS + 5 after), the kernels K_m read with wave-uniform
-// addresses (scalar loads).  VEC (V = 4, L a multiple of 4): the V bins go
+// before and 2 RS + 5 after), the kernels K_m read from LDS at wave-uniform
+// addresses.  VEC (V = 4, L a multiple of 4): the V bins go
 // out as one aligned 16-byte store, so a wavefront writes 1 KB contiguous.
 template <int RS, int V, bool VEC>
 __device__ __forceinline__ void adj_moment_rows(const float* gl, const float* __restrict__ kt, float* out, int L)
@@ -610,10 +610,14 @@ __device__ __forceinline__ void adj_moment_rows(const float* gl, const float* __
 template <int RS>
 __global__ void __launch_bounds__(1024) k_adj_moments(const SmoothArgs a)
 {
-    constexpr int NM = adj_moments(RS);
+    constexpr int NM = adj_moments(RS), ND = 2 * RS + 1;
     extern __shared__ __align__(16) unsigned char smem[];
     float* gl = reinterpret_cast<float*>(smem);   // g with 2 RS zeros before, 2 RS + 5 after
     const int T = a.T, L = a.mlen, s = (int)blockIdx.x;
+    // the kernels K_m copied next to it: LDS broadcasts instead of a vector
+    // load of the table per moment
+    float* kl = gl + ((T + 4 * RS + 8 + 3) & ~3);
+    for (int i = threadIdx.x; i < NM * ND; i += blockDim.x) kl[i] = a.mtaps[i];
     const float* g = a.grad_out + (size_t)s * T;
     for (int i = threadIdx.x; i < T + 4 * RS + 5; i += blockDim.x) {
         const int k = i - 2 * RS;
@@ -622,9 +626,9 @@ __global__ void __launch_bounds__(1024) k_adj_moments(const SmoothArgs a)
     __syncthreads();
     float* out = a.moments + (size_t)s * NM * L;
     if ((L & 3) == 0)
-        adj_moment_rows<RS, 4, true>(gl, a.mtaps, out, L);
+        adj_moment_rows<RS, 4, true>(gl, kl, out, L);
     else
-        adj_moment_rows<RS, 5, false>(gl, a.mtaps, out, L);
+        adj_moment_rows<RS, 5, false>(gl, kl, out, L);
 }
 
 template <bool COS, int RS>
@@ -941,7 +945,8 @@ static hipError_t launch_adjoint_mom_rs(const SmoothArgs& a, int64_t patch_block
     hipLaunchKernelGGL(k_adj_taps<RS>, dim3(1), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t lds_m = (size_t)(a.T + 4 * RS + 8) * 4;
+    // gradient row (T + 4 RS + 8 floats, rounded to 16 bytes), then the taps
+    const size_t lds_m = (size_t)((a.T + 4 * RS + 8 + 3) & ~3) * 4 + (size_t)adj_moments(RS) * (2 * RS + 1) * 4;
     e = hipFuncSetAttribute((const void*)k_adj_moments<RS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_m);
     if (e != hipSuccess) return e;
     const int per_thread = (a.mlen & 3) == 0 ? 4 : 5;   // bins per thread in k_adj_moments
