@@ -661,7 +661,8 @@ int adjoint_plan(const nlos_params* p, int32_t n_patches, int rs, AdjPlan* ap)
         const int nm = nlos::adj_moments(rs);
         const int64_t per_row = (int64_t)nm * L * 4;
         const int64_t rows = std::min<int64_t>(5, ((int64_t)kLdsMax - 1024) / per_row);
-        const size_t lds_pre = (size_t)(T + 4 * rs + 8) * 4;
+        // correlation pass: gradient row (rounded to 16 bytes), then the taps
+        const size_t lds_pre = (size_t)((T + 4 * rs + 8 + 3) & ~3) * 4 + (size_t)nm * (2 * rs + 1) * 4;
         if (rows >= 1 && lds_pre <= kLdsMax) {
             ap->moments = 1;
             ap->rows = (int)rows;
