@@ -67,7 +67,7 @@
 extern "C" {
 #endif
 
-#define NLOS_ABI_VERSION 1
+#define NLOS_ABI_VERSION 2
 
 #define NLOS_OK 0
 #define NLOS_EINVAL (-1)
@@ -169,6 +169,16 @@ int nlos_forward_workspace_bytes(const nlos_params* p, int32_t n_patches, size_t
  *              nlos_forward_workspace_bytes (may be NULL when that size is 0);
  *              overwritten by the call, so calls that share a workspace must be
  *              ordered on one stream.
+ * Precision: each pair's weight is found in fp32 and accumulated in 64-bit
+ * fixed point: it adds round(w * s_u), s_u = 2^31 / W_u, where the unit u
+ * (the group of histograms of nlos_get_plan) has the bound
+ *   W_u = max over the summaries of 256 consecutive records of
+ *         a_max / ((d_l^2 + z_min^2) (d_d^2 + z_min^2)),
+ * d_l, d_d the lateral distances from the summary's bounding box to the
+ * unit's laser and detector rectangles.  A pair's rounding is therefore at
+ * most g_l g_d W_u / 2^32; the fp32 weight is within a few ulp of its fp64
+ * value except where a patch cosine cancels (grazing patches), where the
+ * error is that of the fp32 record normals.
  */
 int nlos_forward(const nlos_params* p, const float* patches, int32_t n_patches,
                  const int32_t* n_active, float* out, void* ws, size_t ws_bytes, void* stream);
@@ -176,20 +186,31 @@ int nlos_forward(const nlos_params* p, const float* patches, int32_t n_patches,
 /*
  * The whole path in one call: nlos_patches_from_depth for the depth map on
  * grid g (flags = p->flags) followed by nlos_forward over its records, with
- * the record summaries (one per 16x16-pixel tile of the map) built while the
- * records are written (no separate pass).  patches [g.nx*g.ny][8] and
- * n_active are written as by nlos_patches_from_depth, bit for bit; out as by
- * nlos_forward, with the same bins and values equal to rounding (the
- * summaries, and so the fixed-point scales, differ).  ws: at least
- * nlos_simulate_workspace_bytes, 256-byte aligned.  forward_mark: a
- * hipEvent_t recorded on the stream right before the pair kernel (for timing
- * it), or NULL.
+ * the record summaries built while the records are written (no separate
+ * pass).  patches [g.nx*g.ny][8] and n_active are written as by
+ * nlos_patches_from_depth, bit for bit; the summaries cover the same records
+ * as nlos_forward's (256 consecutive records each), so the fixed-point scales
+ * are the same and out equals nlos_forward's bit for bit, except where
+ * patches are split over workgroups (nlos_get_plan n_split > 1: partial
+ * histograms are then added with float atomics, in no fixed order).
+ * ws: at least nlos_simulate_workspace_bytes, 256-byte aligned.
+ * probe: NULL, or instrumentation of the call (host pointer, read during the
+ * call only).
  */
+typedef struct nlos_probe {
+    void* forward_mark;                 /* hipEvent_t recorded on the stream right before
+                                           the pair kernel (to time it), or NULL */
+    unsigned long long* evaluated_pairs; /* device uint64, 8-byte aligned, or NULL: the pair
+                                           kernel adds the number of (histogram, patch) pairs
+                                           it evaluated; the rest were culled as arriving
+                                           past the window (the caller zeroes it) */
+} nlos_probe;
+
 int nlos_simulate_workspace_bytes(const nlos_params* p, const nlos_grid* g, size_t* bytes);
 
 int nlos_simulate(const nlos_params* p, const nlos_grid* g, const float* depth, const float* albedo,
                   const uint8_t* mask, float* patches, int32_t* n_active, float* out, void* ws, size_t ws_bytes,
-                  void* forward_mark, void* stream);
+                  const nlos_probe* probe, void* stream);
 
 /*
  * Batched calls: many independent scenes (uneven sizes, time windows, bin

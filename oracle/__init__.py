@@ -86,6 +86,9 @@ def _bind(lib):
     lib.oracle_smooth_grad.restype = C.c_int32
     lib.oracle_adjoint_records.argtypes = [C.POINTER(Params), dp, C.c_int32, dp, C.c_void_p, C.c_int32, dp]
     lib.oracle_adjoint_records.restype = C.c_int32
+    lib.oracle_forward_error_model.argtypes = [C.POINTER(Params), dp, C.c_int32, C.c_void_p, C.c_int32, C.c_double,
+                                               C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.oracle_forward_error_model.restype = C.c_int32
     u64p = C.POINTER(C.c_uint64)
     lib.oracle_philox4x64.argtypes = [u64p, u64p, u64p]
     lib.oracle_nx_exp.argtypes = [C.c_double]
@@ -197,6 +200,40 @@ def forward(scene, rec: np.ndarray | None = None, subset=None, want_hist=False,
     if want_bins:
         out["bins"] = bins
     return out
+
+
+# Error model of an fp32 evaluation (the parity tests' per-histogram
+# tolerance): e0 relative error of every weight; e1 of each patch-cosine
+# numerator relative to the sum of its terms' magnitudes (fp32 normals differ
+# from these fp64 ones by a few ulp per component, and fp32 arithmetic adds a
+# few more: 16 ulp of 2^-24 bounds both).
+ERR_E0 = 2e-6
+ERR_E1 = 16 * 2.0 ** -24
+
+
+def error_model(scene, rec: np.ndarray | None = None, subset=None, e0: float = ERR_E0, e1: float = ERR_E1,
+                lib=None):
+    """Per bin of each histogram: a bound on the error of an fp32 evaluation
+    of the in-window pair weights (``err``) and the in-window pair count
+    (``count``), both [n_out, T] fp64, before the jitter; and each
+    histogram's stand-off weight g_l g_d (``gain``, [n_out])."""
+    lib = lib or load()
+    if rec is None:
+        rec = patches(scene, lib)
+    rec = np.ascontiguousarray(rec, np.float64)
+    n_total = scene.n_laser * scene.n_scan
+    sub = None if subset is None else np.ascontiguousarray(subset, np.int32)
+    n_out = n_total if sub is None else sub.shape[0]
+    T = int(scene.n_bins)
+    err = np.zeros((n_out, T), np.float64)
+    cnt = np.zeros((n_out, T), np.float64)
+    gain = np.zeros(n_out, np.float64)
+    rc = lib.oracle_forward_error_model(C.byref(make_params(scene)), _dptr(rec), rec.shape[0],
+                                        None if sub is None else sub.ctypes.data, 0 if sub is None else n_out,
+                                        float(e0), float(e1), err.ctypes.data, cnt.ctypes.data, gain.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_forward_error_model rejected its arguments")
+    return {"err": err, "count": cnt, "gain": gain}
 
 
 def _maps64(scene, depth64=None, albedo64=None):

@@ -471,6 +471,99 @@ int32_t oracle_forward_smooth(const oracle_params* prm, const double* rec, int32
     return err;
 }
 
+/*
+ * Error model of an fp32 evaluation of the direct operator (Section 2,
+ * Eq. (1), with the cosines and stand-off legs of oracle_forward): the
+ * per-histogram tolerance of the parity tests, not part of the operator.
+ * The histogram bins are exact (the fast path re-bins in fp64), so the
+ * error of an fp32 evaluation is the error of each in-window pair's weight.
+ * That weight is w = K c_l c_d (K = a gg cw_l cw_d / (r_l^2 r_d^2),
+ * c = max(0, n . (w - p)) / r the patch cosine of each leg); its factors
+ * come within a few ulp except the patch cosines, whose numerator
+ * n . (w - p) cancels for grazing patches: fp32 record normals, fp32
+ * coordinates (each rounded before the difference is taken) and fp32
+ * arithmetic give it an error of up to e1 times the magnitudes it is built
+ * from, so each cosine is uncertain by
+ *     dc = e1 (|n_x| (|p_x| + |w_x|) + |n_y| (|p_y| + |w_y|) + |n_z p_z|) / r.
+ * Per bin k of histogram h this accumulates, over the in-window pairs,
+ *     err[h][k] = sum_p e0 w_p + K_p (dc_l c_d + c_l dc_d + dc_l dc_d)
+ * (the last terms bound |K ((c_l + dc_l)(c_d + dc_d) - c_l c_d)|, clamped
+ * pairs included: c = 0 may still become dc), and
+ *     count[h][k] = number of in-window pairs,
+ * from which a test bounds rounding that is absolute per pair; gain[h] is
+ * the histogram's stand-off weight g_l g_d.  Without cosines only the e0
+ * term remains.  Layout and `subset` as in oracle_forward; err and count
+ * are [n_out][T], gain [n_out] (each may be NULL).  Returns 0 or -1.
+ */
+int32_t oracle_forward_error_model(const oracle_params* prm, const double* rec, int32_t P,
+                                   const int32_t* subset, int32_t n_subset, double e0, double e1,
+                                   double* err, double* count, double* gain)
+{
+    const oracle_grid* rg = &prm->relay;
+    const int confocal = prm->laser.nx <= 0 || prm->laser.ny <= 0;
+    const oracle_grid* lg = confocal ? rg : &prm->laser;
+    const int64_t S = (int64_t)rg->nx * rg->ny;
+    const int64_t L = confocal ? 1 : (int64_t)lg->nx * lg->ny;
+    const int64_t n_out = subset ? n_subset : L * S;
+    const int32_t T = prm->n_bins;
+    if (T < 1 || !(prm->bin_ps > 0.0) || prm->standoff_m < 0.0 || P < 0 || !(e0 >= 0.0) || !(e1 >= 0.0))
+        return -1;
+    const double inv = oracle_inv_bin(prm->bin_ps);
+    double* rx = (double*)malloc(sizeof(double) * (size_t)(rg->nx + rg->ny));
+    double* lx = (double*)malloc(sizeof(double) * (size_t)(lg->nx + lg->ny));
+    if (!rx || !lx) { free(rx); free(lx); return -1; }
+    oracle_grid_coords(rg, rx, rx + rg->nx);
+    oracle_grid_coords(lg, lx, lx + lg->nx);
+    int32_t rc = 0;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t oi = 0; oi < n_out; ++oi) {
+        const int64_t h = subset ? subset[oi] : oi;
+        if (h < 0 || h >= L * S) { rc = -1; continue; }
+        double wlx, wly, wdx, wdy, o, gg;
+        hist_setup(prm, rx, lx, h, &wlx, &wly, &wdx, &wdy, &o, &gg);
+        if (gain) gain[oi] = gg;
+        double* E = err ? err + oi * T : NULL;
+        double* N = count ? count + oi * T : NULL;
+        for (int32_t k = 0; k < T; ++k) {
+            if (E) E[k] = 0.0;
+            if (N) N[k] = 0.0;
+        }
+        for (int32_t p = 0; p < P; ++p) {
+            const double* q = rec + (int64_t)p * 8;
+            if (q[7] == 0.0) continue;
+            const double px = q[0], py = q[1], pz = q[2];
+            const double alx = px - wlx, aly = py - wly, alz = pz;
+            const double adx = px - wdx, ady = py - wdy, adz = pz;
+            const double r_l = sqrt((alx * alx + aly * aly) + alz * alz);
+            const double r_d = sqrt((adx * adx + ady * ady) + adz * adz);
+            const double u = ((r_l + r_d) + o) * inv;
+            const double kf = floor(u);
+            if (!(kf >= 0.0 && kf < (double)T)) continue;
+            const int32_t k = (int32_t)kf;
+            double e;
+            if (prm->cosines) {
+                const double K = q[3] * gg * (alz / r_l) * (adz / r_d) / (r_l * r_l * r_d * r_d);
+                double c_l = -(q[4] * alx + q[5] * aly + q[6] * alz) / r_l;
+                double c_d = -(q[4] * adx + q[5] * ady + q[6] * adz) / r_d;
+                if (c_l < 0.0) c_l = 0.0;
+                if (c_d < 0.0) c_d = 0.0;
+                const double dc_l =
+                    e1 * (fabs(q[4]) * (fabs(px) + fabs(wlx)) + fabs(q[5]) * (fabs(py) + fabs(wly)) + fabs(q[6] * pz)) / r_l;
+                const double dc_d =
+                    e1 * (fabs(q[4]) * (fabs(px) + fabs(wdx)) + fabs(q[5]) * (fabs(py) + fabs(wdy)) + fabs(q[6] * pz)) / r_d;
+                e = e0 * (K * c_l * c_d) + K * (dc_l * c_d + c_l * dc_d + dc_l * dc_d);
+            } else {
+                e = e0 * (q[3] * gg / (r_l * r_l * r_d * r_d));
+            }
+            if (E) E[k] += e;
+            if (N) N[k] += 1.0;
+        }
+    }
+    free(rx);
+    free(lx);
+    return rc;
+}
+
 /* dL/d(pz, a, n_x, n_y, n_z) of one present record q, summed over every
  * histogram, for upstream gradient G = dL/dtau_s [H][T]: per pair
  * dL/dw = G0 = sum_k G N(x_k) and dL/du = w G1, G1 = sum_k G (x_k / sigma^2)

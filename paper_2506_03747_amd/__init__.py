@@ -23,8 +23,8 @@ import torch
 
 from ._native import TUNING_PATH  # noqa: F401
 from ._native import (NLOS_F_COSINES, NLOS_MAX_BINS, NLOS_MAX_PATCHES, NLOS_MAX_RADIUS,  # noqa: F401
-                      NLOS_RECORD_FLOATS, DepthRequest, Grid, NlosError, Params, PlanInfo, Request, TuningEntry,
-                      check, lib, strerror)
+                      NLOS_RECORD_FLOATS, DepthRequest, Grid, NlosError, Params, PlanInfo, Probe, Request,
+                      TuningEntry, check, lib, strerror)
 
 __all__ = ["Grid", "Params", "NlosError", "make_grid", "make_params", "params_of",
            "patches_from_depth", "forward", "simulate", "debug_bins", "out_shape", "n_histograms",
@@ -140,11 +140,12 @@ def forward(params: Params, patches: torch.Tensor, n_active: Optional[torch.Tens
 def simulate(params: Params, depth: torch.Tensor, grid, albedo: Optional[torch.Tensor] = None,
              mask: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
              patches: Optional[torch.Tensor] = None, n_active: Optional[torch.Tensor] = None,
-             workspace: Optional[torch.Tensor] = None, forward_mark=None, stream=None):
+             workspace: Optional[torch.Tensor] = None, forward_mark=None, evaluated_pairs=None, stream=None):
     """Depth map -> jittered histograms in one call (geometry, record
     summaries and the forward operator).  Returns (out, patches, n_active).
     ``forward_mark``: a torch.cuda.Event recorded right before the pair
-    kernel (timing hook), or None."""
+    kernel (timing hook), or None.  ``evaluated_pairs``: a device int64[1]
+    the pair kernel adds its evaluated pair count to, or None."""
     g = make_grid(grid)
     _dev(depth, torch.float32, "depth")
     _dev(albedo, torch.float32, "albedo")
@@ -168,9 +169,13 @@ def simulate(params: Params, depth: torch.Tensor, grid, albedo: Optional[torch.T
           "nlos_simulate_workspace_bytes")
     if workspace is None or workspace.numel() < need.value:
         workspace = torch.empty(need.value, dtype=torch.uint8, device=dev)
-    mark = None if forward_mark is None else C.c_void_p(forward_mark.cuda_event)
+    probe = None
+    if forward_mark is not None or evaluated_pairs is not None:
+        _dev(evaluated_pairs, torch.int64, "evaluated_pairs")
+        probe = C.byref(Probe(None if forward_mark is None else forward_mark.cuda_event,
+                              None if evaluated_pairs is None else evaluated_pairs.data_ptr()))
     check(lib().nlos_simulate(C.byref(params), C.byref(g), _ptr(depth), _ptr(albedo), _ptr(mask), _ptr(patches),
-                              _ptr(n_active), _ptr(out), _ptr(workspace), workspace.numel(), mark,
+                              _ptr(n_active), _ptr(out), _ptr(workspace), workspace.numel(), probe,
                               _stream(stream)), "nlos_simulate")
     return out, patches, n_active
 

@@ -57,6 +57,10 @@ class PlanInfo(C.Structure):
                 ("lds_bytes", C.c_int64)]
 
 
+class Probe(C.Structure):
+    _fields_ = [("forward_mark", C.c_void_p), ("evaluated_pairs", C.c_void_p)]
+
+
 class NlosError(RuntimeError):
     def __init__(self, code: int, where: str, hip: int = 0):
         self.code = code
@@ -84,7 +88,7 @@ SIGNATURES = [
     ("nlos_simulate_workspace_bytes", C.c_int, [C.POINTER(Params), C.POINTER(Grid), C.POINTER(C.c_size_t)]),
     ("nlos_simulate", C.c_int,
      [C.POINTER(Params), C.POINTER(Grid), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-      C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
+      C.c_void_p, C.c_size_t, C.POINTER(Probe), C.c_void_p]),
     ("nlos_patches_batched_sizes", C.c_int,
      [C.POINTER(DepthRequest), C.c_int32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     ("nlos_patches_batched", C.c_int,

@@ -862,21 +862,17 @@ int nlos_simulate_workspace_bytes(const nlos_params* p, const nlos_grid* g, size
     if (rc != NLOS_OK) return rc;
     rc = nlos_forward_workspace_bytes(p, g->nx * g->ny, &fwd);
     if (rc != NLOS_OK) return rc;
-    // the summaries here are one per 16x16-pixel tile of every geometry block
-    const int64_t bx = (g->nx + nlos::kBlockPx - 1) / nlos::kBlockPx;
-    const int64_t by = (g->ny + nlos::kBlockPx - 1) / nlos::kBlockPx;
-    const int64_t blocks = ((int64_t)nlos::kBlockPx * nlos::kBlockPx * bx * by + nlos::kGeomBlock - 1) / nlos::kGeomBlock;
-    const int64_t tiles = blocks * (nlos::kGeomBlock / (nlos::kBlockPx * nlos::kBlockPx));
-    // then the records' pair-loop constants, 32 bytes per record
-    *bytes = align_up(geo, 256) + align_up(std::max(fwd, (size_t)tiles * sizeof(nlos::ChunkStat)), 256) +
-             (size_t)g->nx * g->ny * 32;
+    // the geometry's block counts, the record summaries (those of
+    // nlos_forward), then the records' pair-loop constants, 32 bytes per record
+    *bytes = align_up(geo, 256) + align_up(fwd, 256) + (size_t)g->nx * g->ny * 32;
     return NLOS_OK;
 }
 
 int nlos_simulate(const nlos_params* p, const nlos_grid* g, const float* depth, const float* albedo,
                   const uint8_t* mask, float* patches, int32_t* n_active, float* out, void* ws, size_t ws_bytes,
-                  void* forward_mark, void* stream)
+                  const nlos_probe* probe, void* stream)
 {
+    if (probe && probe->evaluated_pairs && !aligned(probe->evaluated_pairs, 8)) return NLOS_EINVAL;
     nlos::GeomArgs ga;
     int rc = geom_args(g, depth, albedo, mask, p ? p->flags : 0u, patches, n_active, &ga);
     if (rc != NLOS_OK) return rc;
@@ -898,25 +894,24 @@ int nlos_simulate(const nlos_params* p, const nlos_grid* g, const float* depth, 
     unsigned char* w = static_cast<unsigned char*>(ws);
     ga.counts = reinterpret_cast<int32_t*>(w);
     ga.offsets = ga.n_blocks <= nlos::kScanFreeBlocks ? nullptr : ga.counts + ga.n_blocks;
-    // record summaries: one per 16x16-pixel tile of every geometry block,
-    // written by the scatter (tiles past the map are empty)
+    // record summaries over the partition nlos_forward uses (kStatBlock
+    // consecutive records; a.n_stats from setup_forward), cleared by the count
+    // pass and merged by the scatter: the same summaries, so the same
+    // fixed-point scales and the same output bits as the two calls
     a.stats = reinterpret_cast<nlos::ChunkStat*>(w + align_up(geo, 256));
-    a.n_stats = ga.n_blocks * (nlos::kGeomBlock / (nlos::kBlockPx * nlos::kBlockPx));
     ga.stats = a.stats;
     ga.n_stats = a.n_stats;
     // the scatter also writes each record's pair-loop constants (scaled as
     // the pair loop scales: by 2 / (c dt) confocal, 1 / (c dt) otherwise)
-    size_t fwd = 0;
-    nlos_forward_workspace_bytes(p, n_patches, &fwd);
-    const size_t stats_b = std::max(fwd, (size_t)a.n_stats * sizeof(nlos::ChunkStat));
-    ga.prep = reinterpret_cast<float4*>(w + align_up(geo, 256) + align_up(stats_b, 256));
+    ga.prep = reinterpret_cast<float4*>(w + align_up(geo, 256) + align_up(need_fwd, 256));
     ga.prep_sig = is_confocal(p) ? a.inv2_f : a.inv_f;
     a.prep = ga.prep;
+    a.eval_pairs = probe ? probe->evaluated_pairs : nullptr;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = nlos::launch_geometry(ga, st);
     if (e != hipSuccess) return hip_fail(e);
-    if (forward_mark) {
-        e = hipEventRecord((hipEvent_t)forward_mark, st);
+    if (probe && probe->forward_mark) {
+        e = hipEventRecord((hipEvent_t)probe->forward_mark, st);
         if (e != hipSuccess) return hip_fail(e);
     }
     if (a.atomic_out) {

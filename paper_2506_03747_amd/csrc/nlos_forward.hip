@@ -809,6 +809,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
     // together however unevenly culling thins the chunks.  A wavefront holds
     // two: the records of the next one are loaded while the current one is
     // evaluated, and the one after is claimed meanwhile.
+    int n_eval = 0;   // pairs evaluated by this wavefront (counted only on request)
     int chunk_id = 0;
     if (lane == 0) chunk_id = (int)atomicAdd(L.next, 2u);
     chunk_id = __builtin_amdgcn_readfirstlane(chunk_id);
@@ -877,6 +878,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
                 }
                 if (__all(out)) continue;
             }
+            n_eval += min(64, pe - base) * NH;
             const int b = k * NH;
             float cx2[TX], axv[TX], cy2[TY], byv[TY];
             if (CONF) {
@@ -947,6 +949,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
         next_id = __builtin_amdgcn_readfirstlane(claim);
     }
     guard_drain<CONF>(L, a, hb, Tl, wave, qw, qn);
+    if (a.eval_pairs && lane == 0) atomicAdd(a.eval_pairs, (unsigned long long)n_eval);
     __syncthreads();
     flush<NS>(a, L, hb, Tl, t0w, t1w, tap);
 }

@@ -51,6 +51,18 @@ __device__ __forceinline__ void count_body(const GeomArgs& a, int blk)
     if (p) p = is_present(a, (int64_t)ix * a.ay.n + iy);
     const int cnt = __syncthreads_count(p);
     if (threadIdx.x == 0) a.counts[blk] = cnt;
+    // empty record summaries for the scatter to merge into: block b clears
+    // kGeomBlock / kStatBlock of them (the blocks cover n_enum >= n_stats * kStatBlock
+    // pixels, so every summary is cleared before the scatter launch)
+    constexpr int kPer = kGeomBlock / kStatBlock;
+    if (a.stats && threadIdx.x < kPer * 8) {
+        const int i = blk * kPer + (int)threadIdx.x / 8, f = (int)threadIdx.x % 8;
+        if (i < a.n_stats) {
+            // x0, x1, y0, y1, z0, amax, count, pad: min fields start high, max fields low
+            const int v = (f >= 6) ? 0 : ((f == 0 || f == 2 || f == 4) ? INT32_MAX : INT32_MIN);
+            reinterpret_cast<int32_t*>(a.stats + i)[f] = v;
+        }
+    }
 }
 
 __global__ void __launch_bounds__(kGeomBlock) k_geom_count(const GeomArgs a) { count_body(a, (int)blockIdx.x); }
@@ -110,14 +122,12 @@ __device__ __forceinline__ int wave_max_i(int v)
 // Records of one enumeration block at base + (rank among the present pixels
 // before it).  base is the exclusive prefix of the block counts: read from
 // `offsets`, or (offsets null) summed here from the counts.  With `stats`,
-// the block also writes the summaries of its own records, one per 16x16-pixel
-// tile (reduced per wave, then across the tile's waves in LDS, on the
-// order-preserving images): no other block touches them.
+// the block also merges its records into the summaries of kStatBlock
+// consecutive records (cleared by the count pass).
 __device__ __forceinline__ void scatter_body(const GeomArgs& a, int blk)
 {
     __shared__ int wave_cnt[kGeomBlock / 64];
     __shared__ int red[kGeomBlock / 64];
-    __shared__ int sst[kGeomBlock / 64][8];   // per wave: x0, x1, y0, y1, z0, amax, count
     const int64_t e = (int64_t)blk * kGeomBlock + threadIdx.x;
     int ix = 0, iy = 0;
     bool p = enum_pixel(a, e, &ix, &iy);
@@ -172,37 +182,34 @@ __device__ __forceinline__ void scatter_body(const GeomArgs& a, int blk)
     }
     if (!a.stats) return;   // uniform across the block
 
-    const int v0 = wave_min_i(p ? ord_f(A.x) : INT32_MAX);
-    const int v1 = wave_max_i(p ? ord_f(A.x) : INT32_MIN);
-    const int v2 = wave_min_i(p ? ord_f(A.y) : INT32_MAX);
-    const int v3 = wave_max_i(p ? ord_f(A.y) : INT32_MIN);
-    const int v4 = wave_min_i(p ? ord_f(A.z) : INT32_MAX);
-    const int v5 = wave_max_i(p ? ord_f(A.w) : INT32_MIN);
-    if (lane == 0) {
-        int* t = sst[wave];
-        t[0] = v0;
-        t[1] = v1;
-        t[2] = v2;
-        t[3] = v3;
-        t[4] = v4;
-        t[5] = v5;
-        t[6] = __popcll(bal);
-    }
-    __syncthreads();
-    // one summary per 16x16-pixel tile (4 waves of the enumeration): thread
-    // 8 t + f reduces field f of tile t; fields in ChunkStat order
-    constexpr int kTileWaves = kBlockPx * kBlockPx / 64;
-    constexpr int kTiles = kGeomBlock / (kBlockPx * kBlockPx);
-    if (threadIdx.x < 8 * kTiles) {
-        const int t = threadIdx.x / 8, f = threadIdx.x % 8;
-        int v = (f == 6 || f == 7) ? 0 : ((f == 0 || f == 2 || f == 4) ? INT32_MAX : INT32_MIN);
-        if (f < 7) {
-            for (int w = t * kTileWaves; w < (t + 1) * kTileWaves; ++w) {
-                const int x = sst[w][f];
-                v = (f == 6) ? v + x : ((f == 0 || f == 2 || f == 4) ? min(v, x) : max(v, x));
-            }
+    // Record summaries, one per kStatBlock consecutive records: a wavefront's
+    // records are consecutive (off - rank is its first), so they meet at most
+    // two summaries; each is reduced over the wavefront and merged with
+    // integer atomics on the order-preserving images (min and max commute,
+    // so the result does not depend on the order of the merges).
+    const int n_w = __popcll(bal);
+    if (n_w == 0) return;
+    const int first = __builtin_amdgcn_readfirstlane(off - rank);   // the same in every lane
+    const int c0 = first / kStatBlock, c1 = (first + n_w - 1) / kStatBlock;
+    for (int c = c0; c <= c1; ++c) {
+        const bool in = p && off / kStatBlock == c;
+        const int v0 = wave_min_i(in ? ord_f(A.x) : INT32_MAX);
+        const int v1 = wave_max_i(in ? ord_f(A.x) : INT32_MIN);
+        const int v2 = wave_min_i(in ? ord_f(A.y) : INT32_MAX);
+        const int v3 = wave_max_i(in ? ord_f(A.y) : INT32_MIN);
+        const int v4 = wave_min_i(in ? ord_f(A.z) : INT32_MAX);
+        const int v5 = wave_max_i(in ? ord_f(A.w) : INT32_MIN);
+        const int cnt = __popcll(__ballot(in));
+        if (lane == 0 && cnt > 0 && c < a.n_stats) {
+            int32_t* t = reinterpret_cast<int32_t*>(a.stats + c);
+            atomicMin(t + 0, v0);
+            atomicMax(t + 1, v1);
+            atomicMin(t + 2, v2);
+            atomicMax(t + 3, v3);
+            atomicMin(t + 4, v4);
+            atomicMax(t + 5, v5);
+            atomicAdd(t + 6, cnt);
         }
-        reinterpret_cast<int32_t*>(a.stats + (int64_t)blk * kTiles + t)[f] = v;
     }
 }
 

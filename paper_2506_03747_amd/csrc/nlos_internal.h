@@ -39,7 +39,8 @@ struct GeomArgs {
     int32_t* counts;       // workspace: per enumeration block
     int32_t* offsets;      // workspace: exclusive prefix of counts; null: each
                            // scatter block sums the counts before it
-    ChunkStat* stats;      // nullable: [n_enum / 256] summaries, one per 16x16-pixel tile, built while scattering
+    ChunkStat* stats;      // nullable: [n_stats] summaries, one per kStatBlock consecutive records (the
+                           // partition k_chunk_stats uses), cleared by the count pass, merged by the scatter
     int32_t n_stats;
     Axis ax, ay;
     float hx, hy;          // spacings
@@ -52,11 +53,11 @@ struct GeomArgs {
 };
 constexpr int kGeomBlock = 1024;
 
-// Summary of a block of patch records (kStatBlock consecutive ones, or the
-// records of one 16x16-pixel tile of the map): lateral bounding box, smallest depth,
-// largest a, record count.  Used to bound the pair weights; any partition of
-// the records serves.  The six float fields are stored as order-preserving
-// int32 images (ord_f).
+// Summary of kStatBlock consecutive patch records: lateral bounding box,
+// smallest depth, largest a, record count.  Used to bound the pair weights
+// (and so the fixed-point scales); both the one-call path and nlos_forward
+// build them over the same partition, so both get the same scales.  The six
+// float fields are stored as order-preserving int32 images (ord_f).
 struct ChunkStat {
     int32_t x0, x1, y0, y1, z0, amax;
     int32_t count, pad;
@@ -126,6 +127,8 @@ struct FwdArgs {
     int32_t atomic_out;        // 1: accumulate into a zeroed output
     int32_t cosines;
     int32_t R;
+    unsigned long long* eval_pairs;   // nullable: += (wavefront lanes in range) x (unit histograms) per
+                                      // evaluated (wavefront, unit) block, i.e. the pairs the loop evaluated
     float taps[kMaxTaps];
 };
 

@@ -38,7 +38,7 @@ def test_exports_every_declared_symbol(nat):
 
 def test_version_and_strerror(nat):
     L = nat.lib()
-    assert L.nlos_abi_version() == 1
+    assert L.nlos_abi_version() == 2
     for code, text in ((0, "ok"), (-1, "invalid argument"), (-2, "workspace too small"),
                        (-3, "HIP runtime error"), (-4, "no usable GPU"), (7, "unknown error")):
         assert nat.strerror(code) == text
@@ -81,6 +81,18 @@ def test_request_struct_layout_matches_header(nat, tmp_path):
             D.n_active.offset, C.sizeof(R), R.patches.offset, R.n_patches.offset, R.n_active.offset,
             R.out.offset, R.params.offset]
     assert got == want
+
+
+def test_probe_struct_layout_matches_header(nat, tmp_path):
+    prog = tmp_path / "probe.c"
+    prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "nlos.h"\n'
+                    'int main(void){printf("%zu %zu %zu\\n", sizeof(nlos_probe), offsetof(nlos_probe, forward_mark),'
+                    'offsetof(nlos_probe, evaluated_pairs)); return 0;}\n')
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    Pr = nat.Probe
+    assert got == [C.sizeof(Pr), Pr.forward_mark.offset, Pr.evaluated_pairs.offset]
 
 
 def test_batched_checks(nat):
@@ -296,6 +308,9 @@ def test_simulate_checks(nat):
                            None) == nat.NLOS_EINVAL
     bad = _params(nat, bin_ps=0.0)
     assert L.nlos_simulate(C.byref(bad), C.byref(g), *args, FAKE, 1 << 30, None, None) == nat.NLOS_EINVAL
+    # a misaligned evaluated-pair counter is rejected before anything is enqueued
+    probe = nat.Probe(None, 0x10004)
+    assert L.nlos_simulate(C.byref(p), C.byref(g), *args, FAKE, need.value, C.byref(probe), None) == nat.NLOS_EINVAL
 
 
 def test_tuning_table_and_plan(nat):

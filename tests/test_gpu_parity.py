@@ -7,8 +7,8 @@ import pytest
 
 import oracle
 import scenes
-from gpu_helpers import (assert_parity, gpu_forward, gpu_patches, guard_delta, log, to_gpu,
-                         oracle_bins_for_records, rel_l2_rows)
+from gpu_helpers import (assert_parity, assert_parity_model, gpu_forward, gpu_patches, guard_delta, log,
+                         oracle_bins_for_records, parity_tolerance, rel_l2_rows, to_gpu)
 
 pytestmark = pytest.mark.gpu
 
@@ -112,35 +112,46 @@ def test_cfg5_full():
     log(f"cfg5 worst rel-L2 {e:.3e}")
 
 
+def _cfg3_subset(tau, H, n_rand=4096, n_weak=64):
+    """4096 seeded histograms and the 64 weakest non-empty ones (weakest by
+    the GPU's output: the choice of cases only, every value is checked
+    against the oracle)."""
+    import torch
+    rng = np.random.default_rng(33)
+    rand = rng.choice(H, n_rand, replace=False)
+    norms = tau.reshape(H, -1).double().norm(dim=1)
+    norms[norms == 0] = float("inf")
+    weakest = torch.topk(norms, n_weak, largest=False).indices.cpu().numpy()
+    return np.unique(np.concatenate([rand, weakest])).astype(np.int32), weakest
+
+
+def _check_cfg3(tau, sc, what):
+    """cfg3 (64 lasers x 128^2 detectors x T = 2048, 8.6 GB): sampled
+    histograms against the oracle, each within its own tolerance
+    max(1e-5, error-model bound): the bound exceeds 1e-5 only where a
+    histogram is made of a few pairs seen nearly edge-on, whose fp32 cosines
+    are ill-conditioned (or far weaker than their unit's fixed-point bound)."""
+    import torch
+    H = sc.n_laser * sc.n_scan
+    sub, weakest = _cfg3_subset(tau, H)
+    got = tau.reshape(H, -1)[torch.from_numpy(sub).long().cuda()].cpu().numpy()
+    rec = oracle.patches(sc)
+    ref = oracle.forward(sc, rec, subset=sub)["tau"]
+    tol = parity_tolerance(sc, ref, subset=sub, rec=rec)
+    e, ratio, loose = assert_parity_model(got, ref, tol, what=what)
+    in_w = np.isin(sub, weakest)
+    log(f"{what}: the 64 weakest: worst rel-L2 {rel_l2_rows(got[in_w], ref[in_w]).max():.3e}")
+    return e
+
+
 def test_cfg3_sampled():
-    """Non-confocal 64 lasers x 128^2 detectors x T=2048 (8.6 GB output):
-    4096 seeded histograms against the oracle at the 1e-5 bar, and the 64
-    weakest non-empty ones at 1e-4.  The weakest hold one or two pairs at the
-    end of the window, seen edge-on (patch cosine ~1e-3): there the weight
-    is conditioned by 1 / cos on the record normals, which are fp32 (within
-    ~2e-7 of the oracle's fp64 ones, as the record parity test allows), so
-    the records alone move such a histogram by up to ~1e-4."""
     import torch
     sc = scenes.cfg3()
     log("cfg3")
     tau, _, _ = gpu_forward(sc)
-    H = sc.n_laser * sc.n_scan
-    rng = np.random.default_rng(33)
-    rand = rng.choice(H, 4096, replace=False)
-    norms = tau.reshape(H, -1).double().norm(dim=1)
-    norms[norms == 0] = float("inf")
-    weakest = torch.topk(norms, 64, largest=False).indices.cpu().numpy()
-    sub = np.unique(np.concatenate([rand, weakest])).astype(np.int32)
-    got = tau.reshape(H, -1)[torch.from_numpy(sub).long().cuda()].cpu().numpy()
+    _check_cfg3(tau, sc, "cfg3 forward")
     del tau
     torch.cuda.empty_cache()
-    ref = oracle.forward(sc, subset=sub)["tau"]
-    in_rand = np.isin(sub, rand)
-    e = assert_parity(got[in_rand], ref[in_rand], what="cfg3")
-    log(f"cfg3 worst rel-L2 {e:.3e}")
-    weak = np.isin(sub, weakest) & ~in_rand
-    ew = assert_parity(got[weak], ref[weak], tol=1e-4, what="cfg3 weakest")
-    log(f"cfg3 weakest worst rel-L2 {ew:.3e}")
 
 
 @pytest.mark.parametrize("name,n_hist", [("cfg1", None), ("cfg2", 256), ("cfg3", 128)])
@@ -332,14 +343,12 @@ def test_repeatable_within_tolerance():
                                                       bin_ps=2.0, fwhm_ps=40.0, zlo=0.5, zhi=4.0, half=2.0)],
                          ids=["cfg1", "cfg2", "cfg3", "split", "windows"])
 def test_simulate_equals_two_calls(make):
-    """One call (geometry with per-tile record summaries + forward) gives the
-    records and count of the two calls bit for bit, and their histograms to
-    the fixed-point rounding.  The summaries partition the records
-    differently, so each unit's bound, hence its scale 2^31 / W and each
-    increment's rounding, can differ: a histogram at least 1e-3 of the
-    scene's strongest agrees to 1e-5; a weaker one (in cfg3, a single
-    grazing pair at the window's end, 1e-5 of the strongest) is held to
-    the absolute rounding of its unit, checked here as rel-L2 <= 2e-4."""
+    """One call (geometry merging the record summaries + forward) gives the
+    records and count of the two calls bit for bit, and -- the summaries
+    covering the same 256-record blocks, so the fixed-point scales are the
+    same -- the same histograms bit for bit.  Where patches are split over
+    workgroups the partial histograms meet in float atomics of no fixed
+    order: there the two agree to 1e-6."""
     import torch
     import paper_2506_03747_amd as nl
     sc = make()
@@ -354,19 +363,58 @@ def test_simulate_equals_two_calls(make):
     assert k == int(n2.item())
     np.testing.assert_array_equal(rec[:k].cpu().numpy().view(np.uint32), rec2[:k].cpu().numpy().view(np.uint32))
     del rec, rec2
-    got = out.cpu().numpy()
-    del out
-    ref = out2.cpu().numpy()
-    del out2
-    e = rel_l2_rows(got, ref)
-    nrm = np.linalg.norm(ref.reshape(-1, ref.shape[-1]).astype(np.float64), axis=1)
-    strong = nrm >= 1e-3 * nrm.max()
-    log(f"simulate {sc.name}: {int(strong.sum())} strong, worst {e[strong].max():.3e}; "
-        f"{int((~strong).sum())} weak, worst {e[~strong].max() if (~strong).any() else 0.0:.3e}; "
-        f"{int((e > 1e-5).sum())} above 1e-5")
-    assert e[strong].max() <= 1e-5, f"simulate: rel-L2 {e[strong].max():.3e}"
-    if (~strong).any():
-        assert e[~strong].max() <= 2e-4, f"simulate (weak): rel-L2 {e[~strong].max():.3e}"
+    split = nl.get_plan(prm, sc.n_patch_total)["n_split"] > 1
+    if not split:
+        same = bool(torch.equal(out.view(torch.int32), out2.view(torch.int32)))
+        log(f"simulate {sc.name}: bitwise equal {same}")
+        assert same, "one call and two calls differ"
+    else:
+        got = out.cpu().numpy()
+        ref = out2.cpu().numpy().astype(np.float64)
+        e = assert_parity(got, ref, tol=1e-6, what=f"simulate {sc.name} (split)")
+        log(f"simulate {sc.name} (split): worst rel-L2 {e:.3e}")
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg2", "cfg3"])
+def test_simulate_matches_oracle(name):
+    """The benchmarked one-call path against the oracle: cfg1 and cfg2 in
+    full at 1e-5 per histogram, cfg3 on 4096 seeded histograms plus its 64
+    weakest, each within its own tolerance."""
+    import torch
+    import paper_2506_03747_amd as nl
+    sc = scenes.by_name(name)
+    log(f"simulate vs oracle {name}")
+    depth, albedo, mask = to_gpu(sc)
+    prm = nl.params_of(sc)
+    out, rec, n = nl.simulate(prm, depth, sc.patch_grid, albedo, mask)
+    torch.cuda.synchronize()
+    if name == "cfg3":
+        _check_cfg3(out, sc, "cfg3 simulate")
+        del out
+        torch.cuda.empty_cache()
+    else:
+        ref = oracle.forward(sc)["tau"]
+        e = assert_parity(out.cpu().numpy(), ref, what=f"{name} simulate")
+        log(f"{name} simulate: worst rel-L2 {e:.3e}")
+
+
+def test_evaluated_pairs_cover_the_window():
+    """The evaluated-pair count of the one-call path: every pair that lands
+    in the window is evaluated (the cull is safe), and no more pairs than
+    (histograms x records) are."""
+    import torch
+    import paper_2506_03747_amd as nl
+    sc = scenes.cfg2()
+    depth, albedo, mask = to_gpu(sc)
+    prm = nl.params_of(sc)
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    out, rec, n = nl.simulate(prm, depth, sc.patch_grid, albedo, mask, evaluated_pairs=cnt)
+    torch.cuda.synchronize()
+    ev = int(cnt.item())
+    in_window = int(oracle.error_model(sc)["count"].sum())
+    total = sc.n_scan * int(n.item())
+    log(f"evaluated {ev} of {total} pairs ({ev / total:.3f}); in the window {in_window}")
+    assert in_window <= ev <= total
 
 
 def test_simulate_empty_scene():

@@ -126,6 +126,46 @@ def test_noise_mutant_is_caught(tmp_path, name, old, new):
     print(name, "caught by", failures)
 
 
+# planted mistakes in the fp32 error model (the GPU tests' tolerance),
+# checked against its own pins
+ERROR_MUTANTS = [
+    ("error_drop_cross_term", "K * (dc_l * c_d + c_l * dc_d + dc_l * dc_d)", "K * (dc_l * c_d + c_l * dc_d)"),
+    ("error_one_leg", "K * (dc_l * c_d + c_l * dc_d + dc_l * dc_d)", "K * (dc_l * c_d)"),
+    ("error_dc_over_r2", "fabs(q[6] * pz)) / r_l;", "fabs(q[6] * pz)) / (r_l * r_l);"),
+    ("error_dc_signed_terms",
+     "e1 * (fabs(q[4]) * (fabs(px) + fabs(wdx)) + fabs(q[5]) * (fabs(py) + fabs(wdy)) + fabs(q[6] * pz))",
+     "e1 * fabs(q[4] * adx + q[5] * ady + q[6] * pz)"),
+    ("error_drop_e0", "e = e0 * (K * c_l * c_d) + K *", "e = K *"),
+    ("error_count_all_pairs", "if (!(kf >= 0.0 && kf < (double)T)) continue;\n            const int32_t k = (int32_t)kf;",
+     "const int32_t k = kf < 0.0 ? 0 : (kf >= (double)T ? T - 1 : (int32_t)kf);"),
+]
+
+
+def _run_error_pins(lib):
+    import pins_error
+    failures = []
+    for pin in pins_error.ERROR_PINS:
+        try:
+            pin(lib)
+        except Exception as e:  # noqa: BLE001 - any failure counts
+            failures.append((pin.__name__, type(e).__name__))
+    return failures
+
+
+@pytest.mark.parametrize("name,old,new", ERROR_MUTANTS, ids=[m[0] for m in ERROR_MUTANTS])
+def test_error_mutant_is_caught(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation site for {name} not found"
+    path = str(tmp_path / "mut.c")
+    with open(path, "w") as f:
+        f.write(src.replace(old, new))
+    so = str(tmp_path / "libmut.so")
+    oracle.compile_library(path, so)
+    failures = _run_error_pins(oracle.load(so))
+    assert failures, f"mutant {name} passed every error-model pin"
+    print(name, "caught by", failures)
+
+
 def _run_pins(lib):
     failures = []
     for pin in pins.FAST_PINS:
