@@ -184,6 +184,25 @@ int nlos_forward(const nlos_params* p, const float* patches, int32_t n_patches,
                  const int32_t* n_active, float* out, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * nlos_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid it): the
+ * same launches and results (bit for bit) with the record summaries in a
+ * scratch array the library holds on each GPU it runs on (512 KiB, kept
+ * until the process ends; its address is looked up on the first call on a
+ * device, with that device current, so `stream` must belong to the current
+ * device).  The call itself allocates nothing.
+ *   n_patches  at most NLOS_NOALLOC_MAX_PATCHES, else NLOS_ENOSPC.
+ * Calls on one GPU share the scratch: calls that overlap in time on one GPU
+ * (on different streams, or from several threads without ordering) race and
+ * give wrong results; order them on one stream.  Other arguments and errors
+ * as nlos_forward.
+ */
+#define NLOS_NOALLOC_MAX_PATCHES (1 << 22)
+
+int nlos_forward_noalloc(const nlos_params* p, const float* patches, int32_t n_patches,
+                         const int32_t* n_active, float* out, void* stream);
+
+/*
  * The whole path in one call: nlos_patches_from_depth for the depth map on
  * grid g (flags = p->flags) followed by nlos_forward over its records, with
  * the record summaries built while the records are written (no separate

@@ -23,6 +23,7 @@ NLOS_MAX_BINS = 1 << 22
 NLOS_MAX_RADIUS = 127
 NLOS_MAX_PATCHES = 1 << 24
 NLOS_RECORD_FLOATS = 8
+NLOS_NOALLOC_MAX_PATCHES = 1 << 22
 
 
 class Grid(C.Structure):
@@ -85,6 +86,8 @@ SIGNATURES = [
     ("nlos_forward", C.c_int,
      [C.POINTER(Params), C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
       C.c_void_p]),
+    ("nlos_forward_noalloc", C.c_int,
+     [C.POINTER(Params), C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("nlos_simulate_workspace_bytes", C.c_int, [C.POINTER(Params), C.POINTER(Grid), C.POINTER(C.c_size_t)]),
     ("nlos_simulate", C.c_int,
      [C.POINTER(Params), C.POINTER(Grid), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,

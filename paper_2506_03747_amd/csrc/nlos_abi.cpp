@@ -724,6 +724,43 @@ int lct_setup(const nlos_params* p, nlos::LctArgs* a, int64_t* n3)
     return NLOS_OK;
 }
 
+// Scratch of nlos_forward_noalloc: the record summaries, for up to
+// NLOS_NOALLOC_MAX_PATCHES records, in a file-scope device array (each GPU
+// the library runs on holds its own copy until the process ends).  Host code
+// never uses the array's name as an address: its device address on each GPU
+// comes from hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t kNoAllocScratchBytes =
+    (size_t)((NLOS_NOALLOC_MAX_PATCHES + nlos::kStatBlock - 1) / nlos::kStatBlock) * sizeof(nlos::ChunkStat);
+static_assert(kNoAllocScratchBytes == 512 * 1024, "the stated scratch size");
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the scratch array on the current device (null on
+// failure, with the HIP error recorded).
+void* scratch_on_current_device()
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        g_last_hip = (int)(e != hipSuccess ? e : hipErrorInvalidDevice);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            g_last_hip = (int)(e != hipSuccess ? e : hipErrorInvalidSymbol);
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -842,6 +879,33 @@ int nlos_forward(const nlos_params* p, const float* patches, int32_t n_patches, 
     if (ws && !aligned(ws, 16)) return NLOS_EINVAL;
     const int dev = device_check();
     if (dev != NLOS_OK) return dev;
+    a.stats = reinterpret_cast<nlos::ChunkStat*>(ws);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = nlos::launch_stats(a, a.stats, st);
+    if (e != hipSuccess) return hip_fail(e);
+    if (a.atomic_out) {
+        e = nlos::launch_fill(out, (size_t)a.out_len, st);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    e = nlos::launch_forward(a, plan, is_confocal(p), st);
+    return e == hipSuccess ? NLOS_OK : hip_fail(e);
+}
+
+int nlos_forward_noalloc(const nlos_params* p, const float* patches, int32_t n_patches, const int32_t* n_active,
+                         float* out, void* stream)
+{
+    nlos::FwdArgs a;
+    nlos::Plan plan;
+    size_t need = 0;
+    int rc = setup_forward(p, patches, n_patches, n_active, out, kTargetBlocks, &a, &plan, &need);
+    if (rc != NLOS_OK) return rc;
+    if (n_patches > NLOS_NOALLOC_MAX_PATCHES || need > kNoAllocScratchBytes) return NLOS_ENOSPC;
+    const int dev = device_check();
+    if (dev != NLOS_OK) return dev;
+    void* ws = scratch_on_current_device();
+    if (!ws) return NLOS_EHIP;
+    // the same launches as nlos_forward, with the summaries in the scratch
+    // array (every summary the pair kernel reads is written first)
     a.stats = reinterpret_cast<nlos::ChunkStat*>(ws);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = nlos::launch_stats(a, a.stats, st);
