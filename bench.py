@@ -374,8 +374,10 @@ def serving_leg(n_req):
     """Batched vs plain serving of the uneven request mix: requests 0..n-1 of
     the serving mix (confocal, scan 32..128 squared, 4k..262k patches, T of
     512/1024/2048), Poisson arrivals at 1.5x the measured plain capacity, 2 GiB
-    HBM budget for requests in flight.  Latency = tick completion on the GPU
-    minus arrival."""
+    HBM budget (tick workspaces and requests in flight).  Batched: each tick
+    is one graph launch on one of three overlapping streams; plain: one
+    request at a time through the one-call path on one stream.  Latency =
+    tick completion on the GPU minus arrival."""
     import torch
     import scenes
     from paper_2506_03747_amd import n_histograms, params_of, serving
@@ -405,7 +407,10 @@ def serving_leg(n_req):
                      "makespan_ms": round(res.makespan_ms, 3),
                      "gpairs_s": round(pairs / (res.makespan_ms * 1e-3) / 1e9, 3),
                      "ticks": res.ticks, "mean_batch": round(float(np.mean(res.batch_sizes)), 2),
-                     "peak_bytes": res.peak_bytes}
+                     "launches_per_tick": round(float(np.mean(res.launches)), 2),
+                     "launches": int(np.sum(res.launches)),
+                     "peak_request_bytes": res.peak_bytes, "workspace_bytes": res.fixed_bytes}
+    out["batched_over_plain"] = round(out["batched"]["gpairs_s"] / out["plain"]["gpairs_s"], 3)
     torch.cuda.synchronize()
     return out
 

@@ -170,15 +170,20 @@ int nlos_forward_workspace_bytes(const nlos_params* p, int32_t n_patches, size_t
  *              overwritten by the call, so calls that share a workspace must be
  *              ordered on one stream.
  * Precision: each pair's weight is found in fp32 and accumulated in 64-bit
- * fixed point: it adds round(w * s_u), s_u = 2^31 / W_u, where the unit u
- * (the group of histograms of nlos_get_plan) has the bound
+ * fixed point: it adds round(w * s_u), s_u = 2^31 / W_u, where the block u of
+ * histograms -- the aligned 4 x 4 scan points that hold the histogram
+ * (confocal), or 2 lasers x 2 x 2 detectors (non-confocal), whatever unit
+ * the plan chose -- has the bound
  *   W_u = max over the summaries of 256 consecutive records of
  *         a_max / ((d_l^2 + z_min^2) (d_d^2 + z_min^2)),
  * d_l, d_d the lateral distances from the summary's bounding box to the
- * unit's laser and detector rectangles.  A pair's rounding is therefore at
+ * block's laser and detector rectangles.  A pair's rounding is therefore at
  * most g_l g_d W_u / 2^32; the fp32 weight is within a few ulp of its fp64
  * value except where a patch cosine cancels (grazing patches), where the
- * error is that of the fp32 record normals.
+ * error is that of the fp32 record normals.  As the scales depend on the
+ * records and the block only, every call that computes a histogram
+ * (nlos_forward, nlos_simulate, the batched calls, a serving tick) gives the
+ * same bits, except where patches are split over workgroups (float atomics).
  */
 int nlos_forward(const nlos_params* p, const float* patches, int32_t n_patches,
                  const int32_t* n_active, float* out, void* ws, size_t ws_bytes, void* stream);
@@ -289,6 +294,81 @@ int nlos_forward_batched_sizes(const nlos_request* reqs, int32_t n, size_t* tabl
  */
 int nlos_forward_batched(const nlos_request* reqs, int32_t n, void* table, size_t table_bytes, void* ws,
                          size_t ws_bytes, void* stream);
+
+/*
+ * Serving ticks: the whole path (depth maps -> records -> histograms) for a
+ * list of requests, as a serving loop runs it once per tick (Algorithm 1
+ * runs the forward model once per frame; many scenes share one tick here).
+ * A tick is a fixed sequence of four operations on one stream: a copy of a
+ * host table to the start of the workspace, then three persistent kernels
+ * with fixed grids (depth-map counts and output zeroing; record scatter with
+ * summaries and pair-loop constants; pairs, binning, guard, jitter and
+ * write-out), whose workgroups claim (request, block) items from tickets in
+ * the copied table.  The operations depend only on the capacities, not on
+ * the requests, so a caller can capture nlos_tick_launch once in a HIP graph
+ * (per table and workspace) and replay it every tick after rewriting the
+ * table with nlos_tick_plan.  Each request's records, n_active and output are
+ * those of nlos_simulate for it alone, bit for bit (outputs that take float
+ * atomics to 1e-6).
+ * Supported requests: confocal, maps of at most 1024 x 1024 enumeration
+ * pixels (1024 blocks of 1024), plans that pair units over the whole window
+ * (nlos_get_plan pair = 1, n_windows = 1); anything else is NLOS_EINVAL
+ * from nlos_tick_plan (serve it through nlos_simulate).
+ */
+typedef struct nlos_sim_request {
+    nlos_params params;
+    nlos_grid grid;          /* lateral grid of the maps */
+    const float* depth;      /* device [nx][ny] */
+    const float* albedo;     /* device [nx][ny] or NULL (0.5) */
+    const uint8_t* mask;     /* device [nx][ny] or NULL (all present) */
+    float* patches;          /* device [nx*ny][8] records, 16-byte aligned */
+    int32_t* n_active;       /* device int32[1] */
+    float* out;              /* device output [relay.nx][relay.ny][T], 16-byte aligned */
+} nlos_sim_request;
+
+typedef struct nlos_tick_caps {
+    int32_t max_requests;    /* 1..4096 per tick */
+    int64_t max_pixels;      /* sum of nx * ny over a tick's requests */
+} nlos_tick_caps;
+
+/* Host table and device workspace bytes of a tick with these capacities
+ * (host pointers). */
+int nlos_tick_sizes(const nlos_tick_caps* caps, size_t* table_bytes, size_t* ws_bytes);
+
+/* Write the tick table for n requests (0..max_requests) into the host
+ * buffer `table` (at least *table_bytes; pinned memory keeps the copy
+ * asynchronous); the table holds device addresses inside `ws` (256-byte
+ * aligned, at least *ws_bytes), where the tick keeps its summaries and
+ * constants.  Host only: nothing is enqueued.  The table must stay untouched
+ * until the stream has passed the tick's copy. */
+int nlos_tick_plan(const nlos_tick_caps* caps, const nlos_sim_request* reqs, int32_t n, void* table,
+                   size_t table_bytes, void* ws, size_t ws_bytes);
+
+/* Enqueue a tick on `stream`: the copy of `table` into `ws`, then the three
+ * kernels (count and scatter persistent with a grid of 2 x CUs; pairs with
+ * one workgroup per item of the planned table).  Ticks that overlap in time
+ * need their own table and workspace. */
+int nlos_tick_launch(const nlos_tick_caps* caps, const void* table, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * The same tick as one HIP graph, instantiated once for a table and a
+ * workspace: create builds it (copy node, three kernel nodes; this is the
+ * only step that creates runtime objects), then each tick is nlos_tick_plan
+ * into `table` followed by nlos_tick_graph_launch, which sets the pair
+ * node's grid to the tick's item count (hipGraphExecKernelNodeSetParams)
+ * and launches the graph: one launch per tick, nothing allocated.  A graph
+ * and its table/workspace serve one tick at a time (wait for the previous
+ * launch to pass before planning the next); ticks in flight together need a
+ * graph each.  destroy frees the graph (NULL is a no-op).
+ */
+typedef struct nlos_tick_graph nlos_tick_graph;
+
+int nlos_tick_graph_create(const nlos_tick_caps* caps, const void* table, void* ws, size_t ws_bytes,
+                           nlos_tick_graph** graph);
+
+int nlos_tick_graph_launch(nlos_tick_graph* graph, void* stream);
+
+int nlos_tick_graph_destroy(nlos_tick_graph* graph);
 
 /*
  * Smooth time response and its adjoint (confocal only).  The hard forward

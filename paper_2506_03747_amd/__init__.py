@@ -24,11 +24,12 @@ import torch
 from ._native import TUNING_PATH  # noqa: F401
 from ._native import (NLOS_F_COSINES, NLOS_MAX_BINS, NLOS_MAX_PATCHES, NLOS_MAX_RADIUS,  # noqa: F401
                       NLOS_RECORD_FLOATS, DepthRequest, Grid, NlosError, Params, PlanInfo, Probe, Request,
-                      TuningEntry, check, lib, strerror)
+                      SimRequest, TickCaps, TuningEntry, check, lib, strerror)
 
 __all__ = ["Grid", "Params", "NlosError", "make_grid", "make_params", "params_of",
            "patches_from_depth", "forward", "simulate", "debug_bins", "out_shape", "n_histograms",
-           "Batcher", "patches_batched", "forward_batched", "forward_smooth", "adjoint", "patches_adjoint",
+           "Batcher", "patches_batched", "forward_batched", "TickGraph", "tick_supported", "forward_smooth",
+           "adjoint", "patches_adjoint",
            "SmoothTransient", "smooth_transient", "noise_scale", "poisson_noise", "add_poisson_noise",
            "lct_forward", "set_tuning", "get_plan", "load_tuning", "reset_tuning", "TUNING_PATH"]
 
@@ -309,6 +310,114 @@ def _run_batched(key, reqs, n, result, batcher, stream, sizes_fn, run_fn):
     if batcher is not None:
         batcher.mark(st)
     return result
+
+
+def tick_supported(params: Params, grid) -> bool:
+    """Whether a request can run in a serving tick: confocal, a map of at most
+    1024 enumeration blocks, and a plan that pairs units over the whole window."""
+    g = make_grid(grid)
+    if params.laser.nx != 0 or params.laser.ny != 0:
+        return False
+    if -(-g.nx // 16) * -(-g.ny // 16) * 256 > 1024 * 1024:
+        return False
+    plan = get_plan(params, g.nx * g.ny)
+    return plan["pair"] == 1 and plan["n_windows"] == 1
+
+
+class TickGraph:
+    """One serving-tick slot: a pinned host table, a device workspace and the
+    library's tick graph over them (instantiated once).  Per tick:
+    ``plan(requests)`` writes the table, ``launch(stream)`` launches the
+    graph (one launch; the pair node's grid follows the tick).  A slot holds
+    one tick at a time: plan the next only once the previous launch has
+    passed (``event`` is recorded behind each launch).
+
+    requests: dicts with params, grid, depth, albedo, mask and, optionally,
+    out, patches, n_active (allocated here on the current stream if absent).
+    ``graph=False`` launches the same four operations without the graph."""
+
+    def __init__(self, max_requests: int, max_pixels: int, device="cuda", graph: bool = True):
+        self.device = torch.device(device)
+        self.caps = TickCaps(int(max_requests), int(max_pixels))
+        tb, wb = C.c_size_t(0), C.c_size_t(0)
+        check(lib().nlos_tick_sizes(C.byref(self.caps), C.byref(tb), C.byref(wb)), "nlos_tick_sizes")
+        self.table = torch.empty(tb.value, dtype=torch.uint8, pin_memory=True)
+        self.ws = torch.empty(wb.value, dtype=torch.uint8, device=self.device)
+        self.event = None
+        self._handle = None
+        self._lib = lib()
+        if graph:
+            h = C.c_void_p()
+            check(self._lib.nlos_tick_graph_create(C.byref(self.caps), _ptr(self.table), _ptr(self.ws),
+                                                   self.ws.numel(), C.byref(h)), "nlos_tick_graph_create")
+            self._handle = h
+
+    @property
+    def bytes(self) -> int:
+        return self.ws.numel()
+
+    def busy(self) -> bool:
+        return self.event is not None and not self.event.query()
+
+    def plan(self, requests):
+        """Write the tick table for ``requests``; returns [(out, patches, n_active)]."""
+        n = len(requests)
+        arr = (SimRequest * max(n, 1))()
+        res = []
+        for i, r in enumerate(requests):
+            prm, g = r["params"], make_grid(r["grid"])
+            depth = _dev(r["depth"], torch.float32, "depth")
+            albedo = _dev(r.get("albedo"), torch.float32, "albedo")
+            mask = _dev(r.get("mask"), torch.uint8, "mask")
+            npx = g.nx * g.ny
+            for t, name in ((depth, "depth"), (albedo, "albedo"), (mask, "mask")):
+                if t is not None and t.numel() != npx:
+                    raise ValueError(f"{name} must have {g.nx}x{g.ny} elements")
+            out = r.get("out")
+            if out is None:
+                out = torch.empty(out_shape(prm), dtype=torch.float32, device=self.device)
+            patches = r.get("patches")
+            if patches is None:
+                patches = torch.empty((npx, NLOS_RECORD_FLOATS), dtype=torch.float32, device=self.device)
+            na = r.get("n_active")
+            if na is None:
+                na = torch.empty(1, dtype=torch.int32, device=self.device)
+            _dev(out, torch.float32, "out")
+            if out.numel() != n_histograms(prm) * prm.n_bins:
+                raise ValueError("out has the wrong size")
+            arr[i] = SimRequest(prm, g, depth.data_ptr(), None if albedo is None else albedo.data_ptr(),
+                                None if mask is None else mask.data_ptr(), patches.data_ptr(), na.data_ptr(),
+                                out.data_ptr())
+            res.append((out, patches, na))
+        if self.busy():
+            raise RuntimeError("tick slot still in flight")
+        check(self._lib.nlos_tick_plan(C.byref(self.caps), arr, n, _ptr(self.table), self.table.numel(),
+                                       _ptr(self.ws), self.ws.numel()), "nlos_tick_plan")
+        return res
+
+    def launch(self, stream=None):
+        st = torch.cuda.current_stream(self.device) if stream is None else stream
+        if self._handle is not None:
+            check(self._lib.nlos_tick_graph_launch(self._handle, C.c_void_p(st.cuda_stream)), "nlos_tick_graph_launch")
+        else:
+            check(self._lib.nlos_tick_launch(C.byref(self.caps), _ptr(self.table), _ptr(self.ws), self.ws.numel(),
+                                             C.c_void_p(st.cuda_stream)), "nlos_tick_launch")
+        self.event = torch.cuda.Event()
+        self.event.record(st)
+        return self.event
+
+    def close(self):
+        if self._handle is not None:
+            if self.event is not None:
+                self.event.synchronize()
+            self._lib.nlos_tick_graph_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
 
 
 def _ws(nbytes: int, device):

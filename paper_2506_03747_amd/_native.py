@@ -47,6 +47,15 @@ class Request(C.Structure):
                 ("n_active", C.c_void_p), ("out", C.c_void_p)]
 
 
+class SimRequest(C.Structure):
+    _fields_ = [("params", Params), ("grid", Grid), ("depth", C.c_void_p), ("albedo", C.c_void_p),
+                ("mask", C.c_void_p), ("patches", C.c_void_p), ("n_active", C.c_void_p), ("out", C.c_void_p)]
+
+
+class TickCaps(C.Structure):
+    _fields_ = [("max_requests", C.c_int32), ("max_pixels", C.c_int64)]
+
+
 class TuningEntry(C.Structure):
     _fields_ = [("confocal", C.c_int32), ("t_min", C.c_int32), ("t_max", C.c_int32), ("h_min", C.c_int64),
                 ("h_max", C.c_int64), ("tl", C.c_int32), ("tx", C.c_int32), ("ty", C.c_int32)]
@@ -100,6 +109,14 @@ SIGNATURES = [
      [C.POINTER(Request), C.c_int32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     ("nlos_forward_batched", C.c_int,
      [C.POINTER(Request), C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("nlos_tick_sizes", C.c_int, [C.POINTER(TickCaps), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    ("nlos_tick_plan", C.c_int,
+     [C.POINTER(TickCaps), C.POINTER(SimRequest), C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t]),
+    ("nlos_tick_launch", C.c_int, [C.POINTER(TickCaps), C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("nlos_tick_graph_create", C.c_int,
+     [C.POINTER(TickCaps), C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]),
+    ("nlos_tick_graph_launch", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("nlos_tick_graph_destroy", C.c_int, [C.c_void_p]),
     ("nlos_forward_smooth_workspace_bytes", C.c_int, [C.POINTER(Params), C.c_int32, C.POINTER(C.c_size_t)]),
     ("nlos_forward_smooth", C.c_int,
      [C.POINTER(Params), C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "nlos.h"
@@ -724,6 +725,104 @@ int lct_setup(const nlos_params* p, nlos::LctArgs* a, int64_t* n3)
     return NLOS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Serving ticks.  The table (host, then its copy at the start of the device
+// workspace): TickList, then per request GeomArgs, FwdArgs, variant and the
+// three block prefixes, then the tickets; the requests' counts, summaries
+// and pair-loop constants follow in the workspace.  Its size depends only on
+// the capacities, so every tick copies the same bytes.
+struct TickLayout {
+    size_t list, geom, fwd, variant, gfirst, zfirst, ffirst, tickets, table_bytes;
+};
+
+TickLayout tick_layout(int32_t max_requests)
+{
+    TickLayout t;
+    size_t off = 0;
+    const size_t m = (size_t)max_requests;
+    t.list = off;
+    off = align_up(off + sizeof(nlos::TickList), 16);
+    t.geom = off;
+    off = align_up(off + sizeof(nlos::GeomArgs) * m, 16);
+    t.fwd = off;
+    off = align_up(off + sizeof(nlos::FwdArgs) * m, 16);
+    t.variant = off;
+    off = align_up(off + 4 * m, 16);
+    t.gfirst = off;
+    off = align_up(off + 8 * (m + 1), 16);
+    t.zfirst = off;
+    off = align_up(off + 8 * (m + 1), 16);
+    t.ffirst = off;
+    off = align_up(off + 8 * (m + 1), 16);
+    t.tickets = off;
+    off = align_up(off + 16, 16);
+    t.table_bytes = align_up(off, 256);
+    return t;
+}
+
+bool caps_ok(const nlos_tick_caps* c)
+{
+    return c && c->max_requests >= 1 && c->max_requests <= 4096 && c->max_pixels >= 0 &&
+           c->max_pixels <= ((int64_t)1 << 31);
+}
+
+// Workspace bytes past the table for a map of npx pixels with n_blocks
+// enumeration blocks: block counts, summaries, pair-loop constants.
+size_t tick_request_bytes(int64_t npx, int64_t n_blocks)
+{
+    return align_up((size_t)n_blocks * 4, 256) + stats_bytes((int32_t)npx) + align_up((size_t)npx * 32, 256);
+}
+
+// The same for the capacities: n_blocks <= ceil(n_enum / 1024) with n_enum
+// <= npx + 16 (nx + ny) + 256 <= 17 npx + 256 summed over the requests.
+size_t tick_ws_bytes(const nlos_tick_caps* c)
+{
+    const TickLayout t = tick_layout(c->max_requests);
+    const size_t px = (size_t)c->max_pixels, m = (size_t)c->max_requests;
+    const size_t blocks = (17 * px + 256 * m) / nlos::kGeomBlock + m;
+    return t.table_bytes + align_up(blocks * 4, 256) + 256 * m +                     // counts
+           align_up((px / nlos::kStatBlock + m) * sizeof(nlos::ChunkStat), 256) + 256 * m +   // summaries
+           align_up(px * 32, 256) + 256 * m;                                          // constants
+}
+
+// Dynamic LDS of the tick's pair kernel: what any plan may use.
+constexpr size_t kTickLds = kLdsMax - 256;
+
+// Device addresses of the list and the pair kernel's arrays in a tick's workspace.
+nlos::TickArrays tick_arrays(void* ws, const TickLayout& t)
+{
+    unsigned char* d = static_cast<unsigned char*>(ws);
+    nlos::TickArrays a;
+    a.list = reinterpret_cast<const nlos::TickList*>(d + t.list);
+    a.fwd = reinterpret_cast<const nlos::FwdArgs*>(d + t.fwd);
+    a.variant = reinterpret_cast<const int32_t*>(d + t.variant);
+    a.ffirst = reinterpret_cast<const int64_t*>(d + t.ffirst);
+    return a;
+}
+
+// Pair-kernel items of a planned tick, read from its host table.
+int64_t tick_pair_items(const void* table, const TickLayout& t)
+{
+    const unsigned char* host = static_cast<const unsigned char*>(table);
+    const nlos::TickList* L = reinterpret_cast<const nlos::TickList*>(host + t.list);
+    return reinterpret_cast<const int64_t*>(host + t.ffirst)[L->n];
+}
+
+int g_cu_count[64] = {};
+
+int cu_count()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return kTargetBlocks;
+    if (g_cu_count[dev] <= 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = kTargetBlocks;
+        g_cu_count[dev] = n;
+    }
+    return g_cu_count[dev];
+}
+
 // Scratch of nlos_forward_noalloc: the record summaries, for up to
 // NLOS_NOALLOC_MAX_PATCHES records, in a file-scope device array (each GPU
 // the library runs on holds its own copy until the process ends).  Host code
@@ -762,6 +861,23 @@ void* scratch_on_current_device()
 }
 
 }  // namespace
+
+// A tick as a HIP graph: the table copy and the three kernels, instantiated
+// once; per tick only the pair kernel's grid (the tick's item count) is set
+// before the launch.
+struct nlos_tick_graph {
+    nlos_tick_caps caps;
+    const void* table = nullptr;
+    void* ws = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t pairs = nullptr;
+    hipKernelNodeParams pp;
+    nlos::TickArrays arr;                    // device addresses in the workspace
+    void* args[1] = {nullptr};               // geometry kernels' arguments: &arr.list
+    void* pair_args[4] = {nullptr, nullptr, nullptr, nullptr};   // the pair kernel's: &arr.*
+    int64_t launched_items = -1;             // grid the executable graph holds
+};
 
 extern "C" {
 
@@ -888,6 +1004,212 @@ int nlos_forward(const nlos_params* p, const float* patches, int32_t n_patches, 
         if (e != hipSuccess) return hip_fail(e);
     }
     e = nlos::launch_forward(a, plan, is_confocal(p), st);
+    return e == hipSuccess ? NLOS_OK : hip_fail(e);
+}
+
+int nlos_tick_sizes(const nlos_tick_caps* caps, size_t* table_bytes, size_t* ws_bytes)
+{
+    if (!caps_ok(caps) || !table_bytes || !ws_bytes) return NLOS_EINVAL;
+    *table_bytes = tick_layout(caps->max_requests).table_bytes;
+    *ws_bytes = tick_ws_bytes(caps);
+    return NLOS_OK;
+}
+
+int nlos_tick_plan(const nlos_tick_caps* caps, const nlos_sim_request* reqs, int32_t n, void* table,
+                   size_t table_bytes, void* ws, size_t ws_bytes)
+{
+    if (!caps_ok(caps) || n < 0 || n > caps->max_requests || (n > 0 && !reqs) || !table || !ws ||
+        !aligned(ws, 256))
+        return NLOS_EINVAL;
+    const TickLayout t = tick_layout(caps->max_requests);
+    if (table_bytes < t.table_bytes || ws_bytes < tick_ws_bytes(caps)) return NLOS_ENOSPC;
+    unsigned char* host = static_cast<unsigned char*>(table);
+    unsigned char* dev = static_cast<unsigned char*>(ws);
+    std::memset(host, 0, t.table_bytes);
+    nlos::GeomArgs* geom = reinterpret_cast<nlos::GeomArgs*>(host + t.geom);
+    nlos::FwdArgs* fwd = reinterpret_cast<nlos::FwdArgs*>(host + t.fwd);
+    int32_t* variant = reinterpret_cast<int32_t*>(host + t.variant);
+    int64_t* gfirst = reinterpret_cast<int64_t*>(host + t.gfirst);
+    int64_t* zfirst = reinterpret_cast<int64_t*>(host + t.zfirst);
+    int64_t* ffirst = reinterpret_cast<int64_t*>(host + t.ffirst);
+    int64_t pixels = 0;
+    double total = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const nlos_sim_request& r = reqs[i];
+        if (params_ok(&r.params) != NLOS_OK || !grid_ok(&r.grid)) return NLOS_EINVAL;
+        pixels += (int64_t)r.grid.nx * r.grid.ny;
+        total += (double)n_hist(&r.params) * (double)((int64_t)r.grid.nx * r.grid.ny);
+    }
+    if (pixels > caps->max_pixels) return NLOS_ENOSPC;
+    // per request: geometry (request order) and its forward plan; each
+    // request gets a share of the GPU's workgroups in proportion to its pairs
+    std::vector<nlos::FwdArgs> fa(n);
+    std::vector<nlos::Plan> pl(n);
+    std::vector<int32_t> var(n);
+    std::vector<double> work(n);
+    size_t off = t.table_bytes;
+    for (int i = 0; i < n; ++i) {
+        const nlos_sim_request& r = reqs[i];
+        nlos::GeomArgs& ga = geom[i];
+        int rc = geom_args(&r.grid, r.depth, r.albedo, r.mask, r.params.flags, r.patches, r.n_active, &ga);
+        if (rc != NLOS_OK) return rc;
+        // one pass per map: the scatter sums the counts before its block itself
+        if (ga.n_blocks > nlos::kScanFreeBlocks) return NLOS_EINVAL;
+        const int32_t npx = r.grid.nx * r.grid.ny;
+        const double pairs = (double)n_hist(&r.params) * (double)npx;
+        const int64_t target = std::max<int64_t>(1, (int64_t)std::ceil(kTargetBlocks * pairs / std::max(total, 1.0)));
+        size_t need = 0;
+        rc = setup_forward(&r.params, r.patches, npx, r.n_active, r.out, target, &fa[i], &pl[i], &need);
+        if (rc != NLOS_OK) return rc;
+        const nlos::Plan& plan = pl[i];
+        const int v = nlos::tick_variant(plan.tx, plan.ty, fa[i].cosines != 0);
+        if (!is_confocal(&r.params) || !plan.pair || plan.n_tw != 1 || v < 0 || plan.lds_bytes > kTickLds)
+            return NLOS_EINVAL;
+        var[i] = v;
+        work[i] = pairs / (double)std::max<int64_t>(1, plan.n_blocks);
+        // workspace regions of this request (device addresses)
+        ga.counts = reinterpret_cast<int32_t*>(dev + off);
+        ga.offsets = nullptr;
+        off += align_up((size_t)ga.n_blocks * 4, 256);
+        fa[i].stats = reinterpret_cast<nlos::ChunkStat*>(dev + off);
+        ga.stats = fa[i].stats;
+        ga.n_stats = fa[i].n_stats;
+        off += stats_bytes(npx);
+        ga.prep = reinterpret_cast<float4*>(dev + off);
+        ga.prep_sig = fa[i].inv2_f;
+        fa[i].prep = ga.prep;
+        off += align_up((size_t)npx * 32, 256);
+        if (off > ws_bytes) return NLOS_ENOSPC;
+        gfirst[i + 1] = gfirst[i] + ga.n_blocks;
+    }
+    // pair items in decreasing work per workgroup, so the longest
+    // workgroups start first and the tick ends with short ones
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+    for (int k = 0; k < n; ++k) {
+        const int i = order[k];
+        fwd[k] = fa[i];
+        variant[k] = var[i];
+        zfirst[k + 1] = zfirst[k] + (fa[i].atomic_out ? (fa[i].out_len + nlos::kTickFillFloats - 1) /
+                                                            nlos::kTickFillFloats : 0);
+        ffirst[k + 1] = ffirst[k] + pl[i].n_blocks;
+    }
+    nlos::TickList* L = reinterpret_cast<nlos::TickList*>(host + t.list);
+    L->geom = reinterpret_cast<const nlos::GeomArgs*>(dev + t.geom);
+    L->fwd = reinterpret_cast<const nlos::FwdArgs*>(dev + t.fwd);
+    L->variant = reinterpret_cast<const int32_t*>(dev + t.variant);
+    L->gfirst = reinterpret_cast<const int64_t*>(dev + t.gfirst);
+    L->zfirst = reinterpret_cast<const int64_t*>(dev + t.zfirst);
+    L->ffirst = reinterpret_cast<const int64_t*>(dev + t.ffirst);
+    L->n = n;
+    L->tickets = reinterpret_cast<unsigned int*>(dev + t.tickets);   // zero in the table
+    return NLOS_OK;
+}
+
+int nlos_tick_launch(const nlos_tick_caps* caps, const void* table, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!caps_ok(caps) || !table || !ws || !aligned(ws, 256)) return NLOS_EINVAL;
+    const TickLayout t = tick_layout(caps->max_requests);
+    if (ws_bytes < tick_ws_bytes(caps)) return NLOS_ENOSPC;
+    const int dev = device_check();
+    if (dev != NLOS_OK) return dev;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(ws, table, t.table_bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e);
+    const nlos::TickArrays arr = tick_arrays(ws, t);
+    e = nlos::launch_tick_geometry(arr.list, 2 * cu_count(), st);
+    if (e != hipSuccess) return hip_fail(e);
+    e = nlos::launch_tick_pairs(arr, std::max<int64_t>(1, tick_pair_items(table, t)), kTickLds, st);
+    return e == hipSuccess ? NLOS_OK : hip_fail(e);
+}
+
+int nlos_tick_graph_destroy(nlos_tick_graph* g)
+{
+    if (!g) return NLOS_OK;
+    hipError_t e = hipSuccess;
+    if (g->exec) e = hipGraphExecDestroy(g->exec);
+    if (g->graph) {
+        const hipError_t e2 = hipGraphDestroy(g->graph);
+        if (e == hipSuccess) e = e2;
+    }
+    delete g;
+    return e == hipSuccess ? NLOS_OK : hip_fail(e);
+}
+
+int nlos_tick_graph_create(const nlos_tick_caps* caps, const void* table, void* ws, size_t ws_bytes,
+                           nlos_tick_graph** out)
+{
+    if (!out) return NLOS_EINVAL;
+    *out = nullptr;
+    if (!caps_ok(caps) || !table || !ws || !aligned(ws, 256)) return NLOS_EINVAL;
+    if (ws_bytes < tick_ws_bytes(caps)) return NLOS_ENOSPC;
+    const int dev = device_check();
+    if (dev != NLOS_OK) return dev;
+    const TickLayout t = tick_layout(caps->max_requests);
+    nlos_tick_graph* g = new (std::nothrow) nlos_tick_graph();
+    if (!g) return NLOS_EHIP;
+    g->caps = *caps;
+    g->table = table;
+    g->ws = ws;
+    g->arr = tick_arrays(ws, t);
+    g->args[0] = &g->arr.list;
+    g->pair_args[0] = &g->arr.list;
+    g->pair_args[1] = &g->arr.fwd;
+    g->pair_args[2] = &g->arr.variant;
+    g->pair_args[3] = &g->arr.ffirst;
+    hipError_t e = nlos::prepare_tick_pairs(kTickLds);
+    if (e == hipSuccess) e = hipGraphCreate(&g->graph, 0);
+    hipGraphNode_t copy = nullptr, count = nullptr, scatter = nullptr;
+    if (e == hipSuccess)
+        e = hipGraphAddMemcpyNode1D(&copy, g->graph, nullptr, 0, ws, table, t.table_bytes, hipMemcpyHostToDevice);
+    hipKernelNodeParams kp;
+    std::memset(&kp, 0, sizeof(kp));
+    kp.gridDim = dim3((unsigned)(2 * cu_count()));
+    kp.blockDim = dim3(nlos::kGeomBlock);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = g->args;
+    kp.extra = nullptr;
+    if (e == hipSuccess) {
+        kp.func = const_cast<void*>(nlos::tick_count_kernel());
+        e = hipGraphAddKernelNode(&count, g->graph, &copy, 1, &kp);
+    }
+    if (e == hipSuccess) {
+        kp.func = const_cast<void*>(nlos::tick_scatter_kernel());
+        e = hipGraphAddKernelNode(&scatter, g->graph, &count, 1, &kp);
+    }
+    std::memset(&g->pp, 0, sizeof(g->pp));
+    g->pp.func = const_cast<void*>(nlos::tick_pairs_kernel());
+    g->pp.gridDim = dim3(1);
+    g->pp.blockDim = dim3(nlos::kBlock);
+    g->pp.sharedMemBytes = (unsigned)kTickLds;
+    g->pp.kernelParams = g->pair_args;
+    g->pp.extra = nullptr;
+    if (e == hipSuccess) e = hipGraphAddKernelNode(&g->pairs, g->graph, &scatter, 1, &g->pp);
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        nlos_tick_graph_destroy(g);
+        return hip_fail(e);
+    }
+    g->launched_items = 1;
+    *out = g;
+    return NLOS_OK;
+}
+
+int nlos_tick_graph_launch(nlos_tick_graph* g, void* stream)
+{
+    if (!g || !g->exec) return NLOS_EINVAL;
+    const TickLayout t = tick_layout(g->caps.max_requests);
+    const int64_t items = std::max<int64_t>(1, tick_pair_items(g->table, t));
+    if (items > 0x7fffffff) return NLOS_EINVAL;
+    hipError_t e = hipSuccess;
+    if (items != g->launched_items) {
+        g->pp.gridDim = dim3((unsigned)items);
+        e = hipGraphExecKernelNodeSetParams(g->exec, g->pairs, &g->pp);
+        if (e != hipSuccess) return hip_fail(e);
+        g->launched_items = items;
+    }
+    e = hipGraphLaunch(g->exec, (hipStream_t)stream);
     return e == hipSuccess ? NLOS_OK : hip_fail(e);
 }
 

@@ -329,9 +329,13 @@ __global__ void __launch_bounds__(kStatBlock) k_chunk_stats(const FwdArgs a, Chu
     chunk_stats_body(a, st, (int)blockIdx.x);
 }
 
-// Wall rectangles of unit u (approximate fp32 grid coordinates; only used for
-// work estimates and bounds): detector points [dx0,dx1]x[dy0,dy1], laser
-// points [lx0,lx1]x[ly0,ly1] (= detector rectangle, confocal).
+// Wall rectangles of the aligned block of histograms that holds unit u --
+// 4 x 4 scan points (confocal), or 2 lasers x 2 x 2 detectors -- in
+// approximate fp32 grid coordinates (only used for bounds): detector points
+// [dx0,dx1]x[dy0,dy1], laser points [lx0,lx1]x[ly0,ly1] (= the detector
+// rectangle, confocal).  Every supported unit shape tiles these blocks, so a
+// histogram's bound, and with it its fixed-point scale, is the same whatever
+// unit the plan chose (alone, batched or in a serving tick).
 struct UnitRect {
     float dx0, dx1, dy0, dy1, lx0, lx1, ly0, ly1;
 };
@@ -341,15 +345,23 @@ __device__ __forceinline__ float approx_coord(const Axis& ax, int i)
     return (float)ax.a0 + ((float)i + 0.5f) * (float)ax.step;
 }
 
+constexpr int kScaleBlockConf = 4;      // scan points per side of a confocal scale block
+constexpr int kScaleBlockNonconf = 2;   // detectors per side and lasers of a non-confocal one
+
 template <bool CONF, int TL, int TX, int TY>
 __device__ __forceinline__ UnitRect unit_rect(const FwdArgs& a, int u)
 {
+    static_assert(CONF ? (kScaleBlockConf % TX == 0 && kScaleBlockConf % TY == 0)
+                       : (kScaleBlockNonconf % TX == 0 && kScaleBlockNonconf % TY == 0 &&
+                          kScaleBlockNonconf % TL == 0),
+                  "units tile the scale blocks");
+    constexpr int B = CONF ? kScaleBlockConf : kScaleBlockNonconf;
     UnitRect R;
     const int uy = u % a.tiles_y;
     const int ux = (u / a.tiles_y) % a.tiles_x;
     const int ul = u / (a.tiles_y * a.tiles_x);
-    const int ix0 = ux * TX, ix1 = min(ix0 + TX, a.rx.n) - 1;
-    const int iy0 = uy * TY, iy1 = min(iy0 + TY, a.ry.n) - 1;
+    const int ix0 = (ux * TX) / B * B, ix1 = min(ix0 + B, a.rx.n) - 1;
+    const int iy0 = (uy * TY) / B * B, iy1 = min(iy0 + B, a.ry.n) - 1;
     R.dx0 = approx_coord(a.rx, ix0);
     R.dx1 = approx_coord(a.rx, ix1);
     R.dy0 = approx_coord(a.ry, iy0);
@@ -361,9 +373,10 @@ __device__ __forceinline__ UnitRect unit_rect(const FwdArgs& a, int u)
         R.ly1 = R.dy1;
     } else {
         const int n_laser = a.lx.n * a.ly.n;
+        const int l0 = (ul * TL) / B * B;
         R.lx0 = R.ly0 = 3.0e38f;
         R.lx1 = R.ly1 = -3.0e38f;
-        for (int l = ul * TL; l < min(ul * TL + TL, n_laser); ++l) {
+        for (int l = l0; l < min(l0 + B, n_laser); ++l) {
             const float x = approx_coord(a.lx, l / a.ly.n), y = approx_coord(a.ly, l % a.ly.n);
             R.lx0 = fminf(R.lx0, x);
             R.lx1 = fmaxf(R.lx1, x);
@@ -374,8 +387,9 @@ __device__ __forceinline__ UnitRect unit_rect(const FwdArgs& a, int u)
     return R;
 }
 
-// Upper bound of every pair weight of unit u: a_max / (r_l,min^2 r_d,min^2)
-// over the record summaries (cosine factors are at most 1).
+// Upper bound of every pair weight of unit u (of its scale block):
+// a_max / (r_l,min^2 r_d,min^2) over the record summaries (cosine factors
+// are at most 1).
 template <bool CONF, int TL, int TX, int TY>
 __device__ float unit_weight_bound(const FwdArgs& a, int u, const StatF& c)
 {
@@ -984,6 +998,67 @@ __global__ void __launch_bounds__(kBlock)
     const int i = batch_slot(first, n, (int64_t)blockIdx.x);
     const FwdArgs& a = tab[req[i]];
     forward_body<CONF, TL, TX, TY, COS, WIN, PAIR>(a, (int)((int64_t)blockIdx.x - first[i]));
+}
+
+// ---------------------------------------------------------------------------
+// Serving tick, pairs: one workgroup per (request, workgroup) item of the
+// tick's list; the workgroup runs its request's variant of the pair kernel.
+// (A persistent loop over claimed items keeps state live across items and
+// spills.)
+int tick_variant(int tx, int ty, bool cosines)
+{
+    int s = -1;
+    if (tx == 4 && ty == 4) s = 0;
+    else if (tx == 4 && ty == 2) s = 1;
+    else if (tx == 2 && ty == 2) s = 2;
+    else if (tx == 2 && ty == 1) s = 3;
+    else if (tx == 1 && ty == 1) s = 4;
+    return s < 0 ? -1 : s + (cosines ? 0 : kTickShapes);
+}
+
+// The list's arrays are restrict-qualified arguments (fixed addresses in the
+// tick's workspace): nothing the kernel stores can alias them, so the
+// request's arguments are read once with scalar loads.
+__global__ void __launch_bounds__(kBlock)
+    k_tick_pairs(const TickList* __restrict__ L, const FwdArgs* __restrict__ fwd,
+                 const int32_t* __restrict__ variant, const int64_t* __restrict__ ffirst)
+{
+    const int n = L->n;
+    const int64_t t = (int64_t)blockIdx.x;
+    if (n <= 0 || t >= ffirst[n]) return;
+    const int i = batch_slot(ffirst, n, t);
+    const FwdArgs& a = fwd[i];
+    const int blk = (int)(t - ffirst[i]);
+    switch (variant[i]) {
+    case 0: forward_body<true, 1, 4, 4, true, false, true>(a, blk); break;
+    case 1: forward_body<true, 1, 4, 2, true, false, true>(a, blk); break;
+    case 2: forward_body<true, 1, 2, 2, true, false, true>(a, blk); break;
+    case 3: forward_body<true, 1, 2, 1, true, false, true>(a, blk); break;
+    case 4: forward_body<true, 1, 1, 1, true, false, true>(a, blk); break;
+    case 5: forward_body<true, 1, 4, 4, false, false, true>(a, blk); break;
+    case 6: forward_body<true, 1, 4, 2, false, false, true>(a, blk); break;
+    case 7: forward_body<true, 1, 2, 2, false, false, true>(a, blk); break;
+    case 8: forward_body<true, 1, 2, 1, false, false, true>(a, blk); break;
+    case 9: forward_body<true, 1, 1, 1, false, false, true>(a, blk); break;
+    default: break;
+    }
+}
+
+const void* tick_pairs_kernel() { return (const void*)k_tick_pairs; }
+
+hipError_t prepare_tick_pairs(size_t lds_bytes)
+{
+    return hipFuncSetAttribute((const void*)k_tick_pairs, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+}
+
+hipError_t launch_tick_pairs(const TickArrays& t, int64_t grid, size_t lds_bytes, hipStream_t st)
+{
+    hipError_t e = prepare_tick_pairs(lds_bytes);
+    if (e != hipSuccess) return e;
+    if (grid < 1 || grid > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_tick_pairs, dim3((unsigned)grid), dim3(kBlock), lds_bytes, st, t.list, t.fwd, t.variant,
+                       t.ffirst);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -244,6 +244,76 @@ __global__ void __launch_bounds__(kGeomBlock) k_geom_scatter_batch(const GeomLis
     scatter_body(g.tab[i], (int)((int64_t)blockIdx.x - g.first[i]));
 }
 
+// ---------------------------------------------------------------------------
+// Serving tick, geometry: persistent workgroups claim items by ticket.  Count
+// pass items: every enumeration block of every map, then the zero-fill of
+// the outputs that take float atomics; scatter pass items: every block again
+// (a map's scatter reads the counts of its blocks before it, all written by
+// the count pass).  No item waits for another.
+__device__ __forceinline__ int64_t tick_claim(unsigned int* ctr)
+{
+    __shared__ unsigned int s_ticket;
+    __syncthreads();   // every thread has read the previous ticket (and left the previous item)
+    if (threadIdx.x == 0) s_ticket = atomicAdd(ctr, 1u);
+    __syncthreads();
+    return (int64_t)s_ticket;
+}
+
+__device__ __forceinline__ int tick_slot(const int64_t* first, int n, int64_t t)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(kGeomBlock) k_tick_count(const TickList* __restrict__ L)
+{
+    const int n = L->n;
+    const int64_t g_total = L->gfirst[n], z_total = L->zfirst[n];
+    for (;;) {
+        const int64_t t = tick_claim(L->tickets + 0);
+        if (t >= g_total + z_total) break;
+        if (t < g_total) {
+            const int i = tick_slot(L->gfirst, n, t);
+            count_body(L->geom[i], (int)(t - L->gfirst[i]));
+        } else {
+            const int64_t tz = t - g_total;
+            const int i = tick_slot(L->zfirst, n, tz);
+            const FwdArgs& a = L->fwd[i];
+            const int64_t b0 = (tz - L->zfirst[i]) * kTickFillFloats;
+            const int64_t b1 = min(b0 + kTickFillFloats, (int64_t)a.out_len);
+            for (int64_t k = b0 + threadIdx.x; k < b1; k += kGeomBlock) a.out[k] = 0.f;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kGeomBlock) k_tick_scatter(const TickList* __restrict__ L)
+{
+    const int n = L->n;
+    const int64_t g_total = L->gfirst[n];
+    for (;;) {
+        const int64_t t = tick_claim(L->tickets + 1);
+        if (t >= g_total) break;
+        const int i = tick_slot(L->gfirst, n, t);
+        scatter_body(L->geom[i], (int)(t - L->gfirst[i]));
+    }
+}
+
+const void* tick_count_kernel() { return (const void*)k_tick_count; }
+const void* tick_scatter_kernel() { return (const void*)k_tick_scatter; }
+
+hipError_t launch_tick_geometry(const TickList* list, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tick_count, dim3(grid), dim3(kGeomBlock), 0, st, list);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tick_scatter, dim3(grid), dim3(kGeomBlock), 0, st, list);
+    return hipGetLastError();
+}
+
 // Two launches (count, scatter) when the scatter can sum the counts itself
 // (a.offsets null), three (count, scan, scatter) otherwise.
 hipError_t launch_geometry(const GeomArgs& a, hipStream_t st)

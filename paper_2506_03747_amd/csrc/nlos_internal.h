@@ -147,6 +147,45 @@ struct GeomList {
     int32_t n;
 };
 
+// A serving tick: the records of a list of depth maps and their histograms,
+// by three persistent launches with fixed grids (count, scatter, pairs)
+// whose workgroups claim work items -- (request, block) pairs -- from
+// tickets.  The list lives in device memory, so the launches do not depend
+// on the requests and one captured graph serves every tick.
+// Pair-kernel variants a tick runs: confocal, two units per workgroup, the
+// five unit shapes, cosines on and off (tick_variant).
+constexpr int kTickShapes = 5;
+constexpr int kTickVariants = 2 * kTickShapes;
+constexpr int kTickFillFloats = 1 << 16;   // floats per zero-fill item
+struct TickList {
+    const GeomArgs* geom;     // [n] in request order
+    const FwdArgs* fwd;       // [n] in pair order: decreasing work per workgroup
+    const int32_t* variant;   // [n] pair order
+    const int64_t* gfirst;    // [n + 1] first enumeration block of each map (exclusive prefix, request order)
+    const int64_t* zfirst;    // [n + 1] first zero-fill item (outputs that take float atomics; pair order)
+    const int64_t* ffirst;    // [n + 1] first pair-kernel workgroup (pair order)
+    int32_t n;
+    int32_t pad;
+    unsigned int* tickets;    // [4]: count pass, scatter pass, pairs; zeroed by the table copy
+};
+int tick_variant(int tx, int ty, bool cosines);   // -1: not a tick variant
+hipError_t launch_tick_geometry(const TickList* list, int grid, hipStream_t st);
+// device addresses of a tick's list and of the arrays the pair kernel reads
+struct TickArrays {
+    const TickList* list;
+    const FwdArgs* fwd;
+    const int32_t* variant;
+    const int64_t* ffirst;
+};
+hipError_t launch_tick_pairs(const TickArrays& t, int64_t grid, size_t lds_bytes, hipStream_t st);
+hipError_t prepare_tick_pairs(size_t lds_bytes);
+// the tick's kernels, for graph nodes: count and scatter (persistent, grid
+// 2 x CUs, kGeomBlock threads; argument: the list), pairs (one workgroup per
+// item, kBlock threads; arguments: the four TickArrays pointers)
+const void* tick_count_kernel();
+const void* tick_scatter_kernel();
+const void* tick_pairs_kernel();
+
 // Smooth time response (continuous Gaussian) and its adjoint, confocal.
 struct SmoothArgs {
     const float4* patches;

@@ -118,9 +118,11 @@ def _approx_coords(g, axis):
     return (a0 + (np.arange(n, dtype=np.float32) + np.float32(0.5)) * step).astype(np.float64)
 
 
-def unit_weight_bounds(scene, rec, plan):
+def unit_weight_bounds(scene, rec):
     """W_u of every histogram ([L*S], output order) under the stated scale
-    rule, from fp64 records ``rec`` (oracle layout) and the launch plan."""
+    rule -- the bound of the aligned block of 4 x 4 scan points (confocal) or
+    2 lasers x 2 x 2 detectors that holds it -- from fp64 records ``rec``
+    (oracle layout)."""
     order = record_order(scene.patch_grid, rec[:, 7] != 0)
     R = rec[order]
     n = len(order)
@@ -132,7 +134,7 @@ def unit_weight_bounds(scene, rec, plan):
     x0, x1 = np.minimum.reduceat(R[:, 0], st), np.maximum.reduceat(R[:, 0], st)
     y0, y1 = np.minimum.reduceat(R[:, 1], st), np.maximum.reduceat(R[:, 1], st)
     z0, am = np.minimum.reduceat(R[:, 2], st), np.maximum.reduceat(R[:, 3], st)
-    tl, tx, ty = int(plan["tl"]), int(plan["tx"]), int(plan["ty"])
+    tl, tx, ty = (1, 4, 4) if scene.laser is None else (2, 2, 2)
     rx, ry = _approx_coords(scene.relay, "x"), _approx_coords(scene.relay, "y")
     nrx, nry = len(rx), len(ry)
     lpts = None
@@ -168,20 +170,17 @@ def unit_weight_bounds(scene, rec, plan):
     return W.reshape(-1)
 
 
-def parity_tolerance(scene, ref_tau, subset=None, rec=None, plan=None, floor=REL_L2_TOL):
+def parity_tolerance(scene, ref_tau, subset=None, rec=None, floor=REL_L2_TOL):
     """Per-histogram tolerance (see above) for the histograms ``subset`` (all
     when None) whose oracle output is ``ref_tau`` [n, T]."""
     from scipy import ndimage
-    import paper_2506_03747_amd as nl
     if rec is None:
         rec = oracle.patches(scene)
-    if plan is None:
-        plan = nl.get_plan(nl.params_of(scene), scene.n_patch_total)
     m = oracle.error_model(scene, rec, subset=subset)
     taps = oracle.taps(scene.fwhm_ps, scene.bin_ps)
     jerr = ndimage.convolve1d(m["err"], taps, axis=1, mode="constant")
     jcnt = ndimage.convolve1d(m["count"], taps, axis=1, mode="constant")
-    W = unit_weight_bounds(scene, rec, plan)
+    W = unit_weight_bounds(scene, rec)
     if subset is not None:
         W = W[np.asarray(subset)]
     # the kernel's bound is taken in fp32 from fp32 records: 1% margin

@@ -57,13 +57,27 @@ def test_admission_never_exceeds_budget_random(sv):
 def test_footprint_counts_maps_records_output(sv):
     sc = scenes.tiny(seed=3, scan=(5, 7), patches=(9, 11), n_bins=77)
     npx = 99
-    b = sv.footprint_bytes(sc)
+    b = sv.footprint_bytes(sc, with_workspace=False)
     out = 4 * 35 * 77
-    assert b >= 4 * npx + 4 * npx + npx + 32 * npx + out
-    assert b <= 4 * npx + 4 * npx + npx + 32 * npx + out + 4096
+    assert b == 4 * npx + 4 * npx + npx + 32 * npx + 4 + out
+    # the one-call workspace: 32 B of pair-loop constants per pixel, summaries, counts
+    w = sv.footprint_bytes(sc) - b
+    assert 32 * npx < w <= 33 * npx + 4096
     sc.mask = None
     sc.albedo = None
-    assert sv.footprint_bytes(sc) == b - 5 * npx
+    assert sv.footprint_bytes(sc, with_workspace=False) == b - 5 * npx
+
+
+def test_admission_pixel_cap(sv):
+    adm = sv.Admission(budget_bytes=1000, max_batch=10)
+    q = collections.deque(range(5))
+    sizes = [1] * 5
+    pixels = [40, 50, 0, 120, 30]
+    got, rej = adm.admit(q, sizes, pixels=pixels, max_pixels=100)
+    assert got == [0, 1, 2] and rej == [3]         # 40 + 50 + 0 <= 100; 120 alone passes the cap
+    assert list(q) == [4]                          # 40 + 50 + 30 would pass it: next tick
+    got, rej = adm.admit(q, sizes, pixels=pixels, max_pixels=100)
+    assert got == [4] and rej == []
 
 
 def test_poisson_arrivals(sv):
@@ -81,6 +95,7 @@ def test_server_rejects_bad_arrivals(sv):
     with pytest.raises(ValueError):
         sv.Server(mode="fast")
     s.budget, s.max_batch, s.depth, s.mode = 1 << 20, 4, 2, "batched"
+    s.tick_pixels, s.fixed_bytes, s.slots, s.streams = 1 << 20, 0, [], []
     with pytest.raises(ValueError):
         sv.Server.serve(s, [scenes.tiny(seed=1)] * 2, [0.2, 0.1], staged=[None, None])
 
