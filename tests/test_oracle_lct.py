@@ -26,6 +26,12 @@ LCT_MUTANTS = [
     ("time_point_sampling", "R[j, c] = ov / (2 * j + 1)", "R[j, c] = float(c == (hi - 1) // M)"),
     ("jitter_sigma", "sigma = fwhm_ps / (2.0 * math.sqrt(2.0 * math.log(2.0))) / bin_ps",
      "sigma = fwhm_ps / math.sqrt(2.0 * math.log(2.0)) / bin_ps"),
+    # constant-factor mistakes that every scale-free pin lets through
+    ("v_scaling_times_2", "/ v ** 1.5", "/ (2.0 * v ** 1.5)"),
+    ("time_bins_summed", "R[j, c] = ov / (2 * j + 1)", "R[j, c] = ov / (2 * j + 1) * 2.0"),
+    ("v_unit_scaled", "v = (J * dz) ** 2", "v = (J * dz * 1.25) ** 2"),
+    ("cone_scaled", "cone = (res == res.min(axis=2, keepdims=True)).astype(np.float64)",
+     "cone = 0.5 * (res == res.min(axis=2, keepdims=True)).astype(np.float64)"),
 ]
 
 
