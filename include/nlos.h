@@ -300,14 +300,13 @@ int nlos_forward_batched(const nlos_request* reqs, int32_t n, void* table, size_
  * list of requests, as a serving loop runs it once per tick (Algorithm 1
  * runs the forward model once per frame; many scenes share one tick here).
  * A tick is a fixed sequence of four operations on one stream: a copy of a
- * host table to the start of the workspace, then three persistent kernels
- * with fixed grids (depth-map counts and output zeroing; record scatter with
- * summaries and pair-loop constants; pairs, binning, guard, jitter and
- * write-out), whose workgroups claim (request, block) items from tickets in
- * the copied table.  The operations depend only on the capacities, not on
- * the requests, so a caller can capture nlos_tick_launch once in a HIP graph
- * (per table and workspace) and replay it every tick after rewriting the
- * table with nlos_tick_plan.  Each request's records, n_active and output are
+ * host table to the start of the workspace, then three kernels over the
+ * (request, block) items the copied table lists: depth-map counts and output
+ * zeroing, then record scatter with summaries and pair-loop constants (both
+ * persistent, a fixed grid of 2 x CUs striding over the items), then pairs,
+ * binning, guard, jitter and write-out (one workgroup per item).  Only the
+ * pair grid depends on the requests, so a tick is one HIP graph launch (see
+ * nlos_tick_graph_*) after rewriting the table with nlos_tick_plan.  Each request's records, n_active and output are
  * those of nlos_simulate for it alone, bit for bit (outputs that take float
  * atomics to 1e-6).
  * Supported requests: confocal, maps of at most 1024 x 1024 enumeration

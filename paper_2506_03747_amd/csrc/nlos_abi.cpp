@@ -728,11 +728,11 @@ int lct_setup(const nlos_params* p, nlos::LctArgs* a, int64_t* n3)
 // ---------------------------------------------------------------------------
 // Serving ticks.  The table (host, then its copy at the start of the device
 // workspace): TickList, then per request GeomArgs, FwdArgs, variant and the
-// three block prefixes, then the tickets; the requests' counts, summaries
+// three block prefixes; the requests' counts, summaries
 // and pair-loop constants follow in the workspace.  Its size depends only on
 // the capacities, so every tick copies the same bytes.
 struct TickLayout {
-    size_t list, geom, fwd, variant, gfirst, zfirst, ffirst, tickets, table_bytes;
+    size_t list, geom, fwd, variant, gfirst, zfirst, ffirst, table_bytes;
 };
 
 TickLayout tick_layout(int32_t max_requests)
@@ -754,8 +754,6 @@ TickLayout tick_layout(int32_t max_requests)
     off = align_up(off + 8 * (m + 1), 16);
     t.ffirst = off;
     off = align_up(off + 8 * (m + 1), 16);
-    t.tickets = off;
-    off = align_up(off + 16, 16);
     t.table_bytes = align_up(off, 256);
     return t;
 }
@@ -1103,7 +1101,6 @@ int nlos_tick_plan(const nlos_tick_caps* caps, const nlos_sim_request* reqs, int
     L->zfirst = reinterpret_cast<const int64_t*>(dev + t.zfirst);
     L->ffirst = reinterpret_cast<const int64_t*>(dev + t.ffirst);
     L->n = n;
-    L->tickets = reinterpret_cast<unsigned int*>(dev + t.tickets);   // zero in the table
     return NLOS_OK;
 }
 

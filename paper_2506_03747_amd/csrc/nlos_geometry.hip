@@ -245,20 +245,14 @@ __global__ void __launch_bounds__(kGeomBlock) k_geom_scatter_batch(const GeomLis
 }
 
 // ---------------------------------------------------------------------------
-// Serving tick, geometry: persistent workgroups claim items by ticket.  Count
-// pass items: every enumeration block of every map, then the zero-fill of
-// the outputs that take float atomics; scatter pass items: every block again
-// (a map's scatter reads the counts of its blocks before it, all written by
-// the count pass).  No item waits for another.
-__device__ __forceinline__ int64_t tick_claim(unsigned int* ctr)
-{
-    __shared__ unsigned int s_ticket;
-    __syncthreads();   // every thread has read the previous ticket (and left the previous item)
-    if (threadIdx.x == 0) s_ticket = atomicAdd(ctr, 1u);
-    __syncthreads();
-    return (int64_t)s_ticket;
-}
-
+// Serving tick, geometry: persistent workgroups take the items of a pass in
+// a fixed stride (item t goes to workgroup t mod grid; the items are
+// 1024-pixel blocks of equal cost, and a shared ticket counter would make
+// every claim a contended atomic).  Count pass items: every enumeration
+// block of every map, then the zero-fill of the outputs that take float
+// atomics; scatter pass items: every block again (a map's scatter reads the
+// counts of its blocks before it, all written by the count pass).  No item
+// waits for another.
 __device__ __forceinline__ int tick_slot(const int64_t* first, int n, int64_t t)
 {
     int lo = 0, hi = n - 1;
@@ -272,10 +266,9 @@ __device__ __forceinline__ int tick_slot(const int64_t* first, int n, int64_t t)
 __global__ void __launch_bounds__(kGeomBlock) k_tick_count(const TickList* __restrict__ L)
 {
     const int n = L->n;
+    if (n <= 0) return;
     const int64_t g_total = L->gfirst[n], z_total = L->zfirst[n];
-    for (;;) {
-        const int64_t t = tick_claim(L->tickets + 0);
-        if (t >= g_total + z_total) break;
+    for (int64_t t = blockIdx.x; t < g_total + z_total; t += gridDim.x) {
         if (t < g_total) {
             const int i = tick_slot(L->gfirst, n, t);
             count_body(L->geom[i], (int)(t - L->gfirst[i]));
@@ -287,18 +280,19 @@ __global__ void __launch_bounds__(kGeomBlock) k_tick_count(const TickList* __res
             const int64_t b1 = min(b0 + kTickFillFloats, (int64_t)a.out_len);
             for (int64_t k = b0 + threadIdx.x; k < b1; k += kGeomBlock) a.out[k] = 0.f;
         }
+        __syncthreads();   // the item's shared memory is free before the next one
     }
 }
 
 __global__ void __launch_bounds__(kGeomBlock) k_tick_scatter(const TickList* __restrict__ L)
 {
     const int n = L->n;
+    if (n <= 0) return;
     const int64_t g_total = L->gfirst[n];
-    for (;;) {
-        const int64_t t = tick_claim(L->tickets + 1);
-        if (t >= g_total) break;
+    for (int64_t t = blockIdx.x; t < g_total; t += gridDim.x) {
         const int i = tick_slot(L->gfirst, n, t);
         scatter_body(L->geom[i], (int)(t - L->gfirst[i]));
+        __syncthreads();   // the item's shared memory is free before the next one
     }
 }
 

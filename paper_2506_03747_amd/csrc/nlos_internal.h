@@ -148,10 +148,11 @@ struct GeomList {
 };
 
 // A serving tick: the records of a list of depth maps and their histograms,
-// by three persistent launches with fixed grids (count, scatter, pairs)
-// whose workgroups claim work items -- (request, block) pairs -- from
-// tickets.  The list lives in device memory, so the launches do not depend
-// on the requests and one captured graph serves every tick.
+// by three launches over a device work list of (request, block) items: the
+// count and scatter passes with fixed persistent grids, the pairs with one
+// workgroup per item.  The list lives in device memory, so the launches do
+// not depend on the requests (but for the pair grid) and one graph serves
+// every tick.
 // Pair-kernel variants a tick runs: confocal, two units per workgroup, the
 // five unit shapes, cosines on and off (tick_variant).
 constexpr int kTickShapes = 5;
@@ -166,7 +167,6 @@ struct TickList {
     const int64_t* ffirst;    // [n + 1] first pair-kernel workgroup (pair order)
     int32_t n;
     int32_t pad;
-    unsigned int* tickets;    // [4]: count pass, scatter pass, pairs; zeroed by the table copy
 };
 int tick_variant(int tx, int ty, bool cosines);   // -1: not a tick variant
 hipError_t launch_tick_geometry(const TickList* list, int grid, hipStream_t st);
