@@ -206,11 +206,12 @@ int make_plan(const nlos_params* p, int32_t n_patches, int R, int64_t target, nl
 
     // u64 bins per histogram row (at least tl + 1: bin tl is a spare that
     // takes the pairs just past the window), even, and reused by the flush as
-    // float rows padded with PAD = RM + 8 zeros on both sides (RM = the
-    // jitter radius rounded up to a compiled variant), so 2 * stride >= tl + 2 PAD
+    // a float row of flush_row_words(tl, RM) words (RM = the jitter radius
+    // rounded up to a compiled variant), so 2 * stride >= that
     const int RM = nlos::jitter_rm(R);
-    const int PAD = RM + 8;
-    auto stride_of = [PAD](int tl) { return std::max((tl + 2) & ~1, ((tl + 2 * PAD + 1) / 2 + 1) & ~1); };
+    auto stride_of = [RM](int tl) {
+        return std::max((tl + 2) & ~1, ((nlos::flush_row_words(tl, RM) + 1) / 2 + 1) & ~1);
+    };
     auto units_of = [&](const Cand& c) {
         return ((L + c.tl - 1) / c.tl) * (int64_t)((p->relay.nx + c.tx - 1) / c.tx) *
                (int64_t)((p->relay.ny + c.ty - 1) / c.ty);

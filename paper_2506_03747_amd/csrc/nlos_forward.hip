@@ -439,78 +439,8 @@ __device__ __forceinline__ void pick_units(const FwdArgs& a, int grp, int* u)
     u[1] = partner != grp ? partner : -1;
 }
 
-// Jitter of one row segment: each lane produces V consecutive outputs from a
-// register window of V + 2 RM values (V odd, so lanes read LDS words V apart
-// without bank conflicts); taps zero-padded to radius RM.  With a staging
-// area (64 V floats per wavefront, LDS), the segment's outputs are transposed
-// there so that every store instruction writes 64 consecutive floats.
-template <int RM>
-__device__ __forceinline__ void jitter_rows(const FwdArgs& a, const Lds& L, const float* F, const float* gp, int NS,
-                                            int P, int PAD, int hb, int t0w, int t1w, float* stg)
-{
-    constexpr int V = 5;
-    constexpr int K = 2 * RM + 1;
-    float g[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) g[k] = gp[k];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
-    const int nt = t1w - t0w;
-    const int seg = 64 * V;
-    const int nseg = (nt + seg - 1) / seg;
-    float* ws = stg ? stg + wave * seg : nullptr;
-    for (int sj = wave; sj < NS * nseg; sj += n_waves) {
-        const int j = sj / nseg, sidx = sj - j * nseg;
-        const long long row = L.row[j];
-        if (row < 0) continue;
-        const int ts = t0w + sidx * seg;                  // first output of the segment
-        const int t0 = ts + lane * V;
-        // H[x] = F[j P + PAD + x - hb]; window w[q] = H[t0 - RM + q] (lanes past
-        // the end read the window of t1w - 1, inside the padded row; their
-        // outputs are dropped)
-        const float* h = F + (size_t)j * P + PAD + ((t0 < t1w ? t0 : t1w - 1) - hb) - RM;
-        float w[V + 2 * RM];
-#pragma unroll
-        for (int q = 0; q < V + 2 * RM; ++q) w[q] = h[q];
-        const float gg = L.gg[j];
-        float acc[V];
-#pragma unroll
-        for (int m = 0; m < V; ++m) {
-            // out[t0 + m] = sum_k gp[k] H[t0 + m + RM - k]
-            float s = 0.f;
-#pragma unroll
-            for (int k = 0; k < K; ++k) s = fmaf(g[k], w[m + 2 * RM - k], s);
-            acc[m] = s * gg;
-        }
-        __attribute__((address_space(1))) float* orow = gmem(a.out) + (size_t)row * (size_t)a.T;
-        if (ws) {
-#pragma unroll
-            for (int m = 0; m < V; ++m) ws[lane * V + m] = acc[m];
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int m = 0; m < V; ++m) {
-                const int t = ts + m * 64 + lane;
-                const float v = ws[m * 64 + lane];
-                if (t < t1w) {
-                    if (a.atomic_out)
-                        unsafeAtomicAdd((float*)(orow + t), v);
-                    else
-                        orow[t] = v;
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
-        } else {
-#pragma unroll
-            for (int m = 0; m < V; ++m) {
-                if (t0 + m < t1w) {
-                    if (a.atomic_out)
-                        unsafeAtomicAdd((float*)(orow + t0 + m), acc[m]);
-                    else
-                        orow[t0 + m] = acc[m];
-                }
-            }
-        }
-    }
-}
+// floor(d / 8) for any sign, at compile time where d is a constant
+__host__ __device__ constexpr int floor_div8(int d) { return d >= 0 ? d / 8 : -((7 - d) / 8); }
 
 // A 64-bit fixed-point sum (low, high words) as fp32: exact enough, since the
 // sum is < 2^56 and only fp32 precision is kept.  The empty asm keeps each
@@ -522,135 +452,145 @@ __device__ __forceinline__ float u64_to_float(uint2 x)
     return fmaf((float)hi, 4294967296.0f, (float)lo);
 }
 
-// Flush: histograms (fixed point in LDS) -> float rows (zero-padded by PAD on
-// both sides, in place) -> Gaussian jitter -> output.  Values are moved
-// through registers (at most 160 KB / 8 bytes / 1024 threads = 20 per
-// thread), read in batches of 8 with no wait in between.
-template <int NS>
-__device__ __forceinline__ void flush(const FwdArgs& a, const Lds& L, int hb, int Tl, int t0w, int t1w, float tap)
+// Flush of the rows j = wave, wave + waves, ... of the workgroup, each by one
+// wavefront from start to end, so no other wavefront waits on it:
+//  1. the row's fixed-point bins become floats in the skewed layout, in place:
+//     the float row starts where the histogram row starts and never reaches
+//     past it, and a batch of eight 64-bin chunks is read before any float of
+//     it is written, while the floats of chunks up to c end before the words
+//     of chunk c + 1 begin (a wavefront's LDS operations run in order);
+//  2. zeros around the bins;
+//  3. the jitter for taps zero-padded to radius RM: lane l of a 64 V-output
+//     segment takes the V consecutive outputs from o0 = 64 V s + V l, reading
+//     its window of V + 2 RM words at compile-time offsets from one address
+//     (nine words apart from its neighbours: distinct banks); each output is
+//     sum_k g[k] H[t + RM - k], accumulated by fma in increasing k, and a
+//     complete, 16-byte aligned lane writes its V outputs as two 16-byte stores.
+template <int RM>
+__device__ __forceinline__ void flush_rows(const FwdArgs& a, const Lds& L, int NS, int Tl, int hb, int t0w,
+                                           int t1w)
 {
-    constexpr int kMaxPer = 24;
-    constexpr int kBatch = 8;
+    constexpr int V = kFlushV;
+    constexpr int K = 2 * RM + 1;
+    constexpr int W = V + 2 * RM;
+    constexpr int B0 = -RM + floor_div8(-RM);   // physical offset of window word 0 from output o0
     const int R = a.R;
-    const int RM = jitter_rm(R);
-    const int PAD = RM + 8;
-    const int P = Tl + 2 * PAD;
-    float* F = reinterpret_cast<float*>(L.hist);
+    const int RMr = RM > 16 ? jitter_rm(R) : RM;   // the radius the host sized the rows for
+    const int lead = flush_lead(RMr), Lr = flush_row_logical(Tl, RMr);
+    const int off = t0w - hb;                   // bin i of the row sits at logical word lead - off + i
+    const int lane = threadIdx.x & 63, n_waves = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    float g[K];
+    if (RM <= 16) {
+        const int sh = RM - R;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const float t = a.taps[min(max(k - sh, 0), 2 * R)];
+            g[k] = (k >= sh && k - sh <= 2 * R) ? t : 0.f;
+        }
+    }
+    const int nch = (Tl + 63) >> 6;
+    const int d = lane - off;                   // logical word of bin 64 c + lane: lead + 64 c + d
+    const int dp = d + floor_div8(d);
+    const int nt = t1w - t0w;
+    const int nseg = (nt + 64 * V - 1) / (64 * V);
+    const int o_last = (nt - 1) & ~(V - 1);     // window of the lanes past the end (inside the row)
+    const int np = Lr - Tl;
     const uint2* H2 = reinterpret_cast<const uint2*>(L.hist);
-    float* gp = reinterpret_cast<float*>(L.q);      // padded taps [2 RM + 1]
-    const int per = (NS * Tl + (int)blockDim.x - 1) / (int)blockDim.x;   // values per thread, uniform
-    const int sj = (int)blockDim.x / Tl, st = (int)blockDim.x % Tl;
-    const int j0 = (int)threadIdx.x / Tl, t0 = (int)threadIdx.x % Tl;
-    // value k of this thread: flat index threadIdx.x + k blockDim.x = (row j, bin t)
-    float v[kMaxPer];
-    if (st == 0) {
-        // Tl divides the workgroup: t fixed, j = j0 + k sj; rows past the last
-        // read the last row again (in bounds, never written back)
-        const int last = (NS - 1) * a.stride + t0, step = sj * a.stride;
-        int idx = j0 * a.stride + t0;
+    for (int j = wave; j < NS; j += n_waves) {
+        const long long row = L.row[j];
+        if (row < 0) continue;
+        float* Fr = reinterpret_cast<float*>(L.hist + (size_t)j * a.stride);
+        const uint2* Hr = H2 + (size_t)j * a.stride;
+        for (int c0 = 0; c0 < nch; c0 += 8) {
+            uint2 x[8];
 #pragma unroll
-        for (int k0 = 0; k0 < kMaxPer; k0 += kBatch) {
-            if (k0 >= per) break;
-            uint2 x[kBatch];
+            for (int b = 0; b < 8; ++b) x[b] = Hr[min((c0 + b) * 64 + lane, Tl - 1)];
 #pragma unroll
-            for (int k = 0; k < kBatch; ++k) {
-                x[k] = H2[min(idx, last)];
-                idx += step;
+            for (int b = 0; b < 8; ++b) {
+                const int xb = lead + 64 * (c0 + b);
+                if (c0 + b < nch && (c0 + b) * 64 + lane < Tl) Fr[xb + (xb >> 3) + dp] = u64_to_float(x[b]);
             }
-#pragma unroll
-            for (int k = 0; k < kBatch; ++k) v[k0 + k] = u64_to_float(x[k]);
         }
-    } else {
-        int j = j0, t = t0;
-#pragma unroll
-        for (int k0 = 0; k0 < kMaxPer; k0 += kBatch) {
-            if (k0 >= per) break;
-            uint2 x[kBatch];
-#pragma unroll
-            for (int k = 0; k < kBatch; ++k) {
-                x[k] = H2[__umul24((unsigned)min(j, NS - 1), (unsigned)a.stride) + t];
-                j += sj;
-                t += st;
-                if (t >= Tl) {
-                    t -= Tl;
-                    ++j;
+        for (int e = lane; e < np; e += 64) {
+            const int x = e < lead - off ? e : e + Tl;
+            Fr[x + (x >> 3)] = 0.f;
+        }
+        const float gg = L.gg[j];
+        if (RM > 16) {
+            // wide kernels: one output per lane, generic tap loop
+            for (int tt = lane; tt < nt; tt += 64) {
+                float acc = 0.f;
+                for (int i = 0; i <= 2 * R; ++i) {
+                    const int x = lead + tt + R - i;    // H[t + R - i]
+                    acc = fmaf(a.taps[i], Fr[x + (x >> 3)], acc);
                 }
+                acc *= gg;
+                __attribute__((address_space(1))) float* out = gmem(a.out) + (size_t)row * (size_t)a.T + t0w + tt;
+                if (a.atomic_out)
+                    unsafeAtomicAdd((float*)out, acc);
+                else
+                    *out = acc;
             }
-#pragma unroll
-            for (int k = 0; k < kBatch; ++k) v[k0 + k] = u64_to_float(x[k]);
+            continue;
         }
-    }
-    __syncthreads();
-    if (st == 0) {
-        const int nv = j0 < NS ? (NS - j0 + sj - 1) / sj : 0;   // values of this thread in the rows
-        const int fstep = sj * P;
-        int fidx = j0 * P + PAD + t0;
+        for (int s = 0; s < nseg; ++s) {
+            const int o0 = s * 64 * V + lane * V;
+            const int x0 = lead + min(o0, o_last);                 // logical word of output o0, 8 | x0
+            const float* h = Fr + (x0 + (x0 >> 3)) + B0;
+            float w[W];
 #pragma unroll
-        for (int k = 0; k < kMaxPer; ++k) {
-            if (k >= per) break;
-            if (k < nv) F[fidx] = v[k];
-            fidx += fstep;
-        }
-    } else {
-        int j = j0, t = t0;
+            for (int q = 0; q < W; ++q) w[q] = h[(q - RM) + floor_div8(q - RM) - B0];
+            float acc[V];
 #pragma unroll
-        for (int k = 0; k < kMaxPer; ++k) {
-            if (k >= per) break;
-            if (j < NS) F[__umul24((unsigned)j, (unsigned)P) + PAD + t] = v[k];
-            j += sj;
-            t += st;
-            if (t >= Tl) {
-                t -= Tl;
-                ++j;
+            for (int m = 0; m < V; ++m) {
+                float sum = 0.f;
+#pragma unroll
+                for (int k = 0; k < K; ++k) sum = fmaf(g[k], w[m + 2 * RM - k], sum);
+                acc[m] = sum * gg;
+            }
+            if (o0 >= nt) continue;
+            const size_t first = (size_t)row * (size_t)a.T + (size_t)(t0w + o0);
+            __attribute__((address_space(1))) float* orow = gmem(a.out) + first;
+            if (a.atomic_out) {
+#pragma unroll
+                for (int m = 0; m < V; ++m)
+                    if (o0 + m < nt) unsafeAtomicAdd((float*)(orow + m), acc[m]);
+            } else if (o0 + V <= nt && (first & 3) == 0) {
+                typedef float v4f __attribute__((ext_vector_type(4)));
+                typedef __attribute__((address_space(1))) v4f gv4f;
+                reinterpret_cast<gv4f*>(orow)[0] = v4f{acc[0], acc[1], acc[2], acc[3]};
+                reinterpret_cast<gv4f*>(orow)[1] = v4f{acc[4], acc[5], acc[6], acc[7]};
+            } else {
+#pragma unroll
+                for (int m = 0; m < V; ++m)
+                    if (o0 + m < nt) orow[m] = acc[m];
             }
         }
     }
-    for (int i = threadIdx.x; i < NS * 2 * PAD; i += blockDim.x) {
-        const int j = i / (2 * PAD), e = i - j * 2 * PAD;
-        F[(size_t)j * P + (e < PAD ? e : Tl + e)] = 0.f;
-    }
-    if ((int)threadIdx.x < 2 * RM + 1) gp[threadIdx.x] = tap;
-    __syncthreads();
-    // staging for coalesced stores: the part of the histogram rows the float
-    // rows leave free, when it holds 64 V floats per wavefront
-    const int free_f = NS * (2 * a.stride - P);
-    float* stg = free_f >= (int)blockDim.x * 5 ? F + NS * P : nullptr;
+}
+
+// Flush: histograms (fixed point in LDS) -> float rows -> Gaussian jitter ->
+// output, after every pair of the workgroup has been added (the caller's
+// barrier); one compiled radius per rounded jitter radius.
+template <int NS>
+__device__ __forceinline__ void flush(const FwdArgs& a, const Lds& L, int hb, int Tl, int t0w, int t1w)
+{
+    const int RM = jitter_rm(a.R);
     if (RM == 2) {
-        jitter_rows<2>(a, L, F, gp, NS, P, PAD, hb, t0w, t1w, stg);
+        flush_rows<2>(a, L, NS, Tl, hb, t0w, t1w);
     } else if (RM == 4) {
-        jitter_rows<4>(a, L, F, gp, NS, P, PAD, hb, t0w, t1w, stg);
+        flush_rows<4>(a, L, NS, Tl, hb, t0w, t1w);
     } else if (RM == 6) {
-        jitter_rows<6>(a, L, F, gp, NS, P, PAD, hb, t0w, t1w, stg);
+        flush_rows<6>(a, L, NS, Tl, hb, t0w, t1w);
     } else if (RM == 8) {
-        jitter_rows<8>(a, L, F, gp, NS, P, PAD, hb, t0w, t1w, stg);
+        flush_rows<8>(a, L, NS, Tl, hb, t0w, t1w);
     } else if (RM == 12) {
-        jitter_rows<12>(a, L, F, gp, NS, P, PAD, hb, t0w, t1w, stg);
+        flush_rows<12>(a, L, NS, Tl, hb, t0w, t1w);
     } else if (RM == 16) {
-        jitter_rows<16>(a, L, F, gp, NS, P, PAD, hb, t0w, t1w, stg);
+        flush_rows<16>(a, L, NS, Tl, hb, t0w, t1w);
     } else {
-        // wide kernels: one output per lane, generic tap loop
-        const int nt = t1w - t0w;
-        const int sj2 = (int)blockDim.x / nt, st2 = (int)blockDim.x % nt;
-        int j = (int)threadIdx.x / nt, tt = (int)threadIdx.x % nt;
-        for (; j < NS; j += sj2, tt += st2) {
-            if (tt >= nt) {
-                tt -= nt;
-                ++j;
-                if (j >= NS) break;
-            }
-            const long long row = L.row[j];
-            if (row < 0) continue;
-            const int t = t0w + tt;
-            const float* h = F + (size_t)j * P + PAD + (t - hb) + R;   // h[-i] = H[t + R - i]
-            float acc = 0.f;
-            for (int i = 0; i <= 2 * R; ++i) acc = fmaf(gp[i], h[-i], acc);
-            acc *= L.gg[j];
-            __attribute__((address_space(1))) float* out = gmem(a.out) + (size_t)row * (size_t)a.T + t;
-            if (a.atomic_out)
-                unsafeAtomicAdd((float*)out, acc);
-            else
-                *out = acc;
-        }
+        flush_rows<17>(a, L, NS, Tl, hb, t0w, t1w);   // any radius past 16: the generic tap loop
     }
 }
 
@@ -693,20 +633,16 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
 
     for (int i = threadIdx.x; i < NS * a.stride / 2; i += blockDim.x) reinterpret_cast<uint4*>(L.hist)[i] = uint4{0, 0, 0, 0};
     if (threadIdx.x == 0) *L.next = 0u;
-    // the flush's jitter tap of this thread (taps zero-padded to radius RM)
-    float tap = 0.f;
-    {
-        const int RM = jitter_rm(a.R), i = (int)threadIdx.x - (RM - a.R);
-        if ((int)threadIdx.x < 2 * RM + 1 && i >= 0 && i <= 2 * a.R) tap = a.taps[i];
-    }
     if (threadIdx.x < NS) {
         const int j = threadIdx.x;
         const int k = j / NH, jl = j % NH;
-        const int u = uvalid[k] ? unit[k] : unit[0];
+        // (NU <= 2: selects, so that the small arrays stay in registers)
+        const bool kv = k == 0 ? uvalid[0] : uvalid[NU - 1];
+        const int u = kv ? (k == 0 ? unit[0] : unit[NU - 1]) : unit[0];
         const int uy = u % a.tiles_y, ux = (u / a.tiles_y) % a.tiles_x, ul = u / (a.tiles_y * a.tiles_x);
         const int dj = jl % ND;
         const int ix_u = ux * TX + dj / TY, iy_u = uy * TY + dj % TY, l_u = ul * TL + jl / ND;
-        L.row[j] = (uvalid[k] && ix_u < a.rx.n && iy_u < a.ry.n && l_u < (CONF ? 1 : n_laser))
+        L.row[j] = (kv && ix_u < a.rx.n && iy_u < a.ry.n && l_u < (CONF ? 1 : n_laser))
                        ? ((long long)l_u * a.rx.n + ix_u) * a.ry.n + iy_u
                        : -1ll;
         const int ix = min(ix_u, a.rx.n - 1);
@@ -753,7 +689,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
     float sk[NU];
 #pragma unroll
     for (int k = 0; k < NU; ++k) sk[k] = wbk[k] > 0.f ? 2147483648.0f / wbk[k] : 1.0f;
-    if (threadIdx.x < NS) L.gg[threadIdx.x] *= 1.0f / sk[threadIdx.x / NH];
+    if (threadIdx.x < NS) L.gg[threadIdx.x] *= 1.0f / ((int)threadIdx.x < NH ? sk[0] : sk[NU - 1]);
     // the pair loop works in bins: coordinates times sig, so its weights
     // carry sig^-4, which the scale it applies takes back
     const float sig = CONF ? a.inv2_f : a.inv_f;
@@ -965,7 +901,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
     guard_drain<CONF>(L, a, hb, Tl, wave, qw, qn);
     if (a.eval_pairs && lane == 0) atomicAdd(a.eval_pairs, (unsigned long long)n_eval);
     __syncthreads();
-    flush<NS>(a, L, hb, Tl, t0w, t1w, tap);
+    flush<NS>(a, L, hb, Tl, t0w, t1w);
 }
 
 template <bool CONF, int TL, int TX, int TY, bool COS, bool WIN, bool PAIR>

@@ -18,6 +18,18 @@ __host__ __device__ inline int jitter_rm(int R)
 {
     return R <= 2 ? 2 : (R <= 4 ? 4 : (R <= 6 ? 6 : (R <= 8 ? 8 : (R <= 12 ? 12 : (R <= 16 ? 16 : R)))));
 }
+
+// The flush turns each histogram row into a float row in the same LDS: logical
+// word x (zeros, the bins, zeros) is stored at physical word x + floor(x / 8),
+// one spare word per eight, so that lanes reading eight consecutive words
+// apiece (a stride of nine) hit distinct banks.  Output t0w + o of the row
+// sits at logical word flush_lead + o.  The host sizes histogram rows so that
+// a float row fits in the bytes of its histogram row.
+constexpr int kFlushV = 8;   // consecutive outputs per lane
+__host__ __device__ inline int flush_lead(int RM) { return ((RM + 7) & ~7) + 8; }
+__host__ __device__ inline int flush_row_logical(int tl, int RM) { return (flush_lead(RM) + tl + RM + 8 + 7) & ~7; }
+__host__ __device__ inline int flush_row_words(int tl, int RM) { return flush_row_logical(tl, RM) / 8 * 9; }
+
 constexpr int kBlock = 1024;           // threads per workgroup of the pair kernels
 constexpr int kBlockPx = 16;           // record order: 16x16-pixel blocks, 4 stride-2 phases
 

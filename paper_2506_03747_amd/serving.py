@@ -172,7 +172,7 @@ class Server:
     per tick through nlos_simulate, on one stream."""
 
     def __init__(self, budget_bytes: int = 2 << 30, max_batch: int = 32, depth: int = 3,
-                 mode: str = "batched", device="cuda", max_tick_pairs: float = 2e9,
+                 mode: str = "batched", device="cuda", max_tick_pairs: float = 1e9,
                  tick_pixels: int = 1 << 21):
         if mode not in ("batched", "plain"):
             raise ValueError("mode is 'batched' or 'plain'")
