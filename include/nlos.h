@@ -310,7 +310,7 @@ int nlos_forward_batched(const nlos_request* reqs, int32_t n, void* table, size_
  * those of nlos_simulate for it alone, bit for bit (outputs that take float
  * atomics to 1e-6).
  * Supported requests: confocal, maps of at most 1024 x 1024 enumeration
- * pixels (1024 blocks of 1024), plans that pair units over the whole window
+ * pixels (4096 blocks of 256), plans that pair units over the whole window
  * (nlos_get_plan pair = 1, n_windows = 1); anything else is NLOS_EINVAL
  * from nlos_tick_plan (serve it through nlos_simulate).
  */

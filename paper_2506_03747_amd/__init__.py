@@ -314,11 +314,12 @@ def _run_batched(key, reqs, n, result, batcher, stream, sizes_fn, run_fn):
 
 def tick_supported(params: Params, grid) -> bool:
     """Whether a request can run in a serving tick: confocal, a map of at most
-    1024 enumeration blocks, and a plan that pairs units over the whole window."""
+    4096 enumeration blocks of 256 pixels, and a plan that pairs units over the
+    whole window."""
     g = make_grid(grid)
     if params.laser.nx != 0 or params.laser.ny != 0:
         return False
-    if -(-g.nx // 16) * -(-g.ny // 16) * 256 > 1024 * 1024:
+    if -(-g.nx // 16) * -(-g.ny // 16) * 256 > 4096 * 256:
         return False
     plan = get_plan(params, g.nx * g.ny)
     return plan["pair"] == 1 and plan["n_windows"] == 1

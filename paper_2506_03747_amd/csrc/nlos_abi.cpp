@@ -772,7 +772,7 @@ size_t tick_request_bytes(int64_t npx, int64_t n_blocks)
     return align_up((size_t)n_blocks * 4, 256) + stats_bytes((int32_t)npx) + align_up((size_t)npx * 32, 256);
 }
 
-// The same for the capacities: n_blocks <= ceil(n_enum / 1024) with n_enum
+// The same for the capacities: n_blocks <= ceil(n_enum / kGeomBlock) with n_enum
 // <= npx + 16 (nx + ny) + 256 <= 17 npx + 256 summed over the requests.
 size_t tick_ws_bytes(const nlos_tick_caps* c)
 {

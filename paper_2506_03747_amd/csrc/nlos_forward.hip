@@ -607,11 +607,26 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
     extern __shared__ __align__(16) unsigned char smem[];
     const Lds L = lds_layout(smem, NS, a.stride, a.q_cap);
     // the global reads of the set-up first, so that their latency overlaps the
-    // LDS clear and the tables below
+    // LDS clear and the tables below: the count, the summaries and, with one
+    // patch range (it starts at record 0), the records of the wavefront's
+    // first chunk.  A wavefront's first two chunks are 2 w and 2 w + 1; the
+    // later ones come from a counter in LDS.  The first chunk is read before
+    // the count is known, so lanes past the capacity read the last slot and
+    // lanes past the count are replaced by the stand-in record in the loop.
     const int n_act = active_count(a);
     StatF st0;
     st0.count = 0;
     if ((int)threadIdx.x < a.n_stats) st0 = load_stat(a.stats, threadIdx.x);
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    const bool prep = a.prep != nullptr;
+    const float4* src = prep ? a.prep : a.patches;
+    const bool early = a.n_split == 1 && a.n_cap > 0;
+    float4 An = make_float4(0.f, 0.f, 0.f, 0.f), Bn = An;
+    if (early) {
+        const int pl = min(2 * wave * 64 + lane, a.n_cap - 1);
+        An = load4(src, 2 * (size_t)pl);
+        Bn = load3(src, 2 * (size_t)pl + 1);
+    }
 
     int id = block_id;
     const int split = id % a.n_split;
@@ -632,7 +647,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
     for (int k = 0; k < NU; ++k) uvalid[k] = unit[k] >= 0;
 
     for (int i = threadIdx.x; i < NS * a.stride / 2; i += blockDim.x) reinterpret_cast<uint4*>(L.hist)[i] = uint4{0, 0, 0, 0};
-    if (threadIdx.x == 0) *L.next = 0u;
+    if (threadIdx.x == 0) *L.next = 2u * (blockDim.x >> 6);
     if (threadIdx.x < NS) {
         const int j = threadIdx.x;
         const int k = j / NH, jl = j % NH;
@@ -752,7 +767,6 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
         cut_r2[k] = rc * rc * 1.00001f;
     }
 
-    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
     const int qw = a.q_cap / kQueueWaves;
     int qn = 0;
     // Wavefronts take 64-record chunks from a counter in LDS, so they finish
@@ -760,17 +774,12 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
     // two: the records of the next one are loaded while the current one is
     // evaluated, and the one after is claimed meanwhile.
     int n_eval = 0;   // pairs evaluated by this wavefront (counted only on request)
-    int chunk_id = 0;
-    if (lane == 0) chunk_id = (int)atomicAdd(L.next, 2u);
-    chunk_id = __builtin_amdgcn_readfirstlane(chunk_id);
+    int chunk_id = __builtin_amdgcn_readfirstlane(2 * wave);
     int next_id = chunk_id + 1;
     // records as written by the geometry, or (prep) their pair-loop
     // constants, which the one-call path writes beside them
-    const bool prep = a.prep != nullptr;
-    const float4* src = prep ? a.prep : a.patches;
     const float dummy_px = a.dummy_x * sig;
-    float4 An = make_float4(0.f, 0.f, 0.f, 0.f), Bn = An;
-    if (pb + chunk_id * 64 < pe) {
+    if (!early && pb + chunk_id * 64 < pe) {
         const int pl = min(pb + chunk_id * 64 + lane, pe - 1);
         An = load4(src, 2 * (size_t)pl);
         Bn = load3(src, 2 * (size_t)pl + 1);
@@ -778,24 +787,25 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
     for (;;) {
         const int base = pb + chunk_id * 64;
         if (base >= pe) break;
-        // lanes past the range read the last record, moved to dummy_x: every
-        // arrival of that position lies past the window
+        // lanes past the range take a stand-in record at x = dummy_x with
+        // zero weight: every arrival of that position lies past the window
         const int p = base + lane;
+        const bool stand_in = p >= pe;
         PatchC pc;
         float aw;
         if (prep) {
-            pc.px = p >= pe ? dummy_px : An.x;
-            pc.py = An.y;
-            pc.pz2 = An.z;
-            pc.ap = An.w;
-            pc.mnxs = Bn.x;
-            pc.mnys = Bn.y;
-            pc.c0s = Bn.z;
-            aw = An.w;
+            pc.px = stand_in ? dummy_px : An.x;
+            pc.py = stand_in ? 0.f : An.y;
+            pc.pz2 = stand_in ? 1.f : An.z;
+            pc.ap = stand_in ? 0.f : An.w;
+            pc.mnxs = stand_in ? 0.f : Bn.x;
+            pc.mnys = stand_in ? 0.f : Bn.y;
+            pc.c0s = stand_in ? 0.f : Bn.z;
+            aw = pc.ap;
         } else {
-            float4 A = An;
-            if (p >= pe) A.x = a.dummy_x;
-            pc = patch_consts_scaled(A, Bn, COS, sig);
+            const float4 A = stand_in ? make_float4(a.dummy_x, 0.f, 1.f, 0.f) : An;
+            const float4 B = stand_in ? make_float4(0.f, 0.f, -1.f, 0.f) : Bn;
+            pc = patch_consts_scaled(A, B, COS, sig);
             aw = A.w;
         }
         // records of the next chunk, into the registers the current ones

@@ -247,7 +247,7 @@ __global__ void __launch_bounds__(kGeomBlock) k_geom_scatter_batch(const GeomLis
 // ---------------------------------------------------------------------------
 // Serving tick, geometry: persistent workgroups take the items of a pass in
 // a fixed stride (item t goes to workgroup t mod grid; the items are
-// 1024-pixel blocks of equal cost, and a shared ticket counter would make
+// 256-pixel blocks of equal cost, and a shared ticket counter would make
 // every claim a contended atomic).  Count pass items: every enumeration
 // block of every map, then the zero-fill of the outputs that take float
 // atomics; scatter pass items: every block again (a map's scatter reads the

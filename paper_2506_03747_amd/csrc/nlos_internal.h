@@ -63,7 +63,7 @@ struct GeomArgs {
     float4* prep;          // nullable: [n][2] the pair loop's per-record constants
     float prep_sig;        // the pair loop's bins per metre (its scale of coordinates)
 };
-constexpr int kGeomBlock = 1024;
+constexpr int kGeomBlock = 256;
 
 // Summary of kStatBlock consecutive patch records: lateral bounding box,
 // smallest depth, largest a, record count.  Used to bound the pair weights
@@ -284,7 +284,7 @@ size_t lds_bytes_for(int slots, int stride, int q_cap);
 bool tile_supported(bool confocal, int tx, int ty, int tl);
 
 hipError_t launch_geometry(const GeomArgs& a, hipStream_t st);
-constexpr int kScanFreeBlocks = 1024;   // up to this many blocks, the scatter sums the counts itself
+constexpr int kScanFreeBlocks = 4096;   // up to this many blocks, the scatter sums the counts itself
 hipError_t launch_forward(const FwdArgs& a, const Plan& plan, bool confocal, hipStream_t st);
 hipError_t launch_stats(const FwdArgs& a, ChunkStat* stats, hipStream_t st);
 hipError_t launch_fill(float* out, size_t n, hipStream_t st);

@@ -37,8 +37,9 @@ from ._native import NLOS_RECORD_FLOATS
 
 RECORD_BYTES = 4 * NLOS_RECORD_FLOATS
 # one-call workspace per pixel: the records' pair-loop constants (32 B), the
-# summaries (32 B per 256 records) and the block counts, rounded up
-SIM_WS_PER_PIXEL = 32.0 + 32.0 / 256.0 + 8.0 / 1024.0
+# summaries (32 B per 256 records) and the block counts (4 B per 256-pixel
+# block), rounded up
+SIM_WS_PER_PIXEL = 32.0 + 32.0 / 256.0 + 8.0 / 256.0
 
 
 def _pixels(req) -> int:
@@ -150,7 +151,7 @@ class _Tick:
 
 
 # Launches of one request served alone through nlos_simulate: geometry count
-# and scatter, the pair kernel (the scan kernel past 1024 blocks, the zero
+# and scatter, the pair kernel (the scan kernel past 4096 blocks, the zero
 # fill when patches are split are not counted).
 PLAIN_LAUNCHES = 3
 
