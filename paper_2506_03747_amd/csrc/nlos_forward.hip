@@ -148,7 +148,7 @@ __device__ __forceinline__ void block_max(float* v, float* red)
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         float m = 0.f;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, red[w * N + k]);
+        for (int w = 0; w < kBlock / 64; ++w) m = fmaxf(m, red[w * N + k]);
         v[k] = m;
     }
 }
@@ -180,14 +180,18 @@ __device__ __forceinline__ float4 load3(const float4* p, size_t i)
     return make_float4(v.x, v.y, v.z, 0.f);
 }
 
+// Stands in for a missing device count, so that the count is always one
+// load with no branch before it (the kernels' first argument reads then go
+// out together instead of one after another).
+__device__ const int32_t kNoCount = 0x7fffffff;
+
 __device__ __forceinline__ int active_count(const FwdArgs& a)
 {
-    int n = a.n_cap;
-    if (a.n_active) {
-        n = *gmem(a.n_active);
-        n = n < 0 ? 0 : (n > a.n_cap ? a.n_cap : n);
-    }
-    return n;
+    // a scalar read: the count was written before this kernel started and
+    // does not change while it runs (kernel start invalidates the scalar cache)
+    const int32_t* c = a.n_active ? a.n_active : &kNoCount;
+    const int n = *(const __attribute__((address_space(4))) int32_t*)(c);
+    return n < 0 ? 0 : (n > a.n_cap ? a.n_cap : n);
 }
 
 __device__ __forceinline__ void lds_sub(u64* p, uint32_t dec)
@@ -478,7 +482,7 @@ __device__ __forceinline__ void flush_rows(const FwdArgs& a, const Lds& L, int N
     const int RMr = RM > 16 ? jitter_rm(R) : RM;   // the radius the host sized the rows for
     const int lead = flush_lead(RMr), Lr = flush_row_logical(Tl, RMr);
     const int off = t0w - hb;                   // bin i of the row sits at logical word lead - off + i
-    const int lane = threadIdx.x & 63, n_waves = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, n_waves = kBlock / 64;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float g[K];
     if (RM <= 16) {
@@ -606,17 +610,23 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
     constexpr int NS = NU * NH;
     extern __shared__ __align__(16) unsigned char smem[];
     const Lds L = lds_layout(smem, NS, a.stride, a.q_cap);
-    // the global reads of the set-up first, so that their latency overlaps the
-    // LDS clear and the tables below: the count, the summaries and, with one
-    // patch range (it starts at record 0), the records of the wavefront's
-    // first chunk.  A wavefront's first two chunks are 2 w and 2 w + 1; the
-    // later ones come from a counter in LDS.  The first chunk is read before
-    // the count is known, so lanes past the capacity read the last slot and
-    // lanes past the count are replaced by the stand-in record in the loop.
+    // The reads of the set-up first, so that their latencies overlap each
+    // other, the LDS clear and the tables below.  The scalar arguments the
+    // set-up uses are read together (one wait, where each use would otherwise
+    // wait for its own read).  Then the count and, with one patch range (it
+    // starts at record 0), the records of the wavefront's first chunk: a
+    // wavefront's first two chunks are 2 w and 2 w + 1, the later ones come
+    // from a counter in LDS.  The first chunk is read before the count is
+    // known, so lanes past the capacity read the last slot and lanes past the
+    // count are replaced by the stand-in record in the loop.  Last, the
+    // summaries.
+    asm volatile("" ::"s"(a.n_active), "s"(a.stats), "s"(a.patches), "s"(a.prep), "s"(a.n_cap), "s"(a.n_stats),
+                 "s"(a.n_split), "s"(a.n_tw), "s"(a.tw), "s"(a.T), "s"(a.R), "s"(a.stride), "s"(a.q_cap),
+                 "s"(a.tiles_x), "s"(a.tiles_y), "s"(a.plan), "s"(a.n_units));
+    asm volatile("" ::"s"(a.rx.a0), "s"(a.rx.step), "s"(a.rx.n), "s"(a.ry.a0), "s"(a.ry.step), "s"(a.ry.n),
+                 "s"(a.cx), "s"(a.cy), "s"(a.s), "s"(a.inv), "s"(a.delta));
+    if (!CONF) asm volatile("" ::"s"(a.lx.a0), "s"(a.lx.step), "s"(a.lx.n), "s"(a.ly.a0), "s"(a.ly.step), "s"(a.ly.n));
     const int n_act = active_count(a);
-    StatF st0;
-    st0.count = 0;
-    if ((int)threadIdx.x < a.n_stats) st0 = load_stat(a.stats, threadIdx.x);
     const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
     const bool prep = a.prep != nullptr;
     const float4* src = prep ? a.prep : a.patches;
@@ -626,6 +636,18 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
         const int pl = min(2 * wave * 64 + lane, a.n_cap - 1);
         An = load4(src, 2 * (size_t)pl);
         Bn = load3(src, 2 * (size_t)pl + 1);
+    }
+    // this thread's summary, read now and decoded where the bound needs it
+    // (three words of the second half: the fourth is padding, and a dead
+    // destination word of a read in flight invites a wait on its reuse)
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    typedef int v3i __attribute__((ext_vector_type(3)));
+    v4i st0a = {0, 0, 0, 0};
+    v3i st0b = {0, 0, 0};
+    if ((int)threadIdx.x < a.n_stats) {
+        const __attribute__((address_space(1))) v4i* g = (const __attribute__((address_space(1))) v4i*)a.stats;
+        st0a = g[2 * (size_t)threadIdx.x];
+        st0b = *(const __attribute__((address_space(1))) v3i*)(g + 2 * (size_t)threadIdx.x + 1);
     }
 
     int id = block_id;
@@ -646,8 +668,8 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
 #pragma unroll
     for (int k = 0; k < NU; ++k) uvalid[k] = unit[k] >= 0;
 
-    for (int i = threadIdx.x; i < NS * a.stride / 2; i += blockDim.x) reinterpret_cast<uint4*>(L.hist)[i] = uint4{0, 0, 0, 0};
-    if (threadIdx.x == 0) *L.next = 2u * (blockDim.x >> 6);
+    for (int i = threadIdx.x; i < NS * a.stride / 2; i += kBlock) reinterpret_cast<uint4*>(L.hist)[i] = uint4{0, 0, 0, 0};
+    if (threadIdx.x == 0) *L.next = 2u * (kBlock / 64);
     if (threadIdx.x < NS) {
         const int j = threadIdx.x;
         const int k = j / NH, jl = j % NH;
@@ -694,8 +716,8 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
     float wbk[NU];
 #pragma unroll
     for (int k = 0; k < NU; ++k) wbk[k] = 0.f;
-    for (int i = threadIdx.x; i < a.n_stats; i += blockDim.x) {
-        const StatF c = i == (int)threadIdx.x ? st0 : load_stat(a.stats, i);
+    for (int i = threadIdx.x; i < a.n_stats; i += kBlock) {
+        const StatF c = i == (int)threadIdx.x ? decode_stat(st0a, v4i{st0b.x, st0b.y, st0b.z, 0}) : load_stat(a.stats, i);
 #pragma unroll
         for (int k = 0; k < NU; ++k)
             if (uvalid[k]) wbk[k] = fmaxf(wbk[k], unit_weight_bound<CONF, TL, TX, TY>(a, unit[k], c));

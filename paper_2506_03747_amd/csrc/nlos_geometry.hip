@@ -94,17 +94,6 @@ __device__ __forceinline__ void scan_body(const GeomArgs& a)
 
 __global__ void __launch_bounds__(1024) k_geom_scan(const GeomArgs a) { scan_body(a); }
 
-// Derivative of the depth map along one axis (central inside, one-sided at
-// the borders, 0 for a single sample); `d` points at sample i, stride between
-// samples in elements.
-__device__ __forceinline__ float deriv(const float* d, int n, int i, int64_t stride, float h)
-{
-    if (n < 2) return 0.f;
-    if (i == 0) return (d[stride] - d[0]) / h;
-    if (i == n - 1) return (d[0] - d[-stride]) / h;
-    return (d[stride] - d[-stride]) / (2.f * h);
-}
-
 __device__ __forceinline__ int wave_min_i(int v)
 {
 #pragma unroll
@@ -130,27 +119,42 @@ __device__ __forceinline__ void scatter_body(const GeomArgs& a, int blk)
     __shared__ int red[kGeomBlock / 64];
     const int64_t e = (int64_t)blk * kGeomBlock + threadIdx.x;
     int ix = 0, iy = 0;
-    bool p = enum_pixel(a, e, &ix, &iy);
+    const bool in_map = enum_pixel(a, e, &ix, &iy);
     const int64_t idx = (int64_t)ix * a.ay.n + iy;
-    if (p) p = is_present(a, idx);
+    // every global read of the block is issued before any of them is used
+    // (the counts of the blocks before this one, the pixel, its neighbours),
+    // so that their latencies overlap
+    int sum = 0;
+    if (a.offsets) {
+        sum = threadIdx.x == 0 ? a.offsets[blk] : 0;
+    } else {
+        for (int i = threadIdx.x; i < blk; i += kGeomBlock) sum += a.counts[i];
+    }
+    float z = 0.f, rho = 0.5f, zxp = 0.f, zxm = 0.f, zyp = 0.f, zym = 0.f;
+    bool m = false;
+    if (in_map) {
+        const float* D = a.depth + idx;
+        z = D[0];
+        if (a.albedo) rho = a.albedo[idx];
+        m = a.mask ? (a.mask[idx] != 0) : true;
+        // neighbours for the normal (a sample of the map itself where the
+        // one-sided difference does not use one)
+        zxp = ix + 1 < a.ax.n ? D[a.ay.n] : z;
+        zxm = ix > 0 ? D[-(int64_t)a.ay.n] : z;
+        zyp = iy + 1 < a.ay.n ? D[1] : z;
+        zym = iy > 0 ? D[-1] : z;
+    }
+    const bool p = in_map && m && rho > 0.f && isfinite(z) && z > 0.f;
     const unsigned long long bal = __ballot(p);
     const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
     const int rank = __popcll(bal & ((1ull << lane) - 1ull));
     if (lane == 0) wave_cnt[wave] = __popcll(bal);
-    int base;
-    if (a.offsets) {
-        base = a.offsets[blk];
-    } else {
-        int sum = 0;
-        for (int i = threadIdx.x; i < blk; i += kGeomBlock) sum += a.counts[i];
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, 64);
-        if (lane == 0) red[wave] = sum;
-        __syncthreads();
-        base = 0;
-        for (int w = 0; w < kGeomBlock / 64; ++w) base += red[w];
-    }
+    for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, 64);
+    if (lane == 0) red[wave] = sum;
     __syncthreads();
+    int base = 0;
+    for (int w = 0; w < kGeomBlock / 64; ++w) base += red[w];
     int off = base + rank;
     for (int w = 0; w < wave; ++w) off += wave_cnt[w];
     if (!a.offsets && blk == a.n_blocks - 1 && threadIdx.x == 0) {
@@ -161,11 +165,16 @@ __device__ __forceinline__ void scatter_body(const GeomArgs& a, int blk)
 
     float4 A = make_float4(0.f, 0.f, 0.f, 0.f);
     if (p) {
-        const float* D = a.depth + idx;
-        const float z = D[0];
-        const float rho = a.albedo ? a.albedo[idx] : 0.5f;
-        const float gx = deriv(D, a.ax.n, ix, a.ay.n, a.hx);
-        const float gy = deriv(D, a.ay.n, iy, 1, a.hy);
+        // central differences inside, one-sided at the borders, 0 for a
+        // single sample (the same operations as before the reads moved up)
+        const float gx = a.ax.n < 2 ? 0.f
+                         : ix == 0 ? (zxp - z) / a.hx
+                         : ix == a.ax.n - 1 ? (z - zxm) / a.hx
+                         : (zxp - zxm) / (2.f * a.hx);
+        const float gy = a.ay.n < 2 ? 0.f
+                         : iy == 0 ? (zyp - z) / a.hy
+                         : iy == a.ay.n - 1 ? (z - zym) / a.hy
+                         : (zyp - zym) / (2.f * a.hy);
         const float len = sqrtf(1.f + gx * gx + gy * gy);
         const float area = a.hx * a.hy * (a.cosines ? len : 1.f);
         A = make_float4(canon(a.ax, ix), canon(a.ay, iy), z, rho * area);

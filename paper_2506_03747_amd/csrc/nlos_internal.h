@@ -91,11 +91,9 @@ __device__ __forceinline__ int32_t ord_f(float f)
 
 __device__ __forceinline__ float unord_f(int32_t k) { return __int_as_float(k >= 0 ? k : k ^ 0x7FFFFFFF); }
 
-__device__ __forceinline__ StatF load_stat(const ChunkStat* st, int i)
+__device__ __forceinline__ StatF decode_stat(int __attribute__((ext_vector_type(4))) c0,
+                                             int __attribute__((ext_vector_type(4))) c1)
 {
-    typedef int v4i __attribute__((ext_vector_type(4)));
-    const __attribute__((address_space(1))) v4i* g = (const __attribute__((address_space(1))) v4i*)st;
-    const v4i c0 = g[2 * (size_t)i], c1 = g[2 * (size_t)i + 1];
     StatF r;
     r.x0 = unord_f(c0.x);
     r.x1 = unord_f(c0.y);
@@ -105,6 +103,13 @@ __device__ __forceinline__ StatF load_stat(const ChunkStat* st, int i)
     r.amax = unord_f(c1.y);
     r.count = c1.z;
     return r;
+}
+
+__device__ __forceinline__ StatF load_stat(const ChunkStat* st, int i)
+{
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const __attribute__((address_space(1))) v4i* g = (const __attribute__((address_space(1))) v4i*)st;
+    return decode_stat(g[2 * (size_t)i], g[2 * (size_t)i + 1]);
 }
 
 // Arguments of the pair kernels (confocal and non-confocal).
