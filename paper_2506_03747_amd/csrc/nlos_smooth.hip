@@ -565,70 +565,84 @@ __global__ void __launch_bounds__(256) k_adj_taps(const SmoothArgs a)
     moment_taps<RS>(a, a.mtaps, adj_moments(RS));
 }
 
-// Rows of one scan point: a thread produces V consecutive bins of every row
-// from a register window of its gradient samples (gl: g with 2 RS zeros
-// before and 2 RS + 5 after), the kernels K_m read from LDS at wave-uniform
-// addresses.  VEC (V = 4, L a multiple of 4): the V bins go
-// out as one aligned 16-byte store, so a wavefront writes 1 KB contiguous.
-template <int RS, int V, bool VEC>
-__device__ __forceinline__ void adj_moment_rows(const float* gl, const float* __restrict__ kt, float* out, int L)
+// Correlation rows.  A thread produces V = 4 consecutive bins j0 .. j0 + 3
+// (bins k0 = j - RS of a row of L = T + 2 RS) of every row of one scan point,
+// from a register window of that point's upstream gradient g[j0 - 2 RS ..
+// j0 + 3] (zero outside 0 .. T - 1).  Threads map flat onto (scan
+// point, group of 4 bins), so every lane of every wavefront has work and no
+// row is staged anywhere first.  The kernels have the parity of their order,
+// K_m(-d) = (-1)^m K_m(d) exactly (He_m has the parity of m, and every
+// operation of moment_taps is symmetric in the sign of d), so
+//     C_m[k0] = K_m(0) g[k0] + sum_{d=1..RS} K_m(d) (g[k0 + d] + (-1)^m g[k0 - d]):
+// a bin's mirrored sums serve every even row and its mirrored differences
+// every odd row, 2 RS adds and about RS + 1 fmas per row where the full
+// support takes 2 RS + 1 fmas.  The kernels are scalar reads (the same for
+// every lane, written by an earlier launch), fma operands in scalar
+// registers, one row at a time.  ALIGNED (T a multiple of 4, so L is too,
+// and both arrays 16-byte aligned): the window arrives as 16-byte reads, each
+// wholly inside the row or wholly in the zero padding, and each row's four
+// bins go out as one 16-byte store.
+template <int RS, bool ALIGNED>
+__global__ void __launch_bounds__(256) k_adj_moments(const SmoothArgs a)
 {
-    constexpr int ND = 2 * RS + 1, NM = adj_moments(RS);
-    for (int j0 = (int)threadIdx.x * V; j0 < L; j0 += (int)blockDim.x * V) {
-        // bins k0 = j - RS, j = j0 .. j0 + V - 1: C_m = sum_d g[k0 + d] K_m(d),
-        // g[k0 + d] = gl[j + d + RS] = w[j - j0 + dd], dd = d + RS
-        float w[V + 2 * RS];
+    constexpr int V = 4, NM = adj_moments(RS), ND = 2 * RS + 1, W = V + 2 * RS;
+    static_assert(W % 4 == 0, "the window is whole 16-byte pieces");
+    const int T = a.T, L = a.mlen, Q = (L + V - 1) / V;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)(a.rx.n * a.ry.n) * Q) return;
+    const int s = (int)(t / Q), j0 = (int)(t % Q) * V;
+    const float* g = a.grad_out + (size_t)s * T;
+    const int kw = j0 - 2 * RS;   // gradient index of window word 0
+    float w[W];
+    if constexpr (ALIGNED) {
 #pragma unroll
-        for (int q = 0; q < V + 2 * RS; ++q) w[q] = gl[j0 + q];
+        for (int q = 0; q < W / 4; ++q) {
+            const int k = kw + 4 * q;
+            const float4 v = (k >= 0 && k < T) ? *reinterpret_cast<const float4*>(g + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+            w[4 * q] = v.x;
+            w[4 * q + 1] = v.y;
+            w[4 * q + 2] = v.z;
+            w[4 * q + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < W; ++q) w[q] = (kw + q >= 0 && kw + q < T) ? g[kw + q] : 0.f;
+    }
+    const __attribute__((address_space(4))) float* kc = (const __attribute__((address_space(4))) float*)a.mtaps;
+    float* out = a.moments + (size_t)s * NM * L + j0;
+    // bin j0 + v: g[k0 + d] = w[v + RS + d] (k0 = j0 + v - RS)
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+        // mirrored sums (even rows) or differences (odd rows) of every bin
+        float x[V][RS];
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+            for (int d = 1; d <= RS; ++d)
+                x[v][d - 1] = par == 0 ? w[v + RS + d] + w[v + RS - d] : w[v + RS + d] - w[v + RS - d];
+        // one row at a time: its kernel in scalar registers
 #pragma unroll 1
-        for (int m = 0; m < NM; ++m) {
+        for (int m = par; m < NM; m += 2) {
+            const int c = m * ND + RS;   // K_m(0)
             float acc[V];
 #pragma unroll
-            for (int v = 0; v < V; ++v) acc[v] = 0.f;
+            for (int v = 0; v < V; ++v) acc[v] = par == 0 ? w[v + RS] * kc[c] : 0.f;
 #pragma unroll
-            for (int dd = 0; dd < ND; ++dd) {
-                const float k = kt[m * ND + dd];
+            for (int d = 1; d <= RS; ++d) {
+                const float k = kc[c + d];
 #pragma unroll
-                for (int v = 0; v < V; ++v) acc[v] = fmaf(w[v + dd], k, acc[v]);
+                for (int v = 0; v < V; ++v) acc[v] = fmaf(x[v][d - 1], k, acc[v]);
             }
-            if constexpr (VEC) {
+            if constexpr (ALIGNED) {
                 // j0 and L are multiples of 4, so j0 + 3 < L
-                *reinterpret_cast<float4*>(out + (size_t)m * L + j0) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+                *reinterpret_cast<float4*>(out + (size_t)m * L) = make_float4(acc[0], acc[1], acc[2], acc[3]);
             } else {
 #pragma unroll
                 for (int v = 0; v < V; ++v)
-                    if (j0 + v < L) out[(size_t)m * L + j0 + v] = acc[v];
+                    if (j0 + v < L) out[(size_t)m * L + v] = acc[v];
             }
         }
     }
-}
-
-// One workgroup per scan point: its upstream-gradient row staged in LDS,
-// then every correlation row of that point.  The launch gives it one thread
-// per V bins of a row (whole wavefronts, at most 1024), so no second pass
-// runs with a few lanes.
-template <int RS>
-__global__ void __launch_bounds__(1024) k_adj_moments(const SmoothArgs a)
-{
-    constexpr int NM = adj_moments(RS), ND = 2 * RS + 1;
-    extern __shared__ __align__(16) unsigned char smem[];
-    float* gl = reinterpret_cast<float*>(smem);   // g with 2 RS zeros before, 2 RS + 5 after
-    const int T = a.T, L = a.mlen, s = (int)blockIdx.x;
-    // the kernels K_m copied next to it: LDS broadcasts instead of a vector
-    // load of the table per moment
-    float* kl = gl + ((T + 4 * RS + 8 + 3) & ~3);
-    for (int i = threadIdx.x; i < NM * ND; i += blockDim.x) kl[i] = a.mtaps[i];
-    const float* g = a.grad_out + (size_t)s * T;
-    for (int i = threadIdx.x; i < T + 4 * RS + 5; i += blockDim.x) {
-        const int k = i - 2 * RS;
-        gl[i] = (k >= 0 && k < T) ? g[k] : 0.f;
-    }
-    __syncthreads();
-    float* out = a.moments + (size_t)s * NM * L;
-    if ((L & 3) == 0)
-        adj_moment_rows<RS, 4, true>(gl, kl, out, L);
-    else
-        adj_moment_rows<RS, 5, false>(gl, kl, out, L);
 }
 
 template <bool COS, int RS>
@@ -945,14 +959,14 @@ static hipError_t launch_adjoint_mom_rs(const SmoothArgs& a, int64_t patch_block
     hipLaunchKernelGGL(k_adj_taps<RS>, dim3(1), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // gradient row (T + 4 RS + 8 floats, rounded to 16 bytes), then the taps
-    const size_t lds_m = (size_t)((a.T + 4 * RS + 8 + 3) & ~3) * 4 + (size_t)adj_moments(RS) * (2 * RS + 1) * 4;
-    e = hipFuncSetAttribute((const void*)k_adj_moments<RS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_m);
-    if (e != hipSuccess) return e;
-    const int per_thread = (a.mlen & 3) == 0 ? 4 : 5;   // bins per thread in k_adj_moments
-    const int need = ((a.mlen + per_thread - 1) / per_thread + 63) / 64 * 64;
-    const int threads = need < 1024 ? need : 1024;
-    hipLaunchKernelGGL(k_adj_moments<RS>, dim3((unsigned)S), dim3((unsigned)threads), lds_m, st, a);
+    // one thread per (scan point, 4 bins of a correlation row)
+    const int64_t n_thr = (int64_t)S * ((a.mlen + 3) / 4);
+    const unsigned blocks = (unsigned)((n_thr + 255) / 256);
+    const bool aligned = (a.T & 3) == 0 && ((uintptr_t)a.grad_out & 15) == 0 && ((uintptr_t)a.moments & 15) == 0;
+    if (aligned)
+        hipLaunchKernelGGL((k_adj_moments<RS, true>), dim3(blocks), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_adj_moments<RS, false>), dim3(blocks), dim3(256), 0, st, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const void* k = a.cosines ? (const void*)k_adjoint_mom<true, RS> : (const void*)k_adjoint_mom<false, RS>;

@@ -71,8 +71,8 @@ RADII = [
     dict(seed=615, bin_ps=8.0, fwhm_ps=50.0, cosines=False),
     dict(seed=616, bin_ps=16.0, fwhm_ps=70.0, standoff_m=0.7, n_bins=768),
     dict(seed=617, bin_ps=8.0, fwhm_ps=50.0, scan=(3, 2), patches=(64, 64)),
-    # T + 2 Rs not a multiple of 4: five bins per thread with scalar stores in
-    # the adjoint's correlation pass, scalar staging in the gather
+    # T not a multiple of 4: scalar window reads and stores in the adjoint's
+    # correlation pass, scalar staging in the gather
     dict(seed=618, bin_ps=8.0, fwhm_ps=50.0, n_bins=517, scan=(3, 2)),
 ]
 
