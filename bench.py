@@ -36,10 +36,10 @@ FP32_FMA_CEILING_TFLOPS = 78.6
 # what the same counters read for a 256 MiB device copy, see
 # profiles/k_forward_cfg2_hbm_counters.md), valid only for the kernel sources
 # they were taken on (hash below); any other source reports null.
-TRAFFIC_BYTES = (7488.2 * 2.0 + 16384.0 * 1.0) * 1024
+TRAFFIC_BYTES = (7473.3 * 2.0 + 16393.8 * 1.0) * 1024
 TRAFFIC_SOURCES = ("paper_2506_03747_amd/csrc/nlos_forward.hip", "paper_2506_03747_amd/csrc/nlos_device.h",
                    "paper_2506_03747_amd/csrc/nlos_internal.h")
-TRAFFIC_HASH = "f25682c6c6b168f7"
+TRAFFIC_HASH = "1c91bc846b7a5791"
 
 
 def traffic_for_sources():
