@@ -764,10 +764,26 @@ __global__ void __launch_bounds__(256) k_adjoint_reduce(const SmoothArgs a, floa
     if (p >= a.n_cap) return;
     double g[kAdjStride] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (p < n_act) {
-        for (int sp = 0; sp < a.n_split; ++sp) {
-            const double* q = a.partial + ((size_t)sp * a.n_cap + p) * kAdjStride;
+        // eight splits' partials read before any is added (their latencies
+        // overlap), then added in split order, as one at a time would
+        constexpr int kB = 8;
+        const size_t step = (size_t)a.n_cap * kAdjStride;
+        const double* q = a.partial + (size_t)p * kAdjStride;
+        int sp = 0;
+        for (; sp + kB <= a.n_split; sp += kB) {
+            double v[kB][kAdjStride];
 #pragma unroll
-            for (int k = 0; k < kAdjStride; ++k) g[k] += q[k];
+            for (int i = 0; i < kB; ++i)
+#pragma unroll
+                for (int k = 0; k < kAdjStride; ++k) v[i][k] = q[(size_t)(sp + i) * step + k];
+#pragma unroll
+            for (int i = 0; i < kB; ++i)
+#pragma unroll
+                for (int k = 0; k < kAdjStride; ++k) g[k] += v[i][k];
+        }
+        for (; sp < a.n_split; ++sp) {
+#pragma unroll
+            for (int k = 0; k < kAdjStride; ++k) g[k] += q[(size_t)sp * step + k];
         }
     }
     float4* o = reinterpret_cast<float4*>(grad_rec + (size_t)p * 8);
