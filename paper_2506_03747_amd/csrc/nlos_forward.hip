@@ -812,23 +812,31 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
         // lanes past the range take a stand-in record at x = dummy_x with
         // zero weight: every arrival of that position lies past the window
         const int p = base + lane;
-        const bool stand_in = p >= pe;
+        // (only the last chunk has lanes past the range: a wave-uniform test
+        // keeps the selects off every other chunk)
+        if (base + 64 > pe && p >= pe) {
+            if (prep) {
+                An = make_float4(dummy_px, 0.f, 1.f, 0.f);
+                Bn = make_float4(0.f, 0.f, 0.f, 0.f);
+            } else {
+                An = make_float4(a.dummy_x, 0.f, 1.f, 0.f);
+                Bn = make_float4(0.f, 0.f, -1.f, 0.f);
+            }
+        }
         PatchC pc;
         float aw;
         if (prep) {
-            pc.px = stand_in ? dummy_px : An.x;
-            pc.py = stand_in ? 0.f : An.y;
-            pc.pz2 = stand_in ? 1.f : An.z;
-            pc.ap = stand_in ? 0.f : An.w;
-            pc.mnxs = stand_in ? 0.f : Bn.x;
-            pc.mnys = stand_in ? 0.f : Bn.y;
-            pc.c0s = stand_in ? 0.f : Bn.z;
-            aw = pc.ap;
+            pc.px = An.x;
+            pc.py = An.y;
+            pc.pz2 = An.z;
+            pc.ap = An.w;
+            pc.mnxs = Bn.x;
+            pc.mnys = Bn.y;
+            pc.c0s = Bn.z;
+            aw = An.w;
         } else {
-            const float4 A = stand_in ? make_float4(a.dummy_x, 0.f, 1.f, 0.f) : An;
-            const float4 B = stand_in ? make_float4(0.f, 0.f, -1.f, 0.f) : Bn;
-            pc = patch_consts_scaled(A, B, COS, sig);
-            aw = A.w;
+            pc = patch_consts_scaled(An, Bn, COS, sig);
+            aw = An.w;
         }
         // records of the next chunk, into the registers the current ones
         // have just left (past the range: the last record, never used)
