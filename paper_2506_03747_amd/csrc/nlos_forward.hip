@@ -456,33 +456,108 @@ __device__ __forceinline__ float u64_to_float(uint2 x)
     return fmaf((float)hi, 4294967296.0f, (float)lo);
 }
 
-// Flush of the rows j = wave, wave + waves, ... of the workgroup, each by one
-// wavefront from start to end, so no other wavefront waits on it:
-//  1. the row's fixed-point bins become floats in the skewed layout, in place:
-//     the float row starts where the histogram row starts and never reaches
-//     past it, and a batch of eight 64-bin chunks is read before any float of
-//     it is written, while the floats of chunks up to c end before the words
-//     of chunk c + 1 begin (a wavefront's LDS operations run in order);
+// Flush of the workgroup's rows, in three steps:
+//  1. a row's fixed-point bins become floats in the skewed layout, in place,
+//     by one wavefront from start to end: the float row starts where the
+//     histogram row starts and never reaches past it, and a batch of eight
+//     64-bin chunks is read before any float of it is written, while the
+//     floats of chunks up to c end before the words of chunk c + 1 begin (a
+//     wavefront's LDS operations run in order);
 //  2. zeros around the bins;
-//  3. the jitter for taps zero-padded to radius RM: lane l of a 64 V-output
-//     segment takes the V consecutive outputs from o0 = 64 V s + V l, reading
-//     its window of V + 2 RM words at compile-time offsets from one address
-//     (nine words apart from its neighbours: distinct banks); each output is
-//     sum_k g[k] H[t + RM - k], accumulated by fma in increasing k, and a
-//     complete, 16-byte aligned lane writes its V outputs as two 16-byte stores.
+//  3. the jitter for taps zero-padded to radius RM, in segments of 64 V
+//     outputs: lane l of segment s takes the V consecutive outputs from
+//     o0 = 64 V s + V l, reading its window of V + 2 RM words at compile-time
+//     offsets from one address (nine words apart from its neighbours:
+//     distinct banks); each output is sum_k g[k] H[t + RM - k], accumulated
+//     by fma in increasing k, and a complete, 16-byte aligned lane writes its
+//     V outputs as two 16-byte stores.
+// With at least as many rows as wavefronts, wavefront w takes rows w,
+// w + waves, ... through all three steps and waits on no other.  With fewer
+// rows, the segments of step 3 are dealt to every wavefront after a barrier
+// (a segment reads floats another wavefront wrote), so that the wavefronts
+// without a row share the jitter; each output is computed the same way.
+
+// Steps 1 and 2 for row j (bin i at logical word lead - off + i).
+__device__ __forceinline__ void flush_convert(const FwdArgs& a, const Lds& L, int j, int Tl, int lead, int off,
+                                              int np, int lane)
+{
+    const int nch = (Tl + 63) >> 6;
+    const int d = lane - off;                   // logical word of bin 64 c + lane: lead + 64 c + d
+    const int dp = d + floor_div8(d);
+    float* Fr = reinterpret_cast<float*>(L.hist + (size_t)j * a.stride);
+    const uint2* Hr = reinterpret_cast<const uint2*>(L.hist) + (size_t)j * a.stride;
+    for (int c0 = 0; c0 < nch; c0 += 8) {
+        uint2 x[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) x[b] = Hr[min((c0 + b) * 64 + lane, Tl - 1)];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int xb = lead + 64 * (c0 + b);
+            if (c0 + b < nch && (c0 + b) * 64 + lane < Tl) Fr[xb + (xb >> 3) + dp] = u64_to_float(x[b]);
+        }
+    }
+    for (int e = lane; e < np; e += 64) {
+        const int x = e < lead - off ? e : e + Tl;
+        Fr[x + (x >> 3)] = 0.f;
+    }
+}
+
+// Step 3 for segment s of row j (output row `row` of the operator).
 template <int RM>
-__device__ __forceinline__ void flush_rows(const FwdArgs& a, const Lds& L, int NS, int Tl, int hb, int t0w,
-                                           int t1w)
+__device__ __forceinline__ void flush_segment(const FwdArgs& a, const Lds& L, int j, long long row,
+                                              const float (&g)[2 * RM + 1], int s, int lead, int nt, int o_last,
+                                              int t0w, int lane)
 {
     constexpr int V = kFlushV;
     constexpr int K = 2 * RM + 1;
     constexpr int W = V + 2 * RM;
     constexpr int B0 = -RM + floor_div8(-RM);   // physical offset of window word 0 from output o0
+    const float* Fr = reinterpret_cast<const float*>(L.hist + (size_t)j * a.stride);
+    const float gg = L.gg[j];
+    const int o0 = s * 64 * V + lane * V;
+    const int x0 = lead + min(o0, o_last);     // logical word of output o0, 8 | x0 (lanes past the end: the last window)
+    const float* h = Fr + (x0 + (x0 >> 3)) + B0;
+    float w[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) w[q] = h[(q - RM) + floor_div8(q - RM) - B0];
+    float acc[V];
+#pragma unroll
+    for (int m = 0; m < V; ++m) {
+        float sum = 0.f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) sum = fmaf(g[k], w[m + 2 * RM - k], sum);
+        acc[m] = sum * gg;
+    }
+    if (o0 >= nt) return;
+    const size_t first = (size_t)row * (size_t)a.T + (size_t)(t0w + o0);
+    __attribute__((address_space(1))) float* orow = gmem(a.out) + first;
+    if (a.atomic_out) {
+#pragma unroll
+        for (int m = 0; m < V; ++m)
+            if (o0 + m < nt) unsafeAtomicAdd((float*)(orow + m), acc[m]);
+    } else if (o0 + V <= nt && (first & 3) == 0) {
+        typedef float v4f __attribute__((ext_vector_type(4)));
+        typedef __attribute__((address_space(1))) v4f gv4f;
+        reinterpret_cast<gv4f*>(orow)[0] = v4f{acc[0], acc[1], acc[2], acc[3]};
+        reinterpret_cast<gv4f*>(orow)[1] = v4f{acc[4], acc[5], acc[6], acc[7]};
+    } else {
+#pragma unroll
+        for (int m = 0; m < V; ++m)
+            if (o0 + m < nt) orow[m] = acc[m];
+    }
+}
+
+template <int RM, int NS>
+__device__ __forceinline__ void flush_rows(const FwdArgs& a, const Lds& L, int Tl, int hb, int t0w, int t1w)
+{
+    constexpr int V = kFlushV;
+    constexpr int K = 2 * RM + 1;
+    constexpr int n_waves = kBlock / 64;
     const int R = a.R;
     const int RMr = RM > 16 ? jitter_rm(R) : RM;   // the radius the host sized the rows for
     const int lead = flush_lead(RMr), Lr = flush_row_logical(Tl, RMr);
-    const int off = t0w - hb;                   // bin i of the row sits at logical word lead - off + i
-    const int lane = threadIdx.x & 63, n_waves = kBlock / 64;
+    const int off = t0w - hb;
+    const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float g[K];
     if (RM <= 16) {
@@ -493,36 +568,28 @@ __device__ __forceinline__ void flush_rows(const FwdArgs& a, const Lds& L, int N
             g[k] = (k >= sh && k - sh <= 2 * R) ? t : 0.f;
         }
     }
-    const int nch = (Tl + 63) >> 6;
-    const int d = lane - off;                   // logical word of bin 64 c + lane: lead + 64 c + d
-    const int dp = d + floor_div8(d);
     const int nt = t1w - t0w;
     const int nseg = (nt + 64 * V - 1) / (64 * V);
     const int o_last = (nt - 1) & ~(V - 1);     // window of the lanes past the end (inside the row)
     const int np = Lr - Tl;
-    const uint2* H2 = reinterpret_cast<const uint2*>(L.hist);
+    if (RM <= 16 && NS < n_waves) {
+        if (wave < NS && L.row[wave] >= 0) flush_convert(a, L, wave, Tl, lead, off, np, lane);
+        __syncthreads();
+        for (int it = wave; it < NS * nseg; it += n_waves) {
+            const int j = it / nseg;
+            const long long row = L.row[j];
+            if (row >= 0) flush_segment<RM>(a, L, j, row, g, it - j * nseg, lead, nt, o_last, t0w, lane);
+        }
+        return;
+    }
     for (int j = wave; j < NS; j += n_waves) {
         const long long row = L.row[j];
         if (row < 0) continue;
-        float* Fr = reinterpret_cast<float*>(L.hist + (size_t)j * a.stride);
-        const uint2* Hr = H2 + (size_t)j * a.stride;
-        for (int c0 = 0; c0 < nch; c0 += 8) {
-            uint2 x[8];
-#pragma unroll
-            for (int b = 0; b < 8; ++b) x[b] = Hr[min((c0 + b) * 64 + lane, Tl - 1)];
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const int xb = lead + 64 * (c0 + b);
-                if (c0 + b < nch && (c0 + b) * 64 + lane < Tl) Fr[xb + (xb >> 3) + dp] = u64_to_float(x[b]);
-            }
-        }
-        for (int e = lane; e < np; e += 64) {
-            const int x = e < lead - off ? e : e + Tl;
-            Fr[x + (x >> 3)] = 0.f;
-        }
-        const float gg = L.gg[j];
+        flush_convert(a, L, j, Tl, lead, off, np, lane);
         if (RM > 16) {
             // wide kernels: one output per lane, generic tap loop
+            const float* Fr = reinterpret_cast<const float*>(L.hist + (size_t)j * a.stride);
+            const float gg = L.gg[j];
             for (int tt = lane; tt < nt; tt += 64) {
                 float acc = 0.f;
                 for (int i = 0; i <= 2 * R; ++i) {
@@ -538,39 +605,7 @@ __device__ __forceinline__ void flush_rows(const FwdArgs& a, const Lds& L, int N
             }
             continue;
         }
-        for (int s = 0; s < nseg; ++s) {
-            const int o0 = s * 64 * V + lane * V;
-            const int x0 = lead + min(o0, o_last);                 // logical word of output o0, 8 | x0
-            const float* h = Fr + (x0 + (x0 >> 3)) + B0;
-            float w[W];
-#pragma unroll
-            for (int q = 0; q < W; ++q) w[q] = h[(q - RM) + floor_div8(q - RM) - B0];
-            float acc[V];
-#pragma unroll
-            for (int m = 0; m < V; ++m) {
-                float sum = 0.f;
-#pragma unroll
-                for (int k = 0; k < K; ++k) sum = fmaf(g[k], w[m + 2 * RM - k], sum);
-                acc[m] = sum * gg;
-            }
-            if (o0 >= nt) continue;
-            const size_t first = (size_t)row * (size_t)a.T + (size_t)(t0w + o0);
-            __attribute__((address_space(1))) float* orow = gmem(a.out) + first;
-            if (a.atomic_out) {
-#pragma unroll
-                for (int m = 0; m < V; ++m)
-                    if (o0 + m < nt) unsafeAtomicAdd((float*)(orow + m), acc[m]);
-            } else if (o0 + V <= nt && (first & 3) == 0) {
-                typedef float v4f __attribute__((ext_vector_type(4)));
-                typedef __attribute__((address_space(1))) v4f gv4f;
-                reinterpret_cast<gv4f*>(orow)[0] = v4f{acc[0], acc[1], acc[2], acc[3]};
-                reinterpret_cast<gv4f*>(orow)[1] = v4f{acc[4], acc[5], acc[6], acc[7]};
-            } else {
-#pragma unroll
-                for (int m = 0; m < V; ++m)
-                    if (o0 + m < nt) orow[m] = acc[m];
-            }
-        }
+        for (int s = 0; s < nseg; ++s) flush_segment<RM>(a, L, j, row, g, s, lead, nt, o_last, t0w, lane);
     }
 }
 
@@ -582,19 +617,19 @@ __device__ __forceinline__ void flush(const FwdArgs& a, const Lds& L, int hb, in
 {
     const int RM = jitter_rm(a.R);
     if (RM == 2) {
-        flush_rows<2>(a, L, NS, Tl, hb, t0w, t1w);
+        flush_rows<2, NS>(a, L, Tl, hb, t0w, t1w);
     } else if (RM == 4) {
-        flush_rows<4>(a, L, NS, Tl, hb, t0w, t1w);
+        flush_rows<4, NS>(a, L, Tl, hb, t0w, t1w);
     } else if (RM == 6) {
-        flush_rows<6>(a, L, NS, Tl, hb, t0w, t1w);
+        flush_rows<6, NS>(a, L, Tl, hb, t0w, t1w);
     } else if (RM == 8) {
-        flush_rows<8>(a, L, NS, Tl, hb, t0w, t1w);
+        flush_rows<8, NS>(a, L, Tl, hb, t0w, t1w);
     } else if (RM == 12) {
-        flush_rows<12>(a, L, NS, Tl, hb, t0w, t1w);
+        flush_rows<12, NS>(a, L, Tl, hb, t0w, t1w);
     } else if (RM == 16) {
-        flush_rows<16>(a, L, NS, Tl, hb, t0w, t1w);
+        flush_rows<16, NS>(a, L, Tl, hb, t0w, t1w);
     } else {
-        flush_rows<17>(a, L, NS, Tl, hb, t0w, t1w);   // any radius past 16: the generic tap loop
+        flush_rows<17, NS>(a, L, Tl, hb, t0w, t1w);   // any radius past 16: the generic tap loop
     }
 }
 
