@@ -94,18 +94,27 @@ __device__ __forceinline__ void scan_body(const GeomArgs& a)
 
 __global__ void __launch_bounds__(1024) k_geom_scan(const GeomArgs a) { scan_body(a); }
 
-__device__ __forceinline__ int wave_min_i(int v)
+// Minimum (MAX false) or maximum of v over the 64 lanes of a wavefront, every
+// lane active: partial results within rows of 16 lanes by row shifts, then
+// across rows by the row broadcasts; lane 63 ends with the result.  Lanes a
+// DPP step does not write keep the identity.
+template <bool MAX>
+__device__ __forceinline__ int wave_reduce_i(int v)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-__device__ __forceinline__ int wave_max_i(int v)
-{
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
+    constexpr int id = MAX ? INT32_MIN : INT32_MAX;
+#define NLOS_DPP_STEP(ctrl, rows)                                                     \
+    {                                                                                 \
+        const int t = __builtin_amdgcn_update_dpp(id, v, ctrl, rows, 0xf, false);    \
+        v = MAX ? max(v, t) : min(v, t);                                              \
+    }
+    NLOS_DPP_STEP(0x111, 0xf)   // row_shr:1
+    NLOS_DPP_STEP(0x112, 0xf)   // row_shr:2
+    NLOS_DPP_STEP(0x114, 0xf)   // row_shr:4
+    NLOS_DPP_STEP(0x118, 0xf)   // row_shr:8
+    NLOS_DPP_STEP(0x142, 0xa)   // row_bcast:15 into rows 1 and 3
+    NLOS_DPP_STEP(0x143, 0xc)   // row_bcast:31 into rows 2 and 3
+#undef NLOS_DPP_STEP
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Records of one enumeration block at base + (rank among the present pixels
@@ -191,33 +200,58 @@ __device__ __forceinline__ void scatter_body(const GeomArgs& a, int blk)
     }
     if (!a.stats) return;   // uniform across the block
 
-    // Record summaries, one per kStatBlock consecutive records: a wavefront's
-    // records are consecutive (off - rank is its first), so they meet at most
-    // two summaries; each is reduced over the wavefront and merged with
-    // integer atomics on the order-preserving images (min and max commute,
-    // so the result does not depend on the order of the merges).
-    const int n_w = __popcll(bal);
-    if (n_w == 0) return;
-    const int first = __builtin_amdgcn_readfirstlane(off - rank);   // the same in every lane
-    const int c0 = first / kStatBlock, c1 = (first + n_w - 1) / kStatBlock;
-    for (int c = c0; c <= c1; ++c) {
-        const bool in = p && off / kStatBlock == c;
-        const int v0 = wave_min_i(in ? ord_f(A.x) : INT32_MAX);
-        const int v1 = wave_max_i(in ? ord_f(A.x) : INT32_MIN);
-        const int v2 = wave_min_i(in ? ord_f(A.y) : INT32_MAX);
-        const int v3 = wave_max_i(in ? ord_f(A.y) : INT32_MIN);
-        const int v4 = wave_min_i(in ? ord_f(A.z) : INT32_MAX);
-        const int v5 = wave_max_i(in ? ord_f(A.w) : INT32_MIN);
-        const int cnt = __popcll(__ballot(in));
-        if (lane == 0 && cnt > 0 && c < a.n_stats) {
-            int32_t* t = reinterpret_cast<int32_t*>(a.stats + c);
-            atomicMin(t + 0, v0);
-            atomicMax(t + 1, v1);
-            atomicMin(t + 2, v2);
-            atomicMax(t + 3, v3);
-            atomicMin(t + 4, v4);
-            atomicMax(t + 5, v5);
-            atomicAdd(t + 6, cnt);
+    // Record summaries, one per kStatBlock consecutive records.  The block's
+    // records are consecutive, [base, base + n), with n <= kStatBlock, so
+    // they meet at most two summaries, cb and cb + 1 (sides 0 and 1).  Each
+    // wavefront reduces its lanes of each side it has, the block combines
+    // its wavefronts' values in LDS, and 14 lanes merge the two sides' seven
+    // fields into the summaries with integer atomics on the order-preserving
+    // images (min and max commute, so the result does not depend on the
+    // order of the merges).
+    static_assert(kGeomBlock <= kStatBlock, "a block's records meet at most two summaries");
+    __shared__ int part[kGeomBlock / 64][2][7];
+    const int cb = base / kStatBlock;
+    const int side = off / kStatBlock - cb;   // 0 or 1 where p
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+        const bool in = p && side == sd;
+        const unsigned long long m = __ballot(in);
+        int v[7] = {INT32_MAX, INT32_MIN, INT32_MAX, INT32_MIN, INT32_MAX, INT32_MIN, (int)__popcll(m)};
+        if (m != 0ull) {   // uniform
+            v[0] = wave_reduce_i<false>(in ? ord_f(A.x) : INT32_MAX);
+            v[1] = wave_reduce_i<true>(in ? ord_f(A.x) : INT32_MIN);
+            v[2] = wave_reduce_i<false>(in ? ord_f(A.y) : INT32_MAX);
+            v[3] = wave_reduce_i<true>(in ? ord_f(A.y) : INT32_MIN);
+            v[4] = wave_reduce_i<false>(in ? ord_f(A.z) : INT32_MAX);
+            v[5] = wave_reduce_i<true>(in ? ord_f(A.w) : INT32_MIN);
+        }
+        if (lane < 7) {
+            int x = v[0];
+#pragma unroll
+            for (int f = 1; f < 7; ++f) x = lane == f ? v[f] : x;
+            part[wave][sd][lane] = x;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 14) {
+        const int sd = (int)threadIdx.x / 7, f = (int)threadIdx.x % 7;
+        int x = part[0][sd][f], cnt = part[0][sd][6];
+#pragma unroll
+        for (int w = 1; w < kGeomBlock / 64; ++w) {
+            const int y = part[w][sd][f];
+            x = f == 6 ? x + y : ((f & 1) ? max(x, y) : min(x, y));
+            cnt += part[w][sd][6];
+        }
+        const int c = cb + sd;
+        if (cnt > 0 && c < a.n_stats) {
+            // fields x0, x1, y0, y1, z0, amax, count: minima at even f < 6
+            int32_t* t = reinterpret_cast<int32_t*>(a.stats + c) + f;
+            if (f == 6)
+                atomicAdd(t, x);
+            else if (f & 1)
+                atomicMax(t, x);
+            else
+                atomicMin(t, x);
         }
     }
 }
