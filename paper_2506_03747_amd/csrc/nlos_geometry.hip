@@ -35,22 +35,72 @@ __device__ __forceinline__ bool enum_pixel(const GeomArgs& a, int64_t e, int* ix
     return *ix < a.ax.n && *iy < a.ay.n;
 }
 
-__device__ __forceinline__ bool is_present(const GeomArgs& a, int64_t idx)
+// Minimum, maximum or sum (OP 0, 1, 2) of v over the 64 lanes of a
+// wavefront, every lane active: partial results within rows of 16 lanes by
+// row shifts, then across rows by the row broadcasts; lane 63 ends with the
+// result.  Lanes a DPP step does not write keep the identity.
+template <int OP>
+__device__ __forceinline__ int wave_reduce_i(int v)
 {
-    const float z = a.depth[idx];
-    const float rho = a.albedo ? a.albedo[idx] : 0.5f;
-    const bool m = a.mask ? (a.mask[idx] != 0) : true;
-    return m && rho > 0.f && isfinite(z) && z > 0.f;
+    constexpr int id = OP == 0 ? INT32_MAX : (OP == 1 ? INT32_MIN : 0);
+#define NLOS_DPP_STEP(ctrl, rows)                                                          \
+    {                                                                                      \
+        const int t = __builtin_amdgcn_update_dpp(id, v, ctrl, rows, 0xf, false);         \
+        v = OP == 0 ? min(v, t) : (OP == 1 ? max(v, t) : v + t);                           \
+    }
+    NLOS_DPP_STEP(0x111, 0xf)   // row_shr:1
+    NLOS_DPP_STEP(0x112, 0xf)   // row_shr:2
+    NLOS_DPP_STEP(0x114, 0xf)   // row_shr:4
+    NLOS_DPP_STEP(0x118, 0xf)   // row_shr:8
+    NLOS_DPP_STEP(0x142, 0xa)   // row_bcast:15 into rows 1 and 3
+    NLOS_DPP_STEP(0x143, 0xc)   // row_bcast:31 into rows 2 and 3
+#undef NLOS_DPP_STEP
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// The samples of map index idx, read together before any is used (where an
+// albedo or mask map is absent, its read goes to the depth map and is not
+// used), and whether they make a present pixel.
+struct Samples {
+    float z, rho;
+    bool m;
+};
+
+__device__ __forceinline__ Samples read_samples(const GeomArgs& a, int64_t idx)
+{
+    const float* al = a.albedo ? a.albedo : a.depth;
+    const uint8_t* mk = a.mask ? a.mask : reinterpret_cast<const uint8_t*>(a.depth);
+    const float z = a.depth[idx], r = al[idx];
+    const uint8_t m = mk[idx];
+    return Samples{z, a.albedo ? r : 0.5f, a.mask ? m != 0 : true};
+}
+
+__device__ __forceinline__ bool is_present(const Samples& s)
+{
+    return s.m && s.rho > 0.f && isfinite(s.z) && s.z > 0.f;
 }
 
 __device__ __forceinline__ void count_body(const GeomArgs& a, int blk)
 {
+    __shared__ int wave_cnt[kGeomBlock / 64];
     const int64_t e = (int64_t)blk * kGeomBlock + threadIdx.x;
     int ix = 0, iy = 0;
-    bool p = enum_pixel(a, e, &ix, &iy);
-    if (p) p = is_present(a, (int64_t)ix * a.ay.n + iy);
-    const int cnt = __syncthreads_count(p);
-    if (threadIdx.x == 0) a.counts[blk] = cnt;
+    const bool in_map = enum_pixel(a, e, &ix, &iy);
+    // (lanes without a pixel read index 0 of the map and use nothing)
+    const Samples smp = read_samples(a, in_map ? (int64_t)ix * a.ay.n + iy : 0);
+    // (every sample taken, so that no read waits for the mask's or albedo's
+    // value before it is issued)
+    asm volatile("" ::"v"(smp.z), "v"(smp.rho), "v"((int)smp.m));
+    const bool p = in_map && is_present(smp);
+    const unsigned long long bal = __ballot(p);
+    if ((threadIdx.x & 63) == 0) wave_cnt[threadIdx.x >> 6] = (int)__popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int cnt = 0;
+#pragma unroll
+        for (int w = 0; w < kGeomBlock / 64; ++w) cnt += wave_cnt[w];
+        a.counts[blk] = cnt;
+    }
     // empty record summaries for the scatter to merge into: block b clears
     // kGeomBlock / kStatBlock of them (the blocks cover n_enum >= n_stats * kStatBlock
     // pixels, so every summary is cleared before the scatter launch)
@@ -94,29 +144,6 @@ __device__ __forceinline__ void scan_body(const GeomArgs& a)
 
 __global__ void __launch_bounds__(1024) k_geom_scan(const GeomArgs a) { scan_body(a); }
 
-// Minimum (MAX false) or maximum of v over the 64 lanes of a wavefront, every
-// lane active: partial results within rows of 16 lanes by row shifts, then
-// across rows by the row broadcasts; lane 63 ends with the result.  Lanes a
-// DPP step does not write keep the identity.
-template <bool MAX>
-__device__ __forceinline__ int wave_reduce_i(int v)
-{
-    constexpr int id = MAX ? INT32_MIN : INT32_MAX;
-#define NLOS_DPP_STEP(ctrl, rows)                                                     \
-    {                                                                                 \
-        const int t = __builtin_amdgcn_update_dpp(id, v, ctrl, rows, 0xf, false);    \
-        v = MAX ? max(v, t) : min(v, t);                                              \
-    }
-    NLOS_DPP_STEP(0x111, 0xf)   // row_shr:1
-    NLOS_DPP_STEP(0x112, 0xf)   // row_shr:2
-    NLOS_DPP_STEP(0x114, 0xf)   // row_shr:4
-    NLOS_DPP_STEP(0x118, 0xf)   // row_shr:8
-    NLOS_DPP_STEP(0x142, 0xa)   // row_bcast:15 into rows 1 and 3
-    NLOS_DPP_STEP(0x143, 0xc)   // row_bcast:31 into rows 2 and 3
-#undef NLOS_DPP_STEP
-    return __builtin_amdgcn_readlane(v, 63);
-}
-
 // Records of one enumeration block at base + (rank among the present pixels
 // before it).  base is the exclusive prefix of the block counts: read from
 // `offsets`, or (offsets null) summed here from the counts.  With `stats`,
@@ -133,33 +160,32 @@ __device__ __forceinline__ void scatter_body(const GeomArgs& a, int blk)
     // every global read of the block is issued before any of them is used
     // (the counts of the blocks before this one, the pixel, its neighbours),
     // so that their latencies overlap
+    // (lanes without a pixel read index 0 of the map and use nothing; the
+    // counts past the first kGeomBlock blocks are read last)
     int sum = 0;
-    if (a.offsets) {
+    if (a.offsets)
         sum = threadIdx.x == 0 ? a.offsets[blk] : 0;
-    } else {
-        for (int i = threadIdx.x; i < blk; i += kGeomBlock) sum += a.counts[i];
-    }
-    float z = 0.f, rho = 0.5f, zxp = 0.f, zxm = 0.f, zyp = 0.f, zym = 0.f;
-    bool m = false;
-    if (in_map) {
-        const float* D = a.depth + idx;
-        z = D[0];
-        if (a.albedo) rho = a.albedo[idx];
-        m = a.mask ? (a.mask[idx] != 0) : true;
-        // neighbours for the normal (a sample of the map itself where the
-        // one-sided difference does not use one)
-        zxp = ix + 1 < a.ax.n ? D[a.ay.n] : z;
-        zxm = ix > 0 ? D[-(int64_t)a.ay.n] : z;
-        zyp = iy + 1 < a.ay.n ? D[1] : z;
-        zym = iy > 0 ? D[-1] : z;
-    }
-    const bool p = in_map && m && rho > 0.f && isfinite(z) && z > 0.f;
+    else
+        sum = (int)threadIdx.x < blk ? a.counts[threadIdx.x] : 0;
+    const int64_t ci = in_map ? idx : 0;
+    const Samples smp = read_samples(a, ci);
+    // neighbours for the normal (the sample itself where the one-sided
+    // difference does not use one)
+    const float* D = a.depth + ci;
+    const int64_t dxp = in_map && ix + 1 < a.ax.n ? (int64_t)a.ay.n : 0;
+    const int64_t dxm = in_map && ix > 0 ? -(int64_t)a.ay.n : 0;
+    const int dyp = in_map && iy + 1 < a.ay.n ? 1 : 0;
+    const int dym = in_map && iy > 0 ? -1 : 0;
+    const float zxp = D[dxp], zxm = D[dxm], zyp = D[dyp], zym = D[dym];
+    if (!a.offsets)
+        for (int i = (int)threadIdx.x + kGeomBlock; i < blk; i += kGeomBlock) sum += a.counts[i];
+    const float z = smp.z, rho = smp.rho;
+    const bool p = in_map && is_present(smp);
     const unsigned long long bal = __ballot(p);
     const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
     const int rank = __popcll(bal & ((1ull << lane) - 1ull));
     if (lane == 0) wave_cnt[wave] = __popcll(bal);
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, 64);
+    sum = wave_reduce_i<2>(sum);
     if (lane == 0) red[wave] = sum;
     __syncthreads();
     int base = 0;
@@ -218,12 +244,12 @@ __device__ __forceinline__ void scatter_body(const GeomArgs& a, int blk)
         const unsigned long long m = __ballot(in);
         int v[7] = {INT32_MAX, INT32_MIN, INT32_MAX, INT32_MIN, INT32_MAX, INT32_MIN, (int)__popcll(m)};
         if (m != 0ull) {   // uniform
-            v[0] = wave_reduce_i<false>(in ? ord_f(A.x) : INT32_MAX);
-            v[1] = wave_reduce_i<true>(in ? ord_f(A.x) : INT32_MIN);
-            v[2] = wave_reduce_i<false>(in ? ord_f(A.y) : INT32_MAX);
-            v[3] = wave_reduce_i<true>(in ? ord_f(A.y) : INT32_MIN);
-            v[4] = wave_reduce_i<false>(in ? ord_f(A.z) : INT32_MAX);
-            v[5] = wave_reduce_i<true>(in ? ord_f(A.w) : INT32_MIN);
+            v[0] = wave_reduce_i<0>(in ? ord_f(A.x) : INT32_MAX);
+            v[1] = wave_reduce_i<1>(in ? ord_f(A.x) : INT32_MIN);
+            v[2] = wave_reduce_i<0>(in ? ord_f(A.y) : INT32_MAX);
+            v[3] = wave_reduce_i<1>(in ? ord_f(A.y) : INT32_MIN);
+            v[4] = wave_reduce_i<0>(in ? ord_f(A.z) : INT32_MAX);
+            v[5] = wave_reduce_i<1>(in ? ord_f(A.w) : INT32_MIN);
         }
         if (lane < 7) {
             int x = v[0];
