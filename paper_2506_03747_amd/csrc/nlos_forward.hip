@@ -133,15 +133,14 @@ __device__ __forceinline__ float rect_rect_d2(float ax0, float ax1, float ay0, f
     return fmaf(dx, dx, dy * dy);
 }
 
-// Block-wide maxima of N non-negative floats, in place (wave butterfly, then
-// LDS; `red` holds N floats per wavefront).
+// Block-wide maxima of N non-negative floats, in place (DPP within each
+// wavefront, then LDS; `red` holds N floats per wavefront).
 template <int N>
 __device__ __forceinline__ void block_max(float* v, float* red)
 {
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) v[k] = fmaxf(v[k], __shfl_xor(v[k], o, 64));
+        v[k] = wave_max_f(v[k]);
         if ((threadIdx.x & 63) == 0) red[(threadIdx.x >> 6) * N + k] = v[k];
     }
     __syncthreads();

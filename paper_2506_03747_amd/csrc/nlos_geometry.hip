@@ -35,29 +35,6 @@ __device__ __forceinline__ bool enum_pixel(const GeomArgs& a, int64_t e, int* ix
     return *ix < a.ax.n && *iy < a.ay.n;
 }
 
-// Minimum, maximum or sum (OP 0, 1, 2) of v over the 64 lanes of a
-// wavefront, every lane active: partial results within rows of 16 lanes by
-// row shifts, then across rows by the row broadcasts; lane 63 ends with the
-// result.  Lanes a DPP step does not write keep the identity.
-template <int OP>
-__device__ __forceinline__ int wave_reduce_i(int v)
-{
-    constexpr int id = OP == 0 ? INT32_MAX : (OP == 1 ? INT32_MIN : 0);
-#define NLOS_DPP_STEP(ctrl, rows)                                                          \
-    {                                                                                      \
-        const int t = __builtin_amdgcn_update_dpp(id, v, ctrl, rows, 0xf, false);         \
-        v = OP == 0 ? min(v, t) : (OP == 1 ? max(v, t) : v + t);                           \
-    }
-    NLOS_DPP_STEP(0x111, 0xf)   // row_shr:1
-    NLOS_DPP_STEP(0x112, 0xf)   // row_shr:2
-    NLOS_DPP_STEP(0x114, 0xf)   // row_shr:4
-    NLOS_DPP_STEP(0x118, 0xf)   // row_shr:8
-    NLOS_DPP_STEP(0x142, 0xa)   // row_bcast:15 into rows 1 and 3
-    NLOS_DPP_STEP(0x143, 0xc)   // row_bcast:31 into rows 2 and 3
-#undef NLOS_DPP_STEP
-    return __builtin_amdgcn_readlane(v, 63);
-}
-
 // The samples of map index idx, read together before any is used (where an
 // albedo or mask map is absent, its read goes to the depth map and is not
 // used), and whether they make a present pixel.

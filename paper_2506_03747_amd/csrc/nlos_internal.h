@@ -82,6 +82,46 @@ struct StatF {
     int32_t count;
 };
 
+// Minimum, maximum or sum (OP 0, 1, 2) of v over the 64 lanes of a
+// wavefront, every lane active: partial results within rows of 16 lanes by
+// row shifts, then across rows by the row broadcasts; lane 63 ends with the
+// result.  Lanes a DPP step does not write keep the identity.
+template <int OP>
+__device__ __forceinline__ int wave_reduce_i(int v)
+{
+    constexpr int id = OP == 0 ? INT32_MAX : (OP == 1 ? INT32_MIN : 0);
+#define NLOS_DPP_STEP(ctrl, rows)                                                          \
+    {                                                                                      \
+        const int t = __builtin_amdgcn_update_dpp(id, v, ctrl, rows, 0xf, false);         \
+        v = OP == 0 ? min(v, t) : (OP == 1 ? max(v, t) : v + t);                           \
+    }
+    NLOS_DPP_STEP(0x111, 0xf)   // row_shr:1
+    NLOS_DPP_STEP(0x112, 0xf)   // row_shr:2
+    NLOS_DPP_STEP(0x114, 0xf)   // row_shr:4
+    NLOS_DPP_STEP(0x118, 0xf)   // row_shr:8
+    NLOS_DPP_STEP(0x142, 0xa)   // row_bcast:15 into rows 1 and 3
+    NLOS_DPP_STEP(0x143, 0xc)   // row_bcast:31 into rows 2 and 3
+#undef NLOS_DPP_STEP
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Maximum of v over the 64 lanes of a wavefront (every lane active), the
+// same DPP steps on the bits of v with -inf as the identity.
+__device__ __forceinline__ float wave_max_f(float v)
+{
+    constexpr int id = (int)0xff800000;   // -inf
+#define NLOS_DPP_STEP(ctrl, rows)                                                                       \
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(id, __float_as_int(v), ctrl, rows, 0xf, false)));
+    NLOS_DPP_STEP(0x111, 0xf)   // row_shr:1
+    NLOS_DPP_STEP(0x112, 0xf)   // row_shr:2
+    NLOS_DPP_STEP(0x114, 0xf)   // row_shr:4
+    NLOS_DPP_STEP(0x118, 0xf)   // row_shr:8
+    NLOS_DPP_STEP(0x142, 0xa)   // row_bcast:15 into rows 1 and 3
+    NLOS_DPP_STEP(0x143, 0xc)   // row_bcast:31 into rows 2 and 3
+#undef NLOS_DPP_STEP
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // f -> int32 with the same order (negative floats: magnitude bits flipped).
 __device__ __forceinline__ int32_t ord_f(float f)
 {
