@@ -394,7 +394,7 @@ __device__ __forceinline__ UnitRect unit_rect(const FwdArgs& a, int u)
 // a_max / (r_l,min^2 r_d,min^2) over the record summaries (cosine factors
 // are at most 1).
 template <bool CONF, int TL, int TX, int TY>
-__device__ float unit_weight_bound(const FwdArgs& a, int u, const StatF& c)
+__device__ __forceinline__ float unit_weight_bound(const FwdArgs& a, int u, const StatF& c)
 {
     const UnitRect R = unit_rect<CONF, TL, TX, TY>(a, u);
     if (c.count <= 0) return 0.f;
