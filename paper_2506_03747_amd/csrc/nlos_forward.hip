@@ -301,12 +301,7 @@ __device__ __forceinline__ void chunk_stats_body(const FwdArgs& a, ChunkStat* st
     }
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        float x = v[k];
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
-            const float y = __shfl_xor(x, o, 64);
-            x = (k == 5) ? fmaxf(x, y) : fminf(x, y);
-        }
+        const float x = k == 5 ? wave_extreme_f<true>(v[k]) : wave_extreme_f<false>(v[k]);
         if ((threadIdx.x & 63) == 0) red[k][threadIdx.x >> 6] = x;
     }
     __syncthreads();

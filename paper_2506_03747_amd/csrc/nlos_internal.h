@@ -105,13 +105,18 @@ __device__ __forceinline__ int wave_reduce_i(int v)
     return __builtin_amdgcn_readlane(v, 63);
 }
 
-// Maximum of v over the 64 lanes of a wavefront (every lane active), the
-// same DPP steps on the bits of v with -inf as the identity.
-__device__ __forceinline__ float wave_max_f(float v)
+// Maximum (MAX true) or minimum of v over the 64 lanes of a wavefront (every
+// lane active), the same DPP steps on the bits of v with -inf or +inf as the
+// identity.
+template <bool MAX>
+__device__ __forceinline__ float wave_extreme_f(float v)
 {
-    constexpr int id = (int)0xff800000;   // -inf
-#define NLOS_DPP_STEP(ctrl, rows)                                                                       \
-    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(id, __float_as_int(v), ctrl, rows, 0xf, false)));
+    constexpr int id = MAX ? (int)0xff800000 : 0x7f800000;   // -inf, +inf
+#define NLOS_DPP_STEP(ctrl, rows)                                                                  \
+    {                                                                                              \
+        const float t = __int_as_float(__builtin_amdgcn_update_dpp(id, __float_as_int(v), ctrl, rows, 0xf, false)); \
+        v = MAX ? fmaxf(v, t) : fminf(v, t);                                                       \
+    }
     NLOS_DPP_STEP(0x111, 0xf)   // row_shr:1
     NLOS_DPP_STEP(0x112, 0xf)   // row_shr:2
     NLOS_DPP_STEP(0x114, 0xf)   // row_shr:4
@@ -122,7 +127,8 @@ __device__ __forceinline__ float wave_max_f(float v)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
-// f -> int32 with the same order (negative floats: magnitude bits flipped).
+__device__ __forceinline__ float wave_max_f(float v) { return wave_extreme_f<true>(v); }
+
 __device__ __forceinline__ int32_t ord_f(float f)
 {
     const int32_t b = __float_as_int(f);

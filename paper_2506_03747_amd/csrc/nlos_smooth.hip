@@ -153,8 +153,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth(const SmoothArgs a)
             wb = fmaxf(wb, c.amax / (r2 * r2));
         }
     }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) wb = fmaxf(wb, __shfl_xor(wb, o, 64));
+    wb = wave_max_f(wb);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = wb;
     __syncthreads();
     float W = 0.f;
@@ -331,8 +330,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_mom(const SmoothArgs a)
             wb = fmaxf(wb, c.amax / (r2 * r2));
         }
     }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) wb = fmaxf(wb, __shfl_xor(wb, o, 64));
+    wb = wave_max_f(wb);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = wb;
     __syncthreads();
     float W = 0.f;

@@ -429,9 +429,9 @@ def test_simulate_empty_scene():
 
 
 def test_large_map_uses_scan_path():
-    """A depth map of more than 1024 enumeration blocks (1056 x 1024 pixels):
-    block offsets come from the scan kernel; every present pixel appears
-    exactly once and the one-call path agrees with the two calls."""
+    """A depth map of more than 4096 enumeration blocks of 256 pixels (1056 x
+    1024 pixels): block offsets come from the scan kernel; every present pixel
+    appears exactly once and the one-call path agrees with the two calls."""
     import torch
     import paper_2506_03747_amd as nl
     rng = np.random.default_rng(77)
