@@ -43,6 +43,55 @@ def test_records_match_oracle(make):
     _records_vs_oracle(sc)
 
 
+def _ord_images(x):
+    """Order-preserving int32 images of fp32 values (negative values have
+    their magnitude bits flipped), as the record summaries store them."""
+    b = np.ascontiguousarray(x, np.float32).view(np.int32)
+    return np.where(b >= 0, b, b ^ np.int32(0x7FFFFFFF))
+
+
+@pytest.mark.parametrize("make", [lambda: scenes.tiny(seed=300, patches=(13, 7)), scenes.cfg1, scenes.cfg2])
+def test_simulate_summaries_bound_their_records(make):
+    """Invariant of the one-call path's record summaries (merged once per
+    geometry block from wavefront reductions and one atomic per field): each
+    is exactly the bounding box of its 256 consecutive records (x, y and
+    depth minima and maxima, largest a, as order-preserving int32 images)
+    with their count, and summaries past the last record stay empty.
+    White-box: the summaries sit right after the geometry's counts in
+    nlos_simulate's workspace.  The records themselves are checked against
+    the oracle by test_records_match_oracle."""
+    import ctypes as C
+    import torch
+    import paper_2506_03747_amd as nl
+    from paper_2506_03747_amd._native import lib
+    sc = make()
+    log(f"summaries {sc.name}")
+    depth, albedo, mask = to_gpu(sc)
+    prm = nl.params_of(sc)
+    g = nl.make_grid(sc.patch_grid)
+    need, geo = C.c_size_t(0), C.c_size_t(0)
+    assert lib().nlos_simulate_workspace_bytes(C.byref(prm), C.byref(g), C.byref(need)) == 0
+    assert lib().nlos_patches_workspace_bytes(C.byref(g), C.byref(geo)) == 0
+    ws = torch.full((need.value,), 0x5A, dtype=torch.uint8, device="cuda")   # stale bytes: every summary is rewritten
+    _, rec, n = nl.simulate(prm, depth, sc.patch_grid, albedo, mask, workspace=ws)
+    torch.cuda.synchronize()
+    k = int(n.item())
+    npx = g.nx * g.ny
+    n_stats = (npx + 255) // 256
+    off = (geo.value + 255) // 256 * 256
+    st = ws[off:off + 32 * n_stats].cpu().numpy().view(np.int32).reshape(n_stats, 8)
+    r = rec[:k].cpu().numpy()
+    imax, imin = np.iinfo(np.int32).max, np.iinfo(np.int32).min
+    for c in range(n_stats):
+        part = r[256 * c:min(256 * (c + 1), k)]
+        if len(part) == 0:
+            want = [imax, imin, imax, imin, imax, imin, 0, 0]
+        else:
+            ox, oy, oz, oa = (_ord_images(part[:, i]) for i in range(4))
+            want = [ox.min(), ox.max(), oy.min(), oy.max(), oz.min(), oa.max(), len(part), 0]
+        np.testing.assert_array_equal(st[c], np.array(want, np.int32), err_msg=f"{sc.name} summary {c}")
+
+
 TINY = [
     dict(seed=400),
     dict(seed=401, standoff_m=0.8),
