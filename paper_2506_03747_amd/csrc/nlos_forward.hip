@@ -239,8 +239,8 @@ __device__ __forceinline__ void guard_push(const Lds& L, const FwdArgs& a, uint6
         }
         qn += n;
     } else if (want) {
-        guard_overflow(L.hist + (size_t)j * a.stride, a.patches, p, kf, L.wlx[j], L.wly[j], L.wdx[j], L.wdy[j],
-                       L.so[j], a.inv, hb, Tl, inc);
+        guard_overflow(L.hist + (size_t)j * a.stride, a.prep ? a.prep : a.patches, p, kf, L.wlx[j], L.wly[j],
+                       L.wdx[j], L.wdy[j], L.so[j], a.inv, hb, Tl, inc);
     }
 }
 
@@ -248,10 +248,11 @@ __device__ __forceinline__ void guard_push(const Lds& L, const FwdArgs& a, uint6
 // operations as the pair loop: coordinates in bins (times sig), then one fma
 // per leg.
 template <bool CONF>
-__device__ __forceinline__ float fast_arrival(const FwdArgs& a, const Lds& L, float4 A, float4 B, int j)
+__device__ __forceinline__ float fast_arrival(const FwdArgs& a, const Lds& L, float4 A, int j)
 {
     const float sig = CONF ? a.inv2_f : a.inv_f;
-    const PatchC pc = patch_consts_scaled(A, B, a.cosines != 0, sig);
+    // (the arrival uses the coordinates only: no normal terms)
+    const PatchC pc = patch_consts_scaled(A, make_float4(0.f, 0.f, 0.f, 0.f), false, sig);
     float cx2, axv, cy2, byv;
     col_terms(pc, L.wdx[j] * sig, &cx2, &axv);
     row_terms(pc, L.wdy[j] * sig, &cy2, &byv);
@@ -264,16 +265,18 @@ __device__ __forceinline__ float fast_arrival(const FwdArgs& a, const Lds& L, fl
 }
 
 // After the wavefront's pair loop: its own segment (qn entries), one entry
-// per lane; other wavefronts may still be adding (all adds commute).
+// per lane; other wavefronts may still be adding (all adds commute).  The
+// coordinates come from the stream the pair loop read (records, or their
+// pair-loop constants, which keep them as recorded).
 template <bool CONF>
 __device__ __forceinline__ void guard_drain(const Lds& L, const FwdArgs& a, int hb, int Tl, int wave, int qw, int qn)
 {
+    const float4* src = a.prep ? a.prep : a.patches;
     for (int e = (int)threadIdx.x & 63; e < qn; e += 64) {
         const uint2 q = L.q[wave * qw + e];
         const int p = (int)(q.x >> 8), j = (int)(q.x & 255u);
-        const float4 A = load4(a.patches, 2 * (size_t)p);
-        const float4 B = load4(a.patches, 2 * (size_t)p + 1);
-        const int kf = decide(fast_arrival<CONF>(a, L, A, B, j), a.two_delta).k - hb;
+        const float4 A = load4(src, 2 * (size_t)p);
+        const int kf = decide(fast_arrival<CONF>(a, L, A, j), a.two_delta).k - hb;
         const int ke = exact_bin(A.x, A.y, A.z, L.wlx[j], L.wly[j], L.wdx[j], L.wdy[j], L.so[j], a.inv) - hb;
         guard_fix(L.hist + (size_t)j * a.stride, kf, ke, Tl, q.y);
     }
@@ -829,7 +832,6 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
     int next_id = chunk_id + 1;
     // records as written by the geometry, or (prep) their pair-loop
     // constants, which the one-call path writes beside them
-    const float dummy_px = a.dummy_x * sig;
     if (!early && pb + chunk_id * 64 < pe) {
         const int pl = min(pb + chunk_id * 64 + lane, pe - 1);
         An = load4(src, 2 * (size_t)pl);
@@ -845,7 +847,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
         // keeps the selects off every other chunk)
         if (base + 64 > pe && p >= pe) {
             if (prep) {
-                An = make_float4(dummy_px, 0.f, 1.f, 0.f);
+                An = make_float4(a.dummy_x, 0.f, 1.f, 0.f);
                 Bn = make_float4(0.f, 0.f, 0.f, 0.f);
             } else {
                 An = make_float4(a.dummy_x, 0.f, 1.f, 0.f);
@@ -855,9 +857,11 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
         PatchC pc;
         float aw;
         if (prep) {
-            pc.px = An.x;
-            pc.py = An.y;
-            pc.pz2 = An.z;
+            // the coordinates in bins, as patch_consts_scaled computes them
+            pc.px = An.x * sig;
+            pc.py = An.y * sig;
+            const float pzs = An.z * sig;
+            pc.pz2 = pzs * pzs;
             pc.ap = An.w;
             pc.mnxs = Bn.x;
             pc.mnys = Bn.y;

@@ -195,9 +195,11 @@ __device__ __forceinline__ void scatter_body(const GeomArgs& a, int blk)
         a.patches[2 * (int64_t)off + 1] = B;
         if (a.prep) {
             // the constants the pair loop derives from this record, by the
-            // same function, so that it need not derive them per chunk
+            // same function, so that it need not derive them per chunk; the
+            // coordinates stay unscaled (the loop scales them per chunk, and
+            // the fp64 re-binning of guard-band pairs needs them as recorded)
             const PatchC pc = patch_consts_scaled(A, B, a.cosines != 0, a.prep_sig);
-            a.prep[2 * (int64_t)off] = make_float4(pc.px, pc.py, pc.pz2, pc.ap);
+            a.prep[2 * (int64_t)off] = make_float4(A.x, A.y, A.z, pc.ap);
             a.prep[2 * (int64_t)off + 1] = make_float4(pc.mnxs, pc.mnys, pc.c0s, 0.f);
         }
     }

@@ -60,7 +60,8 @@ struct GeomArgs {
     int64_t n_enum;        // 256 * bx * by
     int32_t n_blocks;      // ceil(n_enum / kGeomBlock)
     int32_t cosines;
-    float4* prep;          // nullable: [n][2] the pair loop's per-record constants
+    float4* prep;          // nullable: [n][2] the pair loop's per-record constants ({x, y, z} as recorded, then the
+                           // weight and normal terms in the pair loop's units)
     float prep_sig;        // the pair loop's bins per metre (its scale of coordinates)
 };
 constexpr int kGeomBlock = 256;
@@ -161,7 +162,8 @@ __device__ __forceinline__ StatF load_stat(const ChunkStat* st, int i)
 // Arguments of the pair kernels (confocal and non-confocal).
 struct FwdArgs {
     const float4* patches;
-    const float4* prep;        // nullable: the records' pair-loop constants (PatchC), same order
+    const float4* prep;        // nullable: the records' pair-loop constants, same order: {x, y, z, ap} (coordinates
+                               // as recorded), {mnxs, mnys, c0s, 0} (PatchC, scaled)
     const int32_t* n_active;   // nullable
     int32_t n_cap;
     float* out;
