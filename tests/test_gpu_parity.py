@@ -312,6 +312,55 @@ def test_time_windows():
     assert_parity(tau.cpu().numpy(), ref, what="time windows")
 
 
+def _sphere_cap_scene():
+    """16 x 16 confocal scan points; a 128 x 128 depth map on the sphere of
+    radius R around scan point (8, 8), R chosen so that every pair of that
+    scan point arrives 3e-4 bins below bin 500 (fp32 coordinates move it by
+    about 4e-5 bins)."""
+    c = 299792458.0
+    bin_ps, T, half_w, half_p, n_p = 8.0, 1024, 0.5, 0.3, 128
+    canon = lambda half, n: (-half + (np.arange(n) + 0.5) * (2.0 * half / n)).astype(np.float32).astype(np.float64)
+    x0 = canon(half_w, 16)[8]
+    xs = canon(half_p, n_p)
+    R = (500.0 - 3e-4) * c * bin_ps * 1e-12 / 2.0
+    dx2 = (xs[:, None] - x0) ** 2 + (xs[None, :] - x0) ** 2
+    z = np.sqrt(R * R - dx2).astype(np.float32)
+    rng = np.random.default_rng(512)
+    albedo = rng.uniform(0.5, 1.0, (n_p, n_p)).astype(np.float32)
+    return scenes.Scene("sphere_cap", scenes.grid(16, 16, half_w), None, scenes.grid(n_p, n_p, half_p), z, albedo,
+                        None, standoff_m=0.0, bin_ps=bin_ps, n_bins=T, fwhm_ps=40.0, seed=512)
+
+
+def test_guard_queue_overflow_moves_pairs():
+    """Every pair of one scan point lies within the guard band just above a
+    bin edge in fp32 and one bin lower in fp64: each is queued and moved, and
+    with 4096 such pairs per workgroup against 16 wavefronts x 128 queue
+    entries, the queues overflow, so the in-place correction runs too.  Checked against
+    the oracle through the two-call path (raw records) and the one-call path
+    (re-binning from the pair-loop constants)."""
+    import torch
+    import paper_2506_03747_amd as nl
+    sc = _sphere_cap_scene()
+    rec = oracle.patches(sc)
+    ref = oracle.forward(sc, rec)["tau"]
+    bins = oracle.forward(sc, rec, subset=np.array([8 * 16 + 8]), want_tau=False, want_bins=True)["bins"][0]
+    assert np.all(bins == 499), "every pair of the centre scan point is in bin 499 in fp64"
+    assert 500.0 - 3e-4 + guard_delta(sc.n_bins) < 500.0 + 2 * guard_delta(sc.n_bins)
+    tol = parity_tolerance(sc, ref, rec=rec)
+    # a workgroup's share of the records exceeds its 16 x 128 queue entries
+    plan = nl.get_plan(nl.params_of(sc), sc.n_patch_total)
+    assert sc.n_patch_total / plan["n_split"] > 16 * 128, plan
+    two, _, _ = gpu_forward(sc)
+    depth, albedo, mask = to_gpu(sc)
+    one, _, _ = nl.simulate(nl.params_of(sc), depth, sc.patch_grid, albedo, mask)
+    torch.cuda.synchronize()
+    for what, tau in (("two-call", two), ("one-call", one)):
+        got = tau.cpu().numpy().reshape(-1, sc.n_bins)
+        assert_parity_model(got, ref, tol, what=f"sphere cap {what}")
+        # (the jitter is symmetric: the centre histogram peaks at its pairs' bin)
+        assert int(np.argmax(got[8 * 16 + 8])) == 499, f"{what}: the centre histogram's pairs left bin 499"
+
+
 def test_patch_split_many_patches_few_scan_points():
     """Few histograms, many patches: patches are split over workgroups and
     the partial histograms combined with float atomics."""
