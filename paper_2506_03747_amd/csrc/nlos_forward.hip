@@ -179,6 +179,19 @@ __device__ __forceinline__ float4 load3(const float4* p, size_t i)
     return make_float4(v.x, v.y, v.z, 0.f);
 }
 
+// Both halves of record r, 0 <= r < NLOS_MAX_PATCHES = 2^24, so that its
+// byte offset fits 32 bits: the loads take the base as a scalar and a 32-bit
+// offset per lane.
+__device__ __forceinline__ void load_record(const float4* p, int r, float4& A, float4& B)
+{
+    const uint32_t off = (uint32_t)r * 32u;
+    const __attribute__((address_space(1))) char* b = (const __attribute__((address_space(1))) char*)p;
+    const v4f va = *(const __attribute__((address_space(1))) v4f*)(b + off);
+    const v3f vb = *(const __attribute__((address_space(1))) v3f*)(b + off + 16u);
+    A = make_float4(va.x, va.y, va.z, va.w);
+    B = make_float4(vb.x, vb.y, vb.z, 0.f);
+}
+
 // Stands in for a missing device count, so that the count is always one
 // load with no branch before it (the kernels' first argument reads then go
 // out together instead of one after another).
@@ -666,8 +679,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
     float4 An = make_float4(0.f, 0.f, 0.f, 0.f), Bn = An;
     if (early) {
         const int pl = min(2 * wave * 64 + lane, a.n_cap - 1);
-        An = load4(src, 2 * (size_t)pl);
-        Bn = load3(src, 2 * (size_t)pl + 1);
+        load_record(src, pl, An, Bn);
     }
     // this thread's summary, read now and decoded where the bound needs it
     // (three words of the second half: the fourth is padding, and a dead
@@ -834,8 +846,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
     // constants, which the one-call path writes beside them
     if (!early && pb + chunk_id * 64 < pe) {
         const int pl = min(pb + chunk_id * 64 + lane, pe - 1);
-        An = load4(src, 2 * (size_t)pl);
-        Bn = load3(src, 2 * (size_t)pl + 1);
+        load_record(src, pl, An, Bn);
     }
     for (;;) {
         const int base = pb + chunk_id * 64;
@@ -875,8 +886,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
         // have just left (past the range: the last record, never used)
         {
             const int pl = min(pb + next_id * 64 + lane, pe - 1);
-            An = load4(src, 2 * (size_t)pl);
-            Bn = load3(src, 2 * (size_t)pl + 1);
+            load_record(src, pl, An, Bn);
         }
         int claim = 0;
         if (lane == 0) claim = (int)atomicAdd(L.next, 1u);
