@@ -828,7 +828,9 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
 #pragma unroll
     for (int k = 0; k < NU; ++k) {
         // squared distance (in bins) past which every confocal arrival is
-        // beyond cut_hi (enlarged by 1e-5 relative: the fp32 square rounds)
+        // beyond cut_hi, or (non-confocal) the square of the smallest sum of
+        // the two wall-to-patch legs that puts it there (enlarged by 1e-5
+        // relative: the fp32 squares and root round)
         const float rc = fmaxf(cut_hi - omin[k], 0.f);
         cut_r2[k] = rc * rc * 1.00001f;
     }
@@ -898,9 +900,10 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
                 if (CONF) {
                     out = rect_r2_min(pc.px, pc.py, pc.pz2, x0[k], x1[k], y0[k], y1[k]) >= cut_r2[k];
                 } else {
-                    const float rd = __builtin_amdgcn_sqrtf(rect_r2_min(pc.px, pc.py, pc.pz2, x0[k], x1[k], y0[k], y1[k]));
-                    const float rl = __builtin_amdgcn_sqrtf(rect_r2_min(pc.px, pc.py, pc.pz2, lx0[k], lx1[k], ly0[k], ly1[k]));
-                    out = (rl + rd) + omin[k] >= cut_hi;
+                    // (r_l + r_d)^2 = r_l^2 + r_d^2 + 2 sqrt(r_l^2 r_d^2): one root
+                    const float dd = rect_r2_min(pc.px, pc.py, pc.pz2, x0[k], x1[k], y0[k], y1[k]);
+                    const float dl = rect_r2_min(pc.px, pc.py, pc.pz2, lx0[k], lx1[k], ly0[k], ly1[k]);
+                    out = fmaf(2.f, __builtin_amdgcn_sqrtf(dd * dl), dd + dl) >= cut_r2[k];
                 }
                 if (WIN) {
                     const float Rd = __builtin_amdgcn_sqrtf(rect_r2_max(pc.px, pc.py, pc.pz2, x0[k], x1[k], y0[k], y1[k]));
