@@ -711,6 +711,9 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
     bool uvalid[NU];
 #pragma unroll
     for (int k = 0; k < NU; ++k) uvalid[k] = unit[k] >= 0;
+    int unit_on[NU];   // the same, made scalar for the pair loop's per-chunk test
+#pragma unroll
+    for (int k = 0; k < NU; ++k) unit_on[k] = __builtin_amdgcn_readfirstlane(unit[k] >= 0 ? 1 : 0);
 
     for (int i = threadIdx.x; i < NS * a.stride / 2; i += kBlock) reinterpret_cast<uint4*>(L.hist)[i] = uint4{0, 0, 0, 0};
     if (threadIdx.x == 0) *L.next = 2u * (kBlock / 64);
@@ -894,7 +897,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int block_id)
         if (lane == 0) claim = (int)atomicAdd(L.next, 1u);
 #pragma unroll
         for (int k = 0; k < NU; ++k) {
-            if (!uvalid[k]) continue;
+            if (unit_on[k] == 0) continue;
             {
                 bool out;
                 if (CONF) {
