@@ -32,14 +32,14 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
 FP32_FMA_CEILING_TFLOPS = 78.6
 
 # HBM bytes per launch of the cfg2 pair kernel from rocprofv3 counters
-# (FETCH_SIZE 4299.1 KiB x 2.0 + WRITE_SIZE 16393.8 KiB x 1.0; the factors are
+# (FETCH_SIZE 4297.2 KiB x 2.0 + WRITE_SIZE 16393.8 KiB x 1.0; the factors are
 # what the same counters read for a 256 MiB device copy, see
 # profiles/k_forward_cfg2_hbm_counters.md), valid only for the kernel sources
 # they were taken on (hash below); any other source reports null.
-TRAFFIC_BYTES = (4299.1 * 2.0 + 16393.8 * 1.0) * 1024
+TRAFFIC_BYTES = (4297.2 * 2.0 + 16393.8 * 1.0) * 1024
 TRAFFIC_SOURCES = ("paper_2506_03747_amd/csrc/nlos_forward.hip", "paper_2506_03747_amd/csrc/nlos_device.h",
                    "paper_2506_03747_amd/csrc/nlos_internal.h")
-TRAFFIC_HASH = "8fb886171e3b7b33"
+TRAFFIC_HASH = "385650cf3c9ca3e9"
 
 
 def traffic_for_sources():
