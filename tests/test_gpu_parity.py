@@ -303,10 +303,14 @@ def test_single_bin_window():
     assert_parity(tau.cpu().numpy(), ref, what="T=1")
 
 
-def test_time_windows():
-    """A histogram longer than LDS: the time axis is split over workgroups."""
+@pytest.mark.parametrize("fwhm_ps", [40.0, 20.0], ids=["radius17", "radius9"])
+def test_time_windows(fwhm_ps):
+    """A histogram longer than LDS: the time axis is split over workgroups,
+    one row each.  Radius 17 takes the flush's generic tap loop; radius 9
+    (taps padded to 12) deals the row's jitter segments to all 16
+    wavefronts of the workgroup."""
     sc = scenes.tiny(seed=503, scan=(2, 3), patches=(24, 24), n_bins=50000, bin_ps=2.0,
-                     fwhm_ps=40.0, zlo=0.5, zhi=4.0, half=2.0)
+                     fwhm_ps=fwhm_ps, zlo=0.5, zhi=4.0, half=2.0)
     tau, _, _ = gpu_forward(sc)
     ref = oracle.forward(sc)["tau"]
     assert_parity(tau.cpu().numpy(), ref, what="time windows")
