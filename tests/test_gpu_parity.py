@@ -34,8 +34,17 @@ def _records_vs_oracle(sc):
     return n
 
 
+def _no_albedo_no_mask():
+    """Maps without albedo (0.5 everywhere) and without mask: the geometry
+    reads the depth map in their place and uses nothing of it."""
+    import dataclasses
+    sc = scenes.tiny(seed=302, patches=(40, 37), zlo=-0.1, zhi=0.6)   # some depths <= 0: absent
+    return dataclasses.replace(sc, name="tiny302_plain", albedo=None, mask=None)
+
+
 @pytest.mark.parametrize("make", [lambda: scenes.tiny(seed=300, patches=(13, 7)),
                                   lambda: scenes.tiny(seed=301, patches=(1, 1), masked=False),
+                                  _no_albedo_no_mask,
                                   scenes.cfg1, scenes.cfg2, scenes.cfg3])
 def test_records_match_oracle(make):
     sc = make()
