@@ -78,8 +78,8 @@ def main():
                          "the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build runs the operator on a single MI355X "
-              f"(--gpus {args.gpus} is not supported; the multi-GPU sharding is a design note only)",
+        print(f"bench.py measures one GPU: the library runs the operator on a single MI355X "
+              f"(--gpus {args.gpus} is not supported; sharding over several GPUs is described, not built)",
               file=sys.stderr)
         sys.exit(2)
 
