@@ -67,7 +67,7 @@ __device__ __forceinline__ PairS pair_smooth(float4 A, float4 B, float wx, float
     PairS r;
     const float dx = A.x - wx, dy = A.y - wy, pz = A.z;
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, pz * pz));
-    const float ri2 = 1.0f / r2;
+    const float ri2 = __builtin_amdgcn_rcpf(r2);   // weights only: 1 ulp is ample
     const float ri4 = ri2 * ri2;
     // fp64 arrival from the same fp32 coordinates: ((r + r) + o) * inv, with
     // r from an fp32 square root and one Newton step in fp64 (relative error
@@ -85,7 +85,7 @@ __device__ __forceinline__ PairS pair_smooth(float4 A, float4 B, float wx, float
         r.w_a = k * c * c;
         r.w = A.w * r.w_a;
         if (derivs) {
-            r.dw_dz = A.w * k * (2.f * c * c / pz - 2.f * c * B.z) - r.w * 8.f * pz * ri2;
+            r.dw_dz = A.w * k * (2.f * c * c * __builtin_amdgcn_rcpf(pz) - 2.f * c * B.z) - r.w * 8.f * pz * ri2;
             r.dwn = -2.f * A.w * k * c;
         }
     } else {
@@ -96,7 +96,7 @@ __device__ __forceinline__ PairS pair_smooth(float4 A, float4 B, float wx, float
             r.dwn = 0.f;
         }
     }
-    if (derivs) r.du_dz = (float)inv * 2.f * pz * sqrtf(ri2);
+    if (derivs) r.du_dz = (float)inv * 2.f * pz * __builtin_amdgcn_rsqf(r2);   // (gradients: 1 ulp is ample)
     return r;
 }
 
