@@ -265,9 +265,9 @@ __global__ void __launch_bounds__(kBlock) k_smooth(const SmoothArgs a)
 // sums), increments |w (-t)^m| s <= 2^30.
 
 // Taps K_m(d) = N^(m)(d) / m! = N(d) (-1/sigma)^m He_m(d / sigma) / m!,
-// m < n_moments, |d| <= RS, into kt[m (2 RS + 1) + d + RS] (fp64, then fp32).
+// m < n_moments, |d| <= RS, into kt[m pitch + d + RS] (fp64, then fp32).
 template <int RS>
-__device__ __forceinline__ void moment_taps(const SmoothArgs& a, float* kt, int n_moments)
+__device__ __forceinline__ void moment_taps(const SmoothArgs& a, float* kt, int n_moments, int pitch)
 {
     constexpr int ND = 2 * RS + 1;
     for (int i = threadIdx.x; i < n_moments * ND; i += blockDim.x) {
@@ -282,7 +282,7 @@ __device__ __forceinline__ void moment_taps(const SmoothArgs& a, float* kt, int 
         const double he = m == 0 ? 1.0 : h1;
         double f = 1.0;
         for (int n = 2; n <= m; ++n) f *= n;
-        kt[i] = (float)((double)a.norm * exp(-0.5 * x * x) * he * pow(-1.0 / sig, m) / f);
+        kt[m * pitch + d + RS] = (float)((double)a.norm * exp(-0.5 * x * x) * he * pow(-1.0 / sig, m) / f);
     }
 }
 
@@ -290,12 +290,15 @@ template <bool COS, int RS>
 __global__ void __launch_bounds__(kBlock) k_smooth_mom(const SmoothArgs a)
 {
     constexpr int NP = smooth_mom_shape(RS).points, NM = smooth_mom_shape(RS).moments, NR = NP * NM, ND = 2 * RS + 1;
+    constexpr int NDP = (ND + 3) & ~3;             // tap row pitch: rows start 16-byte aligned
     extern __shared__ __align__(16) unsigned char smem[];
     u64s* hist = reinterpret_cast<u64s*>(smem);   // row (point c, moment m) = c NM + m; bin k0 at k0 + RS
     double* so = reinterpret_cast<double*>(smem + (size_t)NR * a.stride * 8);
     float* sg = reinterpret_cast<float*>(so + NP);
     float* red = sg + NP;
-    float* kt = red + 64;                          // [NM][ND]
+    constexpr int KT_OFF = (NP * 12 + 64 * 4 + 15) & ~15;   // past so, sg and red
+    static_assert(KT_OFF + NM * NDP * 4 <= 2048, "the taps must fit the 2 KiB past the moment rows");
+    float* kt = reinterpret_cast<float*>(reinterpret_cast<unsigned char*>(so) + KT_OFF);   // [NM][NDP], 16-byte aligned
     const int n_act = smooth_active(a);
     const int split = (int)(blockIdx.x % a.n_split);
     const int tile = (int)(blockIdx.x / a.n_split);
@@ -312,7 +315,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_mom(const SmoothArgs a)
         so[c] = off + off;
         sg[c] = (float)(g * g);
     }
-    moment_taps<RS>(a, kt, NM);
+    moment_taps<RS>(a, kt, NM, NDP);
     float wx[NP];
 #pragma unroll
     for (int c = 0; c < NP; ++c) wx[c] = canon(a.rx, min(tx0 + c, a.rx.n - 1));
@@ -388,24 +391,62 @@ __global__ void __launch_bounds__(kBlock) k_smooth_mom(const SmoothArgs a)
         }
     }
     __syncthreads();
+    // Each thread takes V consecutive bins of one scan point and holds, per
+    // moment, their window of V + 2 RS samples and the moment's taps in
+    // registers (16-byte LDS reads; row starts and k0 are multiples of four
+    // floats).  A bin's sum runs over m, then d.  Window samples past the
+    // row's T + 2 RS values reach only bins >= T, which are not written.
     const float inv_sc = 1.0f / s;
-    for (int o = threadIdx.x; o < NP * T; o += kBlock) {
-        const int c = o / T, k = o - c * T;
+    constexpr int V = 4, NW = (V + 2 * RS + 3) / 4;
+    const int nseg = (T + V - 1) / V;
+    const bool vec_out = !a.atomic_out && (T & 3) == 0 && ((uintptr_t)a.out & 15) == 0;
+    for (int o = threadIdx.x; o < NP * nseg; o += kBlock) {
+        const int c = o / nseg, k0 = (o - c * nseg) * V;
         if (tx0 + c >= a.rx.n) continue;
-        float acc = 0.f;
+        float acc[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] = 0.f;
 #pragma unroll
         for (int m = 0; m < NM; ++m) {
-            // F index of bin k - d, d = dd - RS: k + 2 RS - dd
-            const float* f = F + (size_t)(c * NM + m) * 2 * stride + k + 2 * RS;
-            const float* km = kt + m * ND;
+            // bin k0 + v, offset d = dd - RS, reads F at k0 + v + 2 RS - dd
+            const float4* f4 = reinterpret_cast<const float4*>(F + (size_t)(c * NM + m) * 2 * stride + k0);
+            const float4* t4 = reinterpret_cast<const float4*>(kt + m * NDP);
+            float w[4 * NW], t[NDP];
 #pragma unroll
-            for (int dd = 0; dd < ND; ++dd) acc = fmaf(f[-dd], km[dd], acc);
+            for (int q = 0; q < NW; ++q) {
+                const float4 x = f4[q];
+                w[4 * q] = x.x;
+                w[4 * q + 1] = x.y;
+                w[4 * q + 2] = x.z;
+                w[4 * q + 3] = x.w;
+            }
+#pragma unroll
+            for (int q = 0; q < NDP / 4; ++q) {
+                const float4 x = t4[q];
+                t[4 * q] = x.x;
+                t[4 * q + 1] = x.y;
+                t[4 * q + 2] = x.z;
+                t[4 * q + 3] = x.w;
+            }
+#pragma unroll
+            for (int dd = 0; dd < ND; ++dd) {
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[v] = fmaf(w[v + 2 * RS - dd], t[dd], acc[v]);
+            }
         }
-        float* dst = a.out + ((size_t)(tx0 + c) * a.ry.n + ty0) * (size_t)T + k;
-        if (a.atomic_out)
-            unsafeAtomicAdd(dst, acc * inv_sc);
-        else
-            *dst = acc * inv_sc;
+        float* dst = a.out + ((size_t)(tx0 + c) * a.ry.n + ty0) * (size_t)T + k0;
+        if (vec_out && k0 + V <= T) {
+            *reinterpret_cast<float4*>(dst) = make_float4(acc[0] * inv_sc, acc[1] * inv_sc, acc[2] * inv_sc, acc[3] * inv_sc);
+            continue;
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            if (k0 + v >= T) break;
+            if (a.atomic_out)
+                unsafeAtomicAdd(dst + v, acc[v] * inv_sc);
+            else
+                dst[v] = acc[v] * inv_sc;
+        }
     }
 }
 
@@ -560,7 +601,7 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(const SmoothArgs a)
 template <int RS>
 __global__ void __launch_bounds__(256) k_adj_taps(const SmoothArgs a)
 {
-    moment_taps<RS>(a, a.mtaps, adj_moments(RS));
+    moment_taps<RS>(a, a.mtaps, adj_moments(RS), 2 * RS + 1);
 }
 
 // Correlation rows.  A thread produces V = 4 consecutive bins j0 .. j0 + 3
@@ -934,6 +975,8 @@ hipError_t launch_smooth_moments(const SmoothArgs& a, int64_t n_blocks, size_t l
     const SmoothMomShape sh = smooth_mom_shape(a.Rs);
     if ((int64_t)sh.points * sh.moments * (a.T + 2 * a.Rs) > 24 * (int64_t)kBlock) return hipErrorInvalidValue;
     if (a.stride < a.T + 2 * a.Rs) return hipErrorInvalidValue;
+    // moment rows, then 2 KiB for the scan points' offsets, the reduction and the taps
+    if (lds < (size_t)sh.points * sh.moments * a.stride * 8 + 2048) return hipErrorInvalidValue;
     if (a.Rs == 12) return launch_smooth_mom_rs<12>(a, n_blocks, lds, st);
     if (a.Rs == 16) return launch_smooth_mom_rs<16>(a, n_blocks, lds, st);
     if (a.Rs == 20) return launch_smooth_mom_rs<20>(a, n_blocks, lds, st);
