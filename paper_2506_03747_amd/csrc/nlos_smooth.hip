@@ -69,15 +69,16 @@ __device__ __forceinline__ PairS pair_smooth(float4 A, float4 B, float wx, float
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, pz * pz));
     const float ri2 = __builtin_amdgcn_rcpf(r2);   // weights only: 1 ulp is ample
     const float ri4 = ri2 * ri2;
-    // fp64 arrival from the same fp32 coordinates: ((r + r) + o) * inv, with
-    // r from an fp32 square root and one Newton step in fp64 (relative error
-    // ~1e-15, far below what the Gaussian samples can see; r^2 > 0 since pz > 0)
+    // fp64 arrival from the same fp32 coordinates: (2 r + o) * inv, with
+    // 2 r = 2 rf + (r^2 - rf^2) / rf, rf an fp32 square root: one Newton step,
+    // the residual exact in fp64 (relative error ~1e-14, far below what the
+    // Gaussian samples can see; r^2 > 0 since pz > 0)
     const double ex = (double)A.x - (double)wx, ey = (double)A.y - (double)wy, ez = (double)pz;
     const double r2d = (ex * ex + ey * ey) + ez * ez;
     const float rf = __builtin_amdgcn_sqrtf((float)r2d);
     const double rfd = (double)rf;
-    const double rd = rfd + (double)((float)fma(-rfd, rfd, r2d) * (0.5f * __builtin_amdgcn_rcpf(rf)));
-    r.u = ((rd + rd) + o) * inv;
+    const double rr = fma((double)__builtin_amdgcn_rcpf(rf), fma(-rfd, rfd, r2d), rfd + rfd);
+    r.u = (rr + o) * inv;
     if (cosines) {
         // w = a gg pz^2 c^2 / r^8, c = -n.(p - w) clamped at 0
         const float c = fmaxf(-(B.x * dx + B.y * dy + B.z * pz), 0.f);
@@ -339,6 +340,13 @@ __global__ void __launch_bounds__(kBlock) k_smooth_mom(const SmoothArgs a)
     float W = 0.f;
     for (int w = 0; w < kBlock / 64; ++w) W = fmaxf(W, red[w]);
     const float s = W > 0.f ? 1073741824.0f / W : 1.0f;   // |increments| <= 2^30
+    double soc[NP];
+    float sgc[NP];
+#pragma unroll
+    for (int c = 0; c < NP; ++c) {
+        soc[c] = so[c];
+        sgc[c] = sg[c];
+    }
 
     for (int base = pb; base < pe; base += kBlock) {
         const int p = base + (int)threadIdx.x;
@@ -348,17 +356,20 @@ __global__ void __launch_bounds__(kBlock) k_smooth_mom(const SmoothArgs a)
 #pragma unroll
         for (int c = 0; c < NP; ++c) {
             if (tx0 + c >= a.rx.n) continue;
-            const PairS q = pair_smooth(A, B, wx[c], wy, so[c], sg[c], a.inv, COS, false);
+            const PairS q = pair_smooth(A, B, wx[c], wy, soc[c], sgc[c], a.inv, COS, false);
             const double k0d = floor(q.u);
-            if (q.w <= 0.f || k0d + RS < 0.0 || k0d - RS > (double)(T - 1)) continue;
-            const int k0 = (int)k0d;
+            const int k0 = (int)k0d;   // u >= 0; a saturated conversion fails the test below
+            // the support [k0 - RS, k0 + RS] meets the bins [0, T)
+            if (q.w <= 0.f || (uint32_t)k0 + (uint32_t)RS > (uint32_t)(T - 1 + 2 * RS)) continue;
             const float mt = 0.5f - (float)(q.u - k0d);   // -t
             float v = q.w * s;
             u64s* r0 = hist + (size_t)(c * NM) * stride + (k0 + RS);
 #pragma unroll
             for (int m = 0; m < NM; ++m) {
-                const long long iv = (long long)__float2int_rn(v);
-                __hip_atomic_fetch_add(r0 + (size_t)m * stride, (u64s)iv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                // even moments are non-negative (w > 0, (-t)^m >= 0): no sign extension
+                const int iv = __float2int_rn(v);
+                const u64s inc = (m & 1) ? (u64s)(long long)iv : (u64s)(uint32_t)iv;
+                __hip_atomic_fetch_add(r0 + (size_t)m * stride, inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 v *= mt;
             }
         }
@@ -758,9 +769,10 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_mom(const SmoothArgs a)
                 if (!live[i]) continue;
                 const PairS q = pair_smooth(A[i], B[i], swx[jj], swy[jj], so[jj], sg[jj], a.inv, COS, true);
                 const double k0d = floor(q.u);
-                if (k0d + RS < 0.0 || k0d - RS > (double)(T - 1)) continue;
+                const int k0 = (int)k0d;   // u >= 0; a saturated conversion fails the test below
+                if ((uint32_t)k0 + (uint32_t)RS > (uint32_t)(T - 1 + 2 * RS)) continue;
                 const float mt = 0.5f - (float)(q.u - k0d);   // -t
-                const float* c = rowbuf + (size_t)jj * NM * L + ((int)k0d + RS);
+                const float* c = rowbuf + (size_t)jj * NM * L + (k0 + RS);
                 float G0 = c[MT * L], G1 = (float)(MT + 1) * c[(MT + 1) * L];
 #pragma unroll
                 for (int m = MT - 1; m >= 0; --m) {
