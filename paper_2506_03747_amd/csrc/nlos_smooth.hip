@@ -51,6 +51,20 @@ __device__ __forceinline__ int smooth_active(const SmoothArgs& a)
     return n;
 }
 
+// A wave-uniform value, kept in scalar registers.
+__device__ __forceinline__ float uniform_f(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+__device__ __forceinline__ double uniform_d(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)b);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Weight, arrival and their patch derivatives of one confocal pair.
 struct PairS {
     float w;        // weight
@@ -764,10 +778,13 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_mom(const SmoothArgs a)
         }
         __syncthreads();
         for (int jj = 0; jj < nr; ++jj) {
+            // the scan point's constants, read once for the patches below
+            const float wxj = uniform_f(swx[jj]), wyj = uniform_f(swy[jj]), gj = uniform_f(sg[jj]);
+            const double oj = uniform_d(so[jj]);
 #pragma unroll
             for (int i = 0; i < PPT; ++i) {
                 if (!live[i]) continue;
-                const PairS q = pair_smooth(A[i], B[i], swx[jj], swy[jj], so[jj], sg[jj], a.inv, COS, true);
+                const PairS q = pair_smooth(A[i], B[i], wxj, wyj, oj, gj, a.inv, COS, true);
                 const double k0d = floor(q.u);
                 const int k0 = (int)k0d;   // u >= 0; a saturated conversion fails the test below
                 if ((uint32_t)k0 + (uint32_t)RS > (uint32_t)(T - 1 + 2 * RS)) continue;
@@ -786,8 +803,8 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_mom(const SmoothArgs a)
                 ga[i] += (double)(G0 * q.w_a);
                 if (COS) {
                     const float gn = G0 * q.dwn;
-                    gnx[i] += (double)(gn * (A[i].x - swx[jj]));
-                    gny[i] += (double)(gn * (A[i].y - swy[jj]));
+                    gnx[i] += (double)(gn * (A[i].x - wxj));
+                    gny[i] += (double)(gn * (A[i].y - wyj));
                     gnz[i] += (double)(gn * A[i].z);
                 }
             }
