@@ -572,9 +572,13 @@ int smooth_plan(const nlos_params* p, int32_t n_patches, int rs, SmoothPlan* sp,
     sp->moments = 0;
     sp->stride = T;
     if (nlos::smooth_moments_radius(rs)) {
-        const int stride = (T + 2 * rs + 1) & ~1;
+        int stride = (T + 2 * rs + 1) & ~1;
         const nlos::SmoothMomShape sh = nlos::smooth_mom_shape(rs);
         const int64_t rows = (int64_t)sh.points * sh.moments;
+        // rows that take more than half the LDS leave one workgroup per CU:
+        // then the compile-time pitch, which costs no occupancy
+        if ((size_t)rows * stride * 8 + 2048 > kLdsMax / 2 && stride <= nlos::smooth_mom_pitch(rs))
+            stride = nlos::smooth_mom_pitch(rs);
         const size_t lds = (size_t)rows * stride * 8 + 2048;
         if (lds <= kLdsMax && rows * (T + 2 * rs) <= 24 * (int64_t)nlos::kBlock) {
             sp->moments = 1;

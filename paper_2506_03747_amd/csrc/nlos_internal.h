@@ -352,6 +352,14 @@ struct SmoothMomShape {
     int points, moments;
 };
 constexpr SmoothMomShape smooth_mom_shape(int rs) { return rs == 12 ? SmoothMomShape{2, 8} : SmoothMomShape{3, 6}; }
+// The rows' pitch (u64 bins) used whenever the rows take more than half the
+// LDS (one workgroup per CU either way): the largest even pitch whose rows
+// and 2 KiB of constants fit in 160 KiB, known at compile time so that the
+// rows' offsets go into the LDS instructions' immediate field.
+constexpr int smooth_mom_pitch(int rs)
+{
+    return ((163840 - 2048) / (smooth_mom_shape(rs).points * smooth_mom_shape(rs).moments * 8)) & ~1;
+}
 bool smooth_moments_radius(int rs);
 hipError_t launch_smooth_moments(const SmoothArgs& a, int64_t n_blocks, size_t lds, hipStream_t st);
 // Adjoint by moments (the same radii): adj_moments correlation rows per scan

@@ -301,14 +301,16 @@ __device__ __forceinline__ void moment_taps(const SmoothArgs& a, float* kt, int 
     }
 }
 
-template <bool COS, int RS>
+template <bool COS, int RS, bool PITCH>
 __global__ void __launch_bounds__(kBlock) k_smooth_mom(const SmoothArgs a)
 {
     constexpr int NP = smooth_mom_shape(RS).points, NM = smooth_mom_shape(RS).moments, NR = NP * NM, ND = 2 * RS + 1;
     constexpr int NDP = (ND + 3) & ~3;             // tap row pitch: rows start 16-byte aligned
     extern __shared__ __align__(16) unsigned char smem[];
     u64s* hist = reinterpret_cast<u64s*>(smem);   // row (point c, moment m) = c NM + m; bin k0 at k0 + RS
-    double* so = reinterpret_cast<double*>(smem + (size_t)NR * a.stride * 8);
+    // (PITCH: the rows at the compile-time pitch, which the host passes as the stride)
+    const int stride = PITCH ? smooth_mom_pitch(RS) : a.stride;
+    double* so = reinterpret_cast<double*>(smem + (size_t)NR * stride * 8);
     float* sg = reinterpret_cast<float*>(so + NP);
     float* red = sg + NP;
     constexpr int KT_OFF = (NP * 12 + 64 * 4 + 15) & ~15;   // past so, sg and red
@@ -320,7 +322,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_mom(const SmoothArgs a)
     const int tx0 = (tile / a.tiles_y) * NP, ty0 = tile % a.tiles_y;
     const int chunk = (n_act + a.n_split - 1) / a.n_split;
     const int pb = min(n_act, split * chunk), pe = min(n_act, pb + chunk);
-    const int T = a.T, stride = a.stride;
+    const int T = a.T;
 
     for (int i = threadIdx.x; i < NR * stride; i += kBlock) hist[i] = 0ull;
     if (threadIdx.x < NP) {
@@ -983,17 +985,24 @@ hipError_t launch_smooth(const SmoothArgs& a, int tx, int ty, int64_t n_blocks, 
 
 bool smooth_moments_radius(int rs) { return rs == 12 || rs == 16 || rs == 20; }
 
-template <int RS>
-static hipError_t launch_smooth_mom_rs(const SmoothArgs& a, int64_t n_blocks, size_t lds, hipStream_t st)
+template <int RS, bool PITCH>
+static hipError_t launch_smooth_mom_pitch(const SmoothArgs& a, int64_t n_blocks, size_t lds, hipStream_t st)
 {
-    const void* k = a.cosines ? (const void*)k_smooth_mom<true, RS> : (const void*)k_smooth_mom<false, RS>;
+    const void* k = a.cosines ? (const void*)k_smooth_mom<true, RS, PITCH> : (const void*)k_smooth_mom<false, RS, PITCH>;
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (a.cosines)
-        hipLaunchKernelGGL((k_smooth_mom<true, RS>), dim3((unsigned)n_blocks), dim3(kBlock), lds, st, a);
+        hipLaunchKernelGGL((k_smooth_mom<true, RS, PITCH>), dim3((unsigned)n_blocks), dim3(kBlock), lds, st, a);
     else
-        hipLaunchKernelGGL((k_smooth_mom<false, RS>), dim3((unsigned)n_blocks), dim3(kBlock), lds, st, a);
+        hipLaunchKernelGGL((k_smooth_mom<false, RS, PITCH>), dim3((unsigned)n_blocks), dim3(kBlock), lds, st, a);
     return hipGetLastError();
+}
+
+template <int RS>
+static hipError_t launch_smooth_mom_rs(const SmoothArgs& a, int64_t n_blocks, size_t lds, hipStream_t st)
+{
+    return a.stride == smooth_mom_pitch(RS) ? launch_smooth_mom_pitch<RS, true>(a, n_blocks, lds, st)
+                                            : launch_smooth_mom_pitch<RS, false>(a, n_blocks, lds, st);
 }
 
 hipError_t launch_smooth_moments(const SmoothArgs& a, int64_t n_blocks, size_t lds, hipStream_t st)
