@@ -829,36 +829,30 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_mom(const SmoothArgs a)
 // {0, 0, dL/dpz, dL/da, dL/dn_x, dL/dn_y, dL/dn_z, 0}; zeros past n_active.
 __global__ void __launch_bounds__(256) k_adjoint_reduce(const SmoothArgs a, float* grad_rec)
 {
+    // one thread per output word of a record: words 2 .. 6 sum their field's
+    // partials over the splits in split order (32 splits' values read before
+    // any is added, so that their latencies overlap), words 0, 1 and 7 are 0
     const int n_act = smooth_active(a);
-    const int p = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t p = t >> 3;
+    const int k = (int)(t & 7) - 2;
     if (p >= a.n_cap) return;
-    double g[kAdjStride] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (p < n_act) {
-        // eight splits' partials read before any is added (their latencies
-        // overlap), then added in split order, as one at a time would
-        constexpr int kB = 8;
+    double g = 0.0;
+    if (p < n_act && k >= 0 && k < kAdjStride) {
+        constexpr int kB = 32;
         const size_t step = (size_t)a.n_cap * kAdjStride;
-        const double* q = a.partial + (size_t)p * kAdjStride;
+        const double* q = a.partial + (size_t)p * kAdjStride + k;
         int sp = 0;
         for (; sp + kB <= a.n_split; sp += kB) {
-            double v[kB][kAdjStride];
+            double v[kB];
 #pragma unroll
-            for (int i = 0; i < kB; ++i)
+            for (int i = 0; i < kB; ++i) v[i] = q[(size_t)(sp + i) * step];
 #pragma unroll
-                for (int k = 0; k < kAdjStride; ++k) v[i][k] = q[(size_t)(sp + i) * step + k];
-#pragma unroll
-            for (int i = 0; i < kB; ++i)
-#pragma unroll
-                for (int k = 0; k < kAdjStride; ++k) g[k] += v[i][k];
+            for (int i = 0; i < kB; ++i) g += v[i];
         }
-        for (; sp < a.n_split; ++sp) {
-#pragma unroll
-            for (int k = 0; k < kAdjStride; ++k) g[k] += q[(size_t)sp * step + k];
-        }
+        for (; sp < a.n_split; ++sp) g += q[(size_t)sp * step];
     }
-    float4* o = reinterpret_cast<float4*>(grad_rec + (size_t)p * 8);
-    o[0] = make_float4(0.f, 0.f, (float)g[0], (float)g[1]);
-    o[1] = make_float4((float)g[2], (float)g[3], (float)g[4], 0.f);
+    grad_rec[t] = (float)g;
 }
 
 // ---------------------------------------------------------------------------
@@ -1088,7 +1082,9 @@ hipError_t launch_adjoint_moments(const SmoothArgs& a, int64_t patch_blocks, siz
 hipError_t launch_adjoint_reduce(const SmoothArgs& a, float* grad_rec, hipStream_t st)
 {
     if (a.n_cap <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_adjoint_reduce, dim3((unsigned)((a.n_cap + 255) / 256)), dim3(256), 0, st, a, grad_rec);
+    const int64_t blocks = ((int64_t)a.n_cap * 8 + 255) / 256;   // one thread per output word
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_adjoint_reduce, dim3((unsigned)blocks), dim3(256), 0, st, a, grad_rec);
     return hipGetLastError();
 }
 
