@@ -10,9 +10,11 @@
 // extensions).  Arrivals are computed in fp64: an fp32 distance puts u off by
 // ~1e-4 bins at u ~ 1000, which would move the Gaussian samples by ~1e-5.
 //
-// k_smooth_mom   forward for support radii 12, 16, 20: eight moments of the
-//                sub-bin offset per pair into LDS rows, then a convolution of
-//                each moment row with the matching Gaussian-derivative kernel.
+// k_smooth_mom   forward for support radii 12, 16, 20: eight (radius 12) or
+//                six moments of the sub-bin offset per pair into LDS rows,
+//                then a convolution of each moment row with the matching
+//                Gaussian-derivative kernel, four bins per thread from
+//                registers.
 // k_smooth       forward otherwise: a workgroup owns a tile of scan points
 //                (LDS rows of 64-bit fixed-point bins), a lane one patch;
 //                2 Rs + 1 LDS adds per pair, Gaussian samples by a
@@ -25,7 +27,8 @@
 //                points whose upstream-gradient rows are staged in LDS; per
 //                pair G0 = sum g N(x), G1 = sum g (x / sigma^2) N(x) give
 //                dL/dw = G0 and dL/du = w G1; per-record partial gradients
-//                (fp64) per scan range, summed in a fixed order afterwards.
+//                (fp64) per scan range, summed in a fixed order afterwards
+//                (k_adjoint_reduce, one thread per output word).
 // k_grad_scatter / k_grad_gather   record gradients -> depth and albedo maps
 //                through the central-difference normals and true areas.
 #include <hip/hip_runtime.h>
