@@ -39,7 +39,7 @@ FP32_FMA_CEILING_TFLOPS = 78.6
 TRAFFIC_BYTES = (4297.2 * 2.0 + 16393.8 * 1.0) * 1024
 TRAFFIC_SOURCES = ("paper_2506_03747_amd/csrc/nlos_forward.hip", "paper_2506_03747_amd/csrc/nlos_device.h",
                    "paper_2506_03747_amd/csrc/nlos_internal.h")
-TRAFFIC_HASH = "32f20ec67c56f9f6"
+TRAFFIC_HASH = "db2b6686818997be"
 
 
 def traffic_for_sources():

@@ -648,6 +648,7 @@ size_t adjoint_lds(int rows, int T) { return (((size_t)rows * T * 4 + 15) & ~(si
 // a compiled variant and its rows fit in LDS, else the tap gather.
 struct AdjPlan {
     int moments, rows, split, mlen;
+    int dbuf;          // moment gather: two row buffers, one filled while the other is read
     int64_t pbk;       // patch blocks of the gather
     size_t c_bytes;    // kernel taps (256 bytes per 64 floats), then correlation rows [S][adj_moments][mlen] fp32
     size_t taps_bytes; // the taps' share of c_bytes
@@ -659,6 +660,7 @@ int adjoint_plan(const nlos_params* p, int32_t n_patches, int rs, AdjPlan* ap)
     const int T = p->n_bins;
     const int64_t S = (int64_t)p->relay.nx * p->relay.ny;
     ap->moments = 0;
+    ap->dbuf = 0;
     ap->mlen = 0;
     ap->c_bytes = 0;
     ap->taps_bytes = 0;
@@ -672,6 +674,17 @@ int adjoint_plan(const nlos_params* p, int32_t n_patches, int rs, AdjPlan* ap)
         if (rows >= 1 && lds_pre <= kLdsMax) {
             ap->moments = 1;
             ap->rows = (int)rows;
+            // double-buffered staging when two buffers of at least one scan
+            // point fit and the rows are whole 16-byte pieces
+            ap->dbuf = 0;
+            if ((L & 3) == 0) {
+                int r2 = 5;
+                while (r2 >= 1 && nlos::adj_mom_lds(2, r2, nm, L) > kLdsMax) --r2;
+                if (r2 >= 1) {
+                    ap->dbuf = 1;
+                    ap->rows = r2;
+                }
+            }
             ap->mlen = L;
             const int64_t per_block = (int64_t)nlos::kAdjPatches * nlos::kBlock;
             ap->pbk = ((int64_t)n_patches + per_block - 1) / per_block;
@@ -680,7 +693,7 @@ int adjoint_plan(const nlos_params* p, int32_t n_patches, int rs, AdjPlan* ap)
             ap->split = (int)std::max<int64_t>(1, std::min<int64_t>(sv, std::min<int64_t>(S, 65535)));
             ap->taps_bytes = ((size_t)nm * (2 * rs + 1) * 4 + 255) & ~(size_t)255;
             ap->c_bytes = ap->taps_bytes + (((size_t)S * nm * L * 4 + 255) & ~(size_t)255);
-            ap->lds = (((size_t)rows * nm * L * 4 + 15) & ~(size_t)15) + (size_t)rows * 24;
+            ap->lds = nlos::adj_mom_lds(ap->dbuf ? 2 : 1, ap->rows, nm, L);
             return NLOS_OK;
         }
     }
@@ -1473,7 +1486,7 @@ int nlos_adjoint(const nlos_params* p, const float* patches, int32_t n_patches, 
     a.n_split = ap.split;
     a.rows = ap.rows;
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = ap.moments ? nlos::launch_adjoint_moments(a, ap.pbk, ap.lds, st)
+    hipError_t e = ap.moments ? nlos::launch_adjoint_moments(a, ap.pbk, ap.lds, ap.dbuf, st)
                               : nlos::launch_adjoint(a, ap.pbk, ap.lds, st);
     if (e != hipSuccess) return hip_fail(e);
     e = nlos::launch_adjoint_reduce(a, grad_patches, st);

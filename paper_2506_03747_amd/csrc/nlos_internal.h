@@ -369,7 +369,14 @@ hipError_t launch_smooth_moments(const SmoothArgs& a, int64_t n_blocks, size_t l
 // 16 and 20 (sigma > 2.5 bins).
 constexpr int adj_moments(int rs) { return rs == 12 ? 9 : 7; }
 constexpr int kAdjPatches = 4;
-hipError_t launch_adjoint_moments(const SmoothArgs& a, int64_t patch_blocks, size_t lds, hipStream_t st);
+// LDS of the moment gather: `buffers` copies (2: the next scan points' rows
+// land while the current ones are used) of `rows` scan points' correlation
+// rows, rounded to 16 bytes, and 24 bytes of constants per point.
+inline size_t adj_mom_lds(int buffers, int rows, int nm, int L)
+{
+    return (size_t)buffers * ((((size_t)rows * nm * L * 4 + 15) & ~(size_t)15) + (size_t)rows * 24);
+}
+hipError_t launch_adjoint_moments(const SmoothArgs& a, int64_t patch_blocks, size_t lds, int dbuf, hipStream_t st);
 hipError_t launch_adjoint(const SmoothArgs& a, int64_t patch_blocks, size_t lds, hipStream_t st);
 hipError_t launch_adjoint_reduce(const SmoothArgs& a, float* grad_rec, hipStream_t st);
 hipError_t launch_grad_maps(const GradMapArgs& g, hipStream_t st);

@@ -714,17 +714,19 @@ __global__ void __launch_bounds__(256) k_adj_moments(const SmoothArgs a)
     }
 }
 
-template <bool COS, int RS>
+template <bool COS, int RS, bool DB>
 __global__ void __launch_bounds__(kBlock) k_adjoint_mom(const SmoothArgs a)
 {
-    constexpr int NM = adj_moments(RS), MT = NM - 2, PPT = kAdjPatches;
+    constexpr int NM = adj_moments(RS), MT = NM - 2, PPT = kAdjPatches, NB = DB ? 2 : 1;
     extern __shared__ __align__(16) unsigned char smem[];
     const int T = a.T, L = a.mlen, NR = a.rows;
-    float* rowbuf = reinterpret_cast<float*>(smem);                        // [NR][NM][L]
-    double* so = reinterpret_cast<double*>(smem + (((size_t)NR * NM * L * 4 + 15) & ~(size_t)15));
-    float* swx = reinterpret_cast<float*>(so + NR);
-    float* swy = swx + NR;
-    float* sg = swy + NR;
+    // NB buffers of NR scan points' rows [NR][NM][L], then per buffer the
+    // points' offsets (fp64), positions and gains
+    const size_t buf_bytes = ((size_t)NR * NM * L * 4 + 15) & ~(size_t)15;
+    double* so = reinterpret_cast<double*>(smem + NB * buf_bytes);
+    float* swx = reinterpret_cast<float*>(so + NB * NR);
+    float* swy = swx + NB * NR;
+    float* sg = swy + NB * NR;
     const int n_act = smooth_active(a);
     const int split = (int)blockIdx.y;
     const int S = a.rx.n * a.ry.n;
@@ -745,47 +747,91 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_mom(const SmoothArgs a)
         }
         gz[i] = ga[i] = gnx[i] = gny[i] = gnz[i] = 0.0;
     }
-    for (int j0 = s0; j0 < s1; j0 += NR) {
-        const int nr = min(NR, s1 - j0);
-        __syncthreads();
-        // stage the correlation rows of scan points [j0, j0 + nr): contiguous
-        const float* src = a.moments + (size_t)j0 * NM * L;
-        if ((L & 3) == 0) {
-            // four loads in flight per thread before their LDS stores (a load
-            // past the end rereads the last element; its store is skipped)
-            const float4* s4 = reinterpret_cast<const float4*>(src);
-            float4* d4 = reinterpret_cast<float4*>(rowbuf);
-            const int n4 = nr * NM * (L >> 2);
-            for (int i0 = threadIdx.x; i0 < n4; i0 += 4 * kBlock) {
-                const int last = n4 - 1;
-                const float4 v0 = s4[min(i0, last)];
-                const float4 v1 = s4[min(i0 + kBlock, last)];
-                const float4 v2 = s4[min(i0 + 2 * kBlock, last)];
-                const float4 v3 = s4[min(i0 + 3 * kBlock, last)];
-                __builtin_amdgcn_sched_barrier(0);
-                d4[i0] = v0;
-                if (i0 + kBlock < n4) d4[i0 + kBlock] = v1;
-                if (i0 + 2 * kBlock < n4) d4[i0 + 2 * kBlock] = v2;
-                if (i0 + 3 * kBlock < n4) d4[i0 + 3 * kBlock] = v3;
-            }
-        } else {
-            for (int i = threadIdx.x; i < nr * NM * L; i += kBlock) rowbuf[i] = src[i];
-        }
-        if (threadIdx.x < nr) {
-            const int h = j0 + threadIdx.x;
+    // the constants of scan points [j, j + nr) into buffer b
+    auto stage_consts = [&](int b, int j, int nr) {
+        if ((int)threadIdx.x < nr) {
+            const int h = j + (int)threadIdx.x;
             const float wx = canon(a.rx, h / a.ry.n), wy = canon(a.ry, h % a.ry.n);
             double off, g;
             device_leg(wx, wy, a.cx, a.cy, a.s, &off, &g);
-            so[threadIdx.x] = off + off;
-            swx[threadIdx.x] = wx;
-            swy[threadIdx.x] = wy;
-            sg[threadIdx.x] = (float)(g * g);
+            so[b * NR + threadIdx.x] = off + off;
+            swx[b * NR + threadIdx.x] = wx;
+            swy[b * NR + threadIdx.x] = wy;
+            sg[b * NR + threadIdx.x] = (float)(g * g);
         }
-        __syncthreads();
+    };
+    // DB: the rows of scan points [j, j + nr) into buffer b by global->LDS
+    // loads, 16 bytes per lane at the wavefront's LDS base + 16 lane; they
+    // land while the other buffer is in use.  Wavefront w moves the pieces of
+    // 64 float4 numbered w, w + 16, ... (L is a multiple of 4: whole pieces
+    // of the contiguous rows, the last one masked past the end)
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = (int)threadIdx.x & 63;
+    auto stage_rows_db = [&](int b, int j, int nr) {
+        const float4* s4 = reinterpret_cast<const float4*>(a.moments + (size_t)j * NM * L);
+        float* dst = reinterpret_cast<float*>(smem + b * buf_bytes);
+        const int n4 = nr * NM * (L >> 2);
+        for (int pc = wave; pc * 64 < n4; pc += kBlock / 64) {
+            const int i = pc * 64 + lane;
+            if (i < n4)
+                __builtin_amdgcn_global_load_lds((const void*)(s4 + i),
+                                                 (__attribute__((address_space(3))) void*)(dst + (size_t)pc * 256), 16,
+                                                 0, 0);
+        }
+    };
+    const int nst = s1 > s0 ? (s1 - s0 + NR - 1) / NR : 0;
+    if (DB && nst > 0) {
+        stage_rows_db(0, s0, min(NR, s1 - s0));
+        stage_consts(0, s0, min(NR, s1 - s0));
+    }
+    for (int st = 0; st < nst; ++st) {
+        const int j0 = s0 + st * NR;
+        const int nr = min(NR, s1 - j0);
+        const int b = DB ? (st & 1) : 0;
+        if (DB) {
+            // this wavefront's loads into buffer b have landed; past the
+            // barrier every wavefront's have, and buffer b ^ 1 (the stage
+            // before) is no longer read: the next stage goes there
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (st + 1 < nst) {
+                stage_rows_db(b ^ 1, j0 + NR, min(NR, s1 - j0 - NR));
+                stage_consts(b ^ 1, j0 + NR, min(NR, s1 - j0 - NR));
+            }
+        } else {
+            __syncthreads();
+            // stage the correlation rows of scan points [j0, j0 + nr): contiguous
+            float* rowbuf = reinterpret_cast<float*>(smem);
+            const float* src = a.moments + (size_t)j0 * NM * L;
+            if ((L & 3) == 0) {
+                // four loads in flight per thread before their LDS stores (a load
+                // past the end rereads the last element; its store is skipped)
+                const float4* s4 = reinterpret_cast<const float4*>(src);
+                float4* d4 = reinterpret_cast<float4*>(rowbuf);
+                const int n4 = nr * NM * (L >> 2);
+                for (int i0 = threadIdx.x; i0 < n4; i0 += 4 * kBlock) {
+                    const int last = n4 - 1;
+                    const float4 v0 = s4[min(i0, last)];
+                    const float4 v1 = s4[min(i0 + kBlock, last)];
+                    const float4 v2 = s4[min(i0 + 2 * kBlock, last)];
+                    const float4 v3 = s4[min(i0 + 3 * kBlock, last)];
+                    __builtin_amdgcn_sched_barrier(0);
+                    d4[i0] = v0;
+                    if (i0 + kBlock < n4) d4[i0 + kBlock] = v1;
+                    if (i0 + 2 * kBlock < n4) d4[i0 + 2 * kBlock] = v2;
+                    if (i0 + 3 * kBlock < n4) d4[i0 + 3 * kBlock] = v3;
+                }
+            } else {
+                for (int i = threadIdx.x; i < nr * NM * L; i += kBlock) rowbuf[i] = src[i];
+            }
+            stage_consts(0, j0, nr);
+            __syncthreads();
+        }
+        const float* rowbuf = reinterpret_cast<const float*>(smem + b * buf_bytes);
         for (int jj = 0; jj < nr; ++jj) {
             // the scan point's constants, read once for the patches below
-            const float wxj = uniform_f(swx[jj]), wyj = uniform_f(swy[jj]), gj = uniform_f(sg[jj]);
-            const double oj = uniform_d(so[jj]);
+            const float wxj = uniform_f(swx[b * NR + jj]), wyj = uniform_f(swy[b * NR + jj]),
+                        gj = uniform_f(sg[b * NR + jj]);
+            const double oj = uniform_d(so[b * NR + jj]);
 #pragma unroll
             for (int i = 0; i < PPT; ++i) {
                 if (!live[i]) continue;
@@ -1044,8 +1090,21 @@ hipError_t launch_adjoint(const SmoothArgs& a, int64_t patch_blocks, size_t lds,
     return hipSuccess;
 }
 
+template <int RS, bool DB>
+static hipError_t launch_adjoint_gather(const SmoothArgs& a, const dim3& grid, size_t lds, hipStream_t st)
+{
+    const void* k = a.cosines ? (const void*)k_adjoint_mom<true, RS, DB> : (const void*)k_adjoint_mom<false, RS, DB>;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (a.cosines)
+        hipLaunchKernelGGL((k_adjoint_mom<true, RS, DB>), grid, dim3(kBlock), lds, st, a);
+    else
+        hipLaunchKernelGGL((k_adjoint_mom<false, RS, DB>), grid, dim3(kBlock), lds, st, a);
+    return hipGetLastError();
+}
+
 template <int RS>
-static hipError_t launch_adjoint_mom_rs(const SmoothArgs& a, int64_t patch_blocks, size_t lds, hipStream_t st)
+static hipError_t launch_adjoint_mom_rs(const SmoothArgs& a, int64_t patch_blocks, size_t lds, int dbuf, hipStream_t st)
 {
     const int S = a.rx.n * a.ry.n;
     hipLaunchKernelGGL(k_adj_taps<RS>, dim3(1), dim3(256), 0, st, a);
@@ -1061,24 +1120,23 @@ static hipError_t launch_adjoint_mom_rs(const SmoothArgs& a, int64_t patch_block
         hipLaunchKernelGGL((k_adj_moments<RS, false>), dim3(blocks), dim3(256), 0, st, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const void* k = a.cosines ? (const void*)k_adjoint_mom<true, RS> : (const void*)k_adjoint_mom<false, RS>;
-    e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+    // two row buffers when the plan gave the LDS for them and the rows are
+    // whole, aligned 16-byte pieces; else one (the same rows per stage)
+    const bool db = dbuf && (a.mlen & 3) == 0 && ((uintptr_t)a.moments & 15) == 0 &&
+                    lds >= adj_mom_lds(2, a.rows, adj_moments(RS), a.mlen);
     const dim3 grid((unsigned)patch_blocks, (unsigned)a.n_split);
-    if (a.cosines)
-        hipLaunchKernelGGL((k_adjoint_mom<true, RS>), grid, dim3(kBlock), lds, st, a);
-    else
-        hipLaunchKernelGGL((k_adjoint_mom<false, RS>), grid, dim3(kBlock), lds, st, a);
-    return hipGetLastError();
+    if (db) return launch_adjoint_gather<RS, true>(a, grid, lds, st);
+    return launch_adjoint_gather<RS, false>(a, grid, lds, st);
 }
 
-hipError_t launch_adjoint_moments(const SmoothArgs& a, int64_t patch_blocks, size_t lds, hipStream_t st)
+hipError_t launch_adjoint_moments(const SmoothArgs& a, int64_t patch_blocks, size_t lds, int dbuf, hipStream_t st)
 {
     if (patch_blocks <= 0) return hipSuccess;
     if (patch_blocks > 0x7fffffff || a.n_split > 65535 || a.rows < 1 || a.mlen != a.T + 2 * a.Rs) return hipErrorInvalidValue;
-    if (a.Rs == 12) return launch_adjoint_mom_rs<12>(a, patch_blocks, lds, st);
-    if (a.Rs == 16) return launch_adjoint_mom_rs<16>(a, patch_blocks, lds, st);
-    if (a.Rs == 20) return launch_adjoint_mom_rs<20>(a, patch_blocks, lds, st);
+    if (!smooth_moments_radius(a.Rs) || lds < adj_mom_lds(1, a.rows, adj_moments(a.Rs), a.mlen)) return hipErrorInvalidValue;
+    if (a.Rs == 12) return launch_adjoint_mom_rs<12>(a, patch_blocks, lds, dbuf, st);
+    if (a.Rs == 16) return launch_adjoint_mom_rs<16>(a, patch_blocks, lds, dbuf, st);
+    if (a.Rs == 20) return launch_adjoint_mom_rs<20>(a, patch_blocks, lds, dbuf, st);
     return hipErrorInvalidValue;
 }
 
