@@ -150,6 +150,31 @@ def test_cfg5_smooth_and_adjoint_sampled():
     _assert_record_grads(got, want, "cfg5 adjoint")
 
 
+def test_adjoint_staging_partial_and_empty_ranges():
+    """The gather's double-buffered row staging over several stages.  With
+    128x128 patches (4 blocks of 4096) the adjoint splits the 19x17 = 323 scan
+    points into 128 ranges of 3 (T = 1024 at radius 16 leaves room for two
+    buffers of two scan points): most ranges take a stage of two points, then
+    one of a single point, in the other buffer; range 107 holds two points and
+    ranges 108 .. 127 none.  Sampled record gradients against the oracle."""
+    import torch
+    import paper_2506_03747_amd as nl
+    sc = smooth_scene(624, scan=(19, 17), patches=(128, 128), n_bins=1024, bin_ps=8.0, fwhm_ps=50.0)
+    log("adjoint staging: 323 scan points x 16383 records")
+    _, _, _, rec, n = _gpu_records(sc)
+    G = np.random.default_rng(624).standard_normal((sc.n_scan, sc.n_bins)).astype(np.float32)
+    gr = nl.adjoint(nl.params_of(sc), rec, n, torch.from_numpy(G).cuda())
+    torch.cuda.synchronize()
+    k = int(n.item())
+    pick = np.sort(np.random.default_rng(625).choice(k, 512, replace=False))
+    R = rec.cpu().numpy()
+    idx = R[pick, 7].view(np.int32)
+    want = oracle.adjoint_records(sc, G.astype(np.float64), subset=idx.astype(np.int32))
+    got = gr.cpu().numpy()[pick].astype(np.float64)
+    _assert_record_grads(got, want, "adjoint staging")
+    assert not gr[k:].cpu().numpy().any()
+
+
 AUTOGRAD = [
     dict(seed=611, scan=(12, 10), patches=(24, 20), n_bins=320),
     dict(seed=612, scan=(8, 8), patches=(16, 16), cosines=False, standoff_m=0.5),
