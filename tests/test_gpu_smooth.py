@@ -74,6 +74,9 @@ RADII = [
     # T not a multiple of 4: scalar window reads and stores in the adjoint's
     # correlation pass, scalar staging in the gather
     dict(seed=618, bin_ps=8.0, fwhm_ps=50.0, n_bins=517, scan=(3, 2)),
+    # T = 1024: the forward's rows at the compile-time pitch, with the patches
+    # split over 4 workgroups per tile (outputs by float atomics)
+    dict(seed=626, bin_ps=8.0, fwhm_ps=50.0, n_bins=1024, scan=(3, 2), patches=(64, 64)),
 ]
 
 
